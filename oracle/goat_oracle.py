@@ -1,0 +1,326 @@
+"""Plain FP64 CPU oracle for the GOAT hot path (graph matching via optimal
+transport, arXiv 2111.05366).
+
+TEST INFRASTRUCTURE ONLY. Nothing in the product path may import, call or
+execute this module: only the tests, the smoke entry point and the
+benchmark's CPU-baseline leg use it. It shares no code with the HIP library
+(no kernels, headers, helpers, tables or pre/post-processing).
+
+Every function is written for a reader to check against the paper by eye:
+float64 throughout, numpy matmul as the only library primitive for products,
+no blocking, fusion or reordering beyond what the definitions state.
+
+Conventions (readings of points the paper leaves open are marked READING):
+  * f(P) = tr(A^T P B P^T) is the relaxed quadratic-assignment objective
+    (Background, eq. (QAP)/(rQAP)); graph matching minimises -f (eq. (GM)),
+    so GOAT maximises f over the Birkhoff polytope D.
+  * grad f(P) = A P B^T + A^T P B (Alg. 3 step 1; Alg. 1 step 1).
+  * The direction is the maximiser of tr(Q^T grad f) over D computed by
+    entropic OT (Alg. 2 "LOT"; Alg. 3 step 2). Maximisation is done by
+    negating the cost (Methods, "Doubly Stochastic Optimal Transport"), i.e.
+    the Gibbs kernel is exp(+G/eps).
+  * READING (regularisation): eps = eps_rel * max|G| (the paper's lambda
+    is 1/eps; it recommends lambda >= 100 without saying whether the cost is
+    normalised). eps_rel defaults to 0.03.
+  * READING (Sinkhorn stop): the L-infinity row-marginal error of the current
+    plan, measured after a column update (so columns are exact), checked from
+    the second iteration on; rows are updated first.
+  * READING (step): the paper's alpha in P <- alpha P + (1-alpha) Q is
+    1 - t with P <- P + t (Q - P); t maximises the exact quadratic
+    f(P + t(Q-P)) over [0, 1] (Alg. 3 step 3, "as in" seeded FAQ).
+  * READING (FW stop): at fw_max iterations or on an exact stall (t == 0);
+    an optional ||dP||_F / sqrt(n) < fw_tol test is off by default.
+  * READING (final projection): perm = argmax over permutations of
+    <Pi, P_final> by default (proj="P"); proj="GRAD" uses <Pi, grad f(P_final)>
+    as printed in Alg. 3's return line.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+# ---------------------------------------------------------------- objective
+
+def relaxed_objective(A, B, P) -> float:
+    """f(P) = tr(A^T P B P^T) (Background, eq. (QAP) over D = eq. (rQAP))."""
+    A = np.asarray(A, np.float64); B = np.asarray(B, np.float64); P = np.asarray(P, np.float64)
+    return float(np.sum(A * (P @ B @ P.T)))
+
+
+def qap_value(A, B, perm) -> float:
+    """tr(A^T Pi B Pi^T) for the permutation matrix Pi[i, perm[i]] = 1, i.e.
+    sum_ij A_ij B_{perm i, perm j}. Graph matching minimises its negation
+    (eq. (GM))."""
+    A = np.asarray(A, np.float64); B = np.asarray(B, np.float64)
+    perm = np.asarray(perm)
+    return float(np.sum(A * B[np.ix_(perm, perm)]))
+
+
+def edge_disagreements(A, B, perm) -> float:
+    """||A - Pi B Pi^T||_F^2 (Graph Matching Problem, eq. (1))."""
+    A = np.asarray(A, np.float64); B = np.asarray(B, np.float64)
+    perm = np.asarray(perm)
+    D = A - B[np.ix_(perm, perm)]
+    return float(np.sum(D * D))
+
+
+def perm_matrix(perm) -> np.ndarray:
+    n = len(perm)
+    Pi = np.zeros((n, n))
+    Pi[np.arange(n), np.asarray(perm)] = 1.0
+    return Pi
+
+
+# ----------------------------------------------------------------- gradient
+
+def gradient(A, B, P) -> np.ndarray:
+    """grad f(P) = A P B^T + A^T P B (Alg. 3 step 1)."""
+    A = np.asarray(A, np.float64); B = np.asarray(B, np.float64); P = np.asarray(P, np.float64)
+    return A @ P @ B.T + A.T @ P @ B
+
+
+# ----------------------------------------------------------------- Sinkhorn
+
+def _lse_rows(X) -> np.ndarray:
+    """log sum_j exp(X_ij), max-shifted."""
+    m = np.max(X, axis=1)
+    m_safe = np.where(np.isfinite(m), m, 0.0)
+    return m_safe + np.log(np.sum(np.exp(X - m_safe[:, None]), axis=1))
+
+
+@dataclass
+class SinkhornResult:
+    f: np.ndarray
+    g: np.ndarray
+    Q: np.ndarray
+    iters: int          # number of completed column updates
+    err: float          # max_i |sum_j Q_ij - 1| of the returned Q
+    converged: bool
+
+
+def log_sinkhorn_max(G, eps: float, tol: float = 1e-6, max_iter: int = 1000,
+                     g0=None) -> SinkhornResult:
+    """Entropic maximiser of tr(Q^T G) over the Birkhoff polytope
+    (Alg. 2 "LOT" with the cost negated; Sinkhorn distance, eq. (5)).
+
+    The Sinkhorn-Knopp fixed point on K = exp(G/eps) is run in the log
+    domain on dual potentials f (rows) and g (columns):
+        f_i = -eps * log sum_j exp((G_ij + g_j)/eps)     (row scaling)
+        g_j = -eps * log sum_i exp((G_ij + f_i)/eps)     (column scaling)
+    and Q_ij = exp((G_ij + f_i + g_j)/eps), which lies in U(1, 1) = D.
+    Stop rule: see the module READING; iters counts column updates.
+    """
+    G = np.asarray(G, np.float64)
+    n, m = G.shape
+    g = np.zeros(m) if g0 is None else np.asarray(g0, np.float64).copy()
+    f = np.zeros(n)
+    iters = 0
+    converged = False
+    for k in range(max_iter):
+        s = _lse_rows((G + g[None, :]) / eps)
+        if k >= 1:
+            err = float(np.max(np.abs(np.exp(f / eps + s) - 1.0)))
+            if err <= tol:
+                converged = True
+                break
+        f = -eps * s
+        g = -eps * _lse_rows(((G + f[:, None]) / eps).T)
+        iters += 1
+    Q = np.exp((G + f[:, None] + g[None, :]) / eps)
+    err = float(np.max(np.abs(Q.sum(axis=1) - 1.0)))
+    return SinkhornResult(f, g, Q, iters, err, converged)
+
+
+def sinkhorn_knopp(K, tol: float = 1e-12, max_iter: int = 100000) -> np.ndarray:
+    """Plain Sinkhorn-Knopp scaling of a positive matrix to a doubly
+    stochastic one (used to draw the random start K in P0 = (J + K)/2,
+    GOAT section, random initialisations)."""
+    K = np.asarray(K, np.float64)
+    n = K.shape[0]
+    r = np.ones(n)
+    c = np.ones(n)
+    for _ in range(max_iter):
+        r = 1.0 / (K @ c)
+        c = 1.0 / (K.T @ r)
+        X = r[:, None] * K * c[None, :]
+        if np.max(np.abs(X.sum(axis=1) - 1.0)) <= tol:
+            return X
+    return r[:, None] * K * c[None, :]
+
+
+def barycenter(n: int) -> np.ndarray:
+    """J = 1 1^T / n (Alg. 1 and Alg. 3 initialisation)."""
+    return np.full((n, n), 1.0 / n)
+
+
+def random_init(U) -> np.ndarray:
+    """P0 = (J + K)/2 with K the Sinkhorn-Knopp scaling of a positive random
+    matrix U (GOAT section, random initialisations)."""
+    U = np.asarray(U, np.float64)
+    return 0.5 * (barycenter(U.shape[0]) + sinkhorn_knopp(U))
+
+
+# -------------------------------------------------------------- line search
+
+@dataclass
+class LineSearch:
+    fP: float
+    fQ: float
+    c: float
+    a: float
+    b: float
+    t: float
+    dist2: float        # ||Q - P||_F^2
+
+
+def linesearch(P, Q, GP, GQ) -> LineSearch:
+    """Exact step of Alg. 3 step 3 (READING: t = 1 - alpha).
+
+    f is quadratic, so with D = Q - P:
+        f(P + tD) = f(P) + t <D, grad f(P)> + t^2 f(D)
+    and <P, grad f(P)> = 2 f(P), f(D) = f(P) + f(Q) - <Q, grad f(P)>. Hence
+    with fP = <P,GP>/2, fQ = <Q,GQ>/2, c = <Q,GP>:
+        b = c - 2 fP,   a = fP + fQ - c,   f(P + tD) = fP + b t + a t^2.
+    t maximises b t + a t^2 over [0, 1]: the vertex -b/(2a) clipped to
+    [0, 1] when a < 0, else the better endpoint (t = 1 iff a + b > 0)."""
+    P = np.asarray(P, np.float64); Q = np.asarray(Q, np.float64)
+    GP = np.asarray(GP, np.float64); GQ = np.asarray(GQ, np.float64)
+    fP = 0.5 * float(np.sum(P * GP))
+    fQ = 0.5 * float(np.sum(Q * GQ))
+    c = float(np.sum(Q * GP))
+    a = fP + fQ - c
+    b = c - 2.0 * fP
+    if a < 0.0:
+        t = min(max(-b / (2.0 * a), 0.0), 1.0)
+    else:
+        t = 1.0 if a + b > 0.0 else 0.0
+    D = Q - P
+    return LineSearch(fP, fQ, c, a, b, t, float(np.sum(D * D)))
+
+
+# ----------------------------------------------------- linear assignment
+
+def hungarian_max(M) -> np.ndarray:
+    """perm maximising sum_i M[i, perm[i]] (the linear assignment of Alg. 3's
+    return line and Alg. 1 step 2, a Hungarian method).
+
+    Textbook shortest-augmenting-path Hungarian algorithm with row/column
+    dual potentials on the cost C = -M, adding one row at a time; FP64.
+    Among columns of equal reduced distance the lowest index is taken.
+    """
+    C = -np.asarray(M, np.float64)
+    n = C.shape[0]
+    INF = math.inf
+    u = np.zeros(n + 1)           # row potentials (1-based, 0 = virtual)
+    v = np.zeros(n + 1)           # column potentials
+    p = np.zeros(n + 1, dtype=np.int64)    # p[j] = row matched to column j
+    way = np.zeros(n + 1, dtype=np.int64)
+    for i in range(1, n + 1):
+        p[0] = i
+        j0 = 0
+        minv = np.full(n + 1, INF)
+        used = np.zeros(n + 1, dtype=bool)
+        while True:
+            used[j0] = True
+            i0 = p[j0]
+            # reduced costs of row i0 to every free (unused) column
+            cur = C[i0 - 1, :] - u[i0] - v[1:]
+            free = ~used[1:]
+            upd = free & (cur < minv[1:])
+            minv[1:][upd] = cur[upd]
+            way[1:][upd] = j0
+            cand = np.where(free, minv[1:], INF)
+            j1 = int(np.argmin(cand)) + 1     # lowest index among equal minima
+            delta = cand[j1 - 1]
+            used_idx = np.nonzero(used)[0]
+            u[p[used_idx]] += delta
+            v[used_idx] -= delta
+            minv[1:][free] -= delta
+            j0 = j1
+            if p[j0] == 0:
+                break
+        while True:
+            j1 = way[j0]
+            p[j0] = p[j1]
+            j0 = j1
+            if j0 == 0:
+                break
+    perm = np.empty(n, dtype=np.int64)
+    for j in range(1, n + 1):
+        perm[p[j] - 1] = j - 1
+    return perm
+
+
+# ---------------------------------------------------------------- GOAT loop
+
+@dataclass
+class GoatOptions:
+    eps_rel: float = 0.03
+    sk_tol: float = 1e-6
+    sk_max: int = 1000
+    fw_max: int = 30
+    fw_tol: float = 0.0
+    proj: str = "P"           # "P" or "GRAD"
+
+
+@dataclass
+class GoatResult:
+    perm: np.ndarray
+    score: float               # tr(A^T Pi B Pi^T) of the returned perm
+    P: np.ndarray
+    fw_iters: int
+    history: list = field(default_factory=list)
+
+
+def goat(A, B, P0=None, opt: GoatOptions | None = None, record: bool = False) -> GoatResult:
+    """Alg. 3 (GOAT): Frank-Wolfe on the relaxed problem with the LAP
+    direction of FAQ (Alg. 1) replaced by LOT (Alg. 2), then one Hungarian
+    projection. The gradient is recomputed plainly each iteration."""
+    opt = opt or GoatOptions()
+    A = np.asarray(A, np.float64); B = np.asarray(B, np.float64)
+    n = A.shape[0]
+    P = barycenter(n) if P0 is None else np.asarray(P0, np.float64).copy()
+    hist = []
+    it = 0
+    for it in range(1, opt.fw_max + 1):
+        G = gradient(A, B, P)                                   # step 1
+        gmax = float(np.max(np.abs(G)))
+        eps = opt.eps_rel * gmax
+        if eps == 0.0:
+            Q = barycenter(n); sk_it = 0; sk_err = 0.0
+        else:
+            sk = log_sinkhorn_max(G, eps, opt.sk_tol, opt.sk_max)   # step 2
+            Q, sk_it, sk_err = sk.Q, sk.iters, sk.err
+        GQ = gradient(A, B, Q)
+        ls = linesearch(P, Q, G, GQ)                            # step 3
+        P = P + ls.t * (Q - P)                                  # step 4
+        delta = ls.t * math.sqrt(ls.dist2) / math.sqrt(n)
+        if record:
+            hist.append(dict(it=it, eps=eps, sk_iters=sk_it, sk_err=sk_err,
+                             t=ls.t, a=ls.a, b=ls.b, fP=ls.fP, fQ=ls.fQ, c=ls.c,
+                             f_next=ls.fP + ls.b * ls.t + ls.a * ls.t ** 2))
+        if ls.t == 0.0 or (opt.fw_tol > 0.0 and delta < opt.fw_tol):
+            break
+    M = P if opt.proj == "P" else gradient(A, B, P)
+    perm = hungarian_max(M)
+    return GoatResult(perm, qap_value(A, B, perm), P, it, hist)
+
+
+def goat_restarts(A, B, inits, opt: GoatOptions | None = None) -> GoatResult:
+    """Several starts P0 (GOAT section, random initialisations); the
+    permutation with the largest tr(A^T Pi B Pi^T) is kept, ties to the
+    earliest start."""
+    best = None
+    for P0 in inits:
+        r = goat(A, B, P0, opt)
+        if best is None or r.score > best.score:
+            best = r
+    return best
+
+
+def match_ratio(perm, truth) -> float:
+    """Fraction of nodes aligned as planted (Results section)."""
+    return float(np.mean(np.asarray(perm) == np.asarray(truth)))
