@@ -1,0 +1,211 @@
+/*
+ * goat.h - C ABI of libgoat, the MI355X (gfx950) hot path of GOAT
+ * ("Graph Matching via Optimal Transport", arXiv 2111.05366).
+ *
+ * Problem (Background, eqs. (QAP), (rQAP), (GM)): for n x n matrices A, B,
+ * maximise f(P) = tr(A^T P B P^T) - equivalently minimise -tr(A P B^T P^T) -
+ * over the Birkhoff polytope D of doubly stochastic matrices with the
+ * Frank-Wolfe method of Alg. 3 (GOAT), whose direction step is entropic
+ * optimal transport (Alg. 2, LOT), then project to a permutation with one
+ * linear assignment.
+ *
+ * Conventions shared by every call
+ *  - Matrices are row-major float32 n x n with a leading dimension ld >= n
+ *    (in elements); a matrix buffer holds n*ld elements. Unless a call says
+ *    "host", pointers are device pointers (HIP global memory).
+ *  - Vectorised loads need ld % 4 == 0 and 16-byte aligned bases; other
+ *    inputs are first repacked into the workspace (slower, still correct).
+ *  - The caller owns every buffer; the library never frees caller memory.
+ *    Scratch space is a caller-provided device workspace of at least
+ *    goat_workspace_size(n, prec, symmetric) bytes, 256-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    goat_grad, goat_sinkhorn and goat_linesearch are asynchronous on it and
+ *    write scalar results to device memory; goat_solve is host-synchronous.
+ *  - Return value: GOAT_OK (0) or a negative status. GOAT_EINVAL: null
+ *    pointer, n < 1, ld < n, bad option. GOAT_ENOMEM: workspace too small.
+ *    GOAT_EHIP: HIP runtime failure. GOAT_ENOTSUP: unsupported mode. The
+ *    message of the last failure on the calling thread is goat_last_error().
+ *    Non-convergence of an iteration is not an error; it is reported in
+ *    the outputs.
+ */
+#ifndef GOAT_H
+#define GOAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GOAT_OK        0
+#define GOAT_EINVAL   -1
+#define GOAT_EHIP     -2
+#define GOAT_ENOMEM   -3
+#define GOAT_ENOTSUP  -4
+
+/* Arithmetic of the gradient products (all accumulate in float32).
+ *  FP32   : float32 operands on the fp32 matrix cores.
+ *  BF16X2 : A, B rounded to bf16 (exact for 0/1 adjacency), the P-side
+ *           operand split into bf16 hi + lo parts: 2 bf16 products.
+ *  BF16X3 : A, B and the P-side operand all split hi + lo; the lo*lo term
+ *           is dropped: 3 bf16 products (weighted graphs).            */
+#define GOAT_PREC_FP32    0
+#define GOAT_PREC_BF16X2  1
+#define GOAT_PREC_BF16X3  2
+
+/* Sinkhorn starting potentials. */
+#define GOAT_INIT_COLD  0   /* g = 0                                   */
+#define GOAT_INIT_G     1   /* start from the caller's g               */
+
+/* Library version as 10000*major + 100*minor + patch. */
+int goat_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* goat_last_error(void);
+
+/* Bytes of device workspace that every call below needs at size n with
+ * the given precision and symmetry flag. */
+size_t goat_workspace_size(int n, int prec, int symmetric);
+
+/*
+ * goat_grad - gradient of the relaxed objective (Alg. 3 step 1):
+ *     G = A P B^T + A^T P B.
+ * A, B, P: inputs (lda = ldb = ld, ldp), G: output (ldg). With
+ * symmetric != 0 the caller promises A = A^T and B = B^T and the library
+ * evaluates G = 2 A P B (two products instead of four). prec selects the
+ * arithmetic (GOAT_PREC_*). BF16X2 requires A and B exactly representable
+ * in bf16 (e.g. 0/1 adjacency); it is the caller's promise.
+ */
+int goat_grad(int n, const float* A, const float* B, int ld,
+              const float* P, int ldp, float* G, int ldg,
+              int prec, int symmetric,
+              void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * goat_sinkhorn - LOT direction (Alg. 2 with the cost negated, as the
+ * Methods section prescribes for the maximisation in Alg. 3 step 2): the
+ * entropic maximiser of tr(Q^T G) over D,
+ *     Q_ij = exp((G_ij + f_i + g_j) / eps),
+ * found by log-domain Sinkhorn-Knopp scaling (Sinkhorn distance, eq. (5)).
+ * Each iteration sets f from the row sums, then g from the column sums.
+ * Stop: after a column update, the largest row-marginal error
+ * max_i |sum_j Q_ij - 1| of the current plan is <= tol (checked from the
+ * second iteration on), or max_iter column updates have run.
+ *
+ *  G        n x n input (ldg).
+ *  eps_dev  device float: the eps to use; NULL = eps_rel * max|G|
+ *           computed on the device. If the resulting eps is 0, Q = J.
+ *  f, g     device float[n]: final potentials (natural units). With
+ *           init == GOAT_INIT_G, g is read first as the starting point.
+ *  Q        n x n output (ldq), or NULL to skip forming it.
+ *  iters_dev, err_dev, eps_out  device int / float / float outputs (each
+ *           may be NULL): column updates run, max_i |sum_j Q_ij - 1| of the
+ *           returned plan, and the eps used.
+ * The call is asynchronous; convergence is decided on the device.
+ */
+int goat_sinkhorn(int n, const float* G, int ldg,
+                  const float* eps_dev, float eps_rel,
+                  float* f, float* g, int init,
+                  int max_iter, float tol,
+                  float* Q, int ldq,
+                  int* iters_dev, float* err_dev, float* eps_out,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * goat_linesearch - exact step of Alg. 3 step 3. With D = Q - P the
+ * objective is the quadratic f(P + tD) = fP + b t + a t^2 where
+ *     fP = <P,GP>/2, fQ = <Q,GQ>/2, c = <Q,GP>, a = fP + fQ - c, b = c - 2 fP
+ * (GP = grad f(P), GQ = grad f(Q)); t maximises it over [0, 1] (the
+ * paper's alpha is 1 - t). All traces accumulate in float64.
+ * out_dev: device double[8] = {fP, fQ, c, a, b, t, ||Q-P||_F^2, 0}.
+ */
+int goat_linesearch(int n, const float* P, const float* Q,
+                    const float* GP, const float* GQ, int ld,
+                    double* out_dev,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Options of goat_solve; goat_default_options() fills the defaults. */
+typedef struct goat_options {
+    float eps_rel;        /* eps = eps_rel * max|grad f(P)| per FW iteration (0.03) */
+    float sk_tol;         /* Sinkhorn row-marginal tolerance (1e-6)                 */
+    int   sk_max;         /* Sinkhorn iteration cap (1000)                          */
+    int   fw_max;         /* Frank-Wolfe iteration cap (30)                         */
+    float fw_tol;         /* stop when t ||Q-P||_F / sqrt(n) < fw_tol; 0 = off      */
+    int   prec;           /* GOAT_PREC_*                                            */
+    int   symmetric;      /* 1: A = A^T and B = B^T                                 */
+    int   proj;           /* 0: final LAP on P_final; 1: on grad f(P_final)         */
+    int   warm;           /* 0: cold Sinkhorn each iteration; 1: start from the
+                             previous iteration's column potentials                 */
+    int   stop_on_stall;  /* 1: stop when t == 0 (default); 0: run fw_max iterations */
+    int   check_every;    /* Sinkhorn convergence flag polled every k iterations (16) */
+    int   reserved[5];
+} goat_options;
+
+/* Per-iteration record of goat_solve (host memory). */
+typedef struct goat_iter_record {
+    double fP, fQ, c, a, b, t, dist2;  /* line-search scalars of this iteration */
+    float  eps;                        /* eps used by Sinkhorn                  */
+    float  sk_err;                     /* row-marginal error of Q               */
+    int    sk_iters;                   /* Sinkhorn column updates               */
+    int    pad;
+} goat_iter_record;
+
+typedef struct goat_stats {
+    int    fw_iters;       /* Frank-Wolfe iterations run                      */
+    int    sk_iters_total; /* Sinkhorn iterations summed over FW iterations   */
+    int    sk_capped;      /* FW iterations whose Sinkhorn hit sk_max         */
+    int    pad;
+    double f_final;        /* f(P_final) = tr(A^T P B P^T)                    */
+    double score;          /* tr(A^T Pi B Pi^T) of the returned permutation   */
+    double ms_loop;        /* device time of the FW loop (HIP events)         */
+    double ms_lap;         /* host time of the final assignment               */
+    double ms_total;       /* wall time of the call                           */
+} goat_stats;
+
+void goat_default_options(goat_options* opt);
+
+/*
+ * goat_solve - Alg. 3 end to end for one pair: P0 (NULL = barycenter
+ * J = 11^T/n, the initialisation of Alg. 1 and Alg. 3; else an n x n
+ * doubly stochastic device matrix with leading dimension ld), Frank-Wolfe
+ * iterations (gradient, LOT direction, exact step, update), then
+ * perm = argmax over permutations of <Pi, P_final> (or of
+ * <Pi, grad f(P_final)> with opt->proj = 1) by a host linear assignment.
+ *  perm_host  host int32[n]: perm[i] = j matches A-node i to B-node j.
+ *  stats_host host goat_stats (may be NULL).
+ *  hist_host  host goat_iter_record[hist_cap] (may be NULL).
+ *  P_out      device n x n (ld) final relaxed P, or NULL.
+ * Host-synchronous on `stream`.
+ */
+int goat_solve(int n, const float* A, const float* B, int ld,
+               const float* P0, const goat_options* opt,
+               int32_t* perm_host, goat_stats* stats_host,
+               goat_iter_record* hist_host, int hist_cap,
+               float* P_out,
+               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * goat_lap_max - host linear assignment (Alg. 3 return line; Alg. 1 step 2
+ * uses the same problem): perm maximising sum_i M[i*ld + perm[i]] over
+ * permutations, for a host float64 matrix M. Jonker-Volgenant shortest
+ * augmenting paths; ties go to the lower column index. O(n^3) worst case.
+ */
+int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
+
+/*
+ * goat_score - tr(A^T Pi B Pi^T) = sum_ij A_ij B_{perm i, perm j} for a
+ * device int32 permutation (entries outside [0, n) are clamped into range;
+ * the result is meaningful only for a permutation), accumulated in float64
+ * (the (QAP) objective at a permutation; graph matching minimises its
+ * negation, eq. (GM)). out_dev: device double.
+ */
+int goat_score(int n, const float* A, const float* B, int ld,
+               const int32_t* perm_dev, double* out_dev,
+               void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GOAT_H */

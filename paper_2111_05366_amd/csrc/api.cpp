@@ -1,0 +1,451 @@
+// C ABI of libgoat: argument checks, workspace layout, and the host drivers
+// of the gradient, LOT (Sinkhorn) and line-search calls and of the full
+// GOAT Frank-Wolfe loop (Alg. 3).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace goat {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+Layout make_layout(int n, int prec, int sym) {
+    Layout L;
+    L.n = n;
+    L.np = pad_n(n);
+    L.prec = prec;
+    L.sym = sym ? 1 : 0;
+    const size_t np = L.np;
+    const size_t pl = np * np;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
+    // small state first: offsets depend on n only
+    L.ctrl = take(256);
+    L.u = take(np * 4);
+    L.unew = take(np * 4);
+    L.v = take(np * 4);
+    L.errpart = take(kSkWG * 4);
+    L.colpart = take((size_t)kSkWG * np * 4);
+    L.red = take((size_t)kRedWG * 4 * 8);
+    L.scal = take(64 * 8 + np * 4 * 2);   // scalars, then g_prev[np], perm_dev[np]
+    L.fscal = take((16 + kRedWG) * 4);
+    // fp32 solver matrices
+    L.P = take(pl * 4);
+    L.Q = take(pl * 4);
+    L.GP = take(pl * 4);
+    L.GQ = take(pl * 4);
+    // packed operands
+    const int rows = L.sym ? 1 : 2;
+    const size_t op_elt = prec == GOAT_PREC_FP32 ? 4 : 2;
+    const int op_planes = prec == GOAT_PREC_BF16X3 ? 2 : 1;
+    L.opA = take(pl * rows * op_elt * op_planes);
+    L.opB = take(pl * rows * op_elt * op_planes);
+    L.opP = take(prec == GOAT_PREC_FP32 ? pl * 4 : pl * 2 * 2);
+    L.opY = take(prec == GOAT_PREC_FP32 ? pl * rows * 4 : pl * rows * 2 * 2);
+    L.total = o;
+    return L;
+}
+
+static size_t small_bytes(const Layout& L) { return L.P; }
+
+// ---------------------------------------------------------------- gradient
+
+// Symmetric: Y^T = B P^T (= (P B)^T) then G = 2 A Y. General: the stacked
+// [B; B^T] P^T gives (P B^T)^T and (P B)^T, then
+// G = A (P B^T) + A^T (P B) as one product over two k-segments.
+int grad_packed(const Layout& L, const GradOps& o, float* G, int ldg, int m_valid, hipStream_t s) {
+    const int np = L.np;
+    const size_t pl = (size_t)np * np;
+    const int rows = L.sym ? 1 : 2;
+    const bool bf = L.prec != GOAT_PREC_FP32;
+    const size_t es = bf ? 2 : 4;
+    auto off = [&](const void* p, size_t elems) {
+        return static_cast<const void*>(static_cast<const char*>(p) + elems * es);
+    };
+    GemmSegs s1{}, s2{};
+    if (L.prec == GOAT_PREC_FP32) {
+        s1.X[0] = o.B_hi; s1.Z[0] = o.P_hi; s1.nseg = 1;
+    } else if (L.prec == GOAT_PREC_BF16X2) {
+        s1.X[0] = o.B_hi; s1.Z[0] = o.P_hi;
+        s1.X[1] = o.B_hi; s1.Z[1] = o.P_lo; s1.nseg = 2;
+    } else {
+        s1.X[0] = o.B_hi; s1.Z[0] = o.P_hi;
+        s1.X[1] = o.B_hi; s1.Z[1] = o.P_lo;
+        s1.X[2] = o.B_lo; s1.Z[2] = o.P_hi; s1.nseg = 3;
+    }
+    int rc = launch_gemm_nt(bf, rows * np, np, np, np, np, s1, 1.0f, bf ? OUT_BF16_SPLIT : OUT_F32,
+                            static_cast<float*>(o.Y_hi), np, rows * np, np,
+                            static_cast<uint16_t*>(o.Y_hi), static_cast<uint16_t*>(o.Y_lo), np, s);
+    if (rc) return rc;
+    // second product: segments over (A-part, Y-part) for each stacked half
+    int k = 0;
+    for (int h = 0; h < rows; ++h) {
+        const size_t ah = (size_t)h * pl;        // A (h=0) or A^T (h=1)
+        const size_t yh = (size_t)h * pl;        // (P B^T)^T (h=0) or (P B)^T (h=1)
+        if (L.prec == GOAT_PREC_FP32) {
+            s2.X[k] = off(o.A_hi, ah); s2.Z[k] = off(o.Y_hi, yh); ++k;
+        } else if (L.prec == GOAT_PREC_BF16X2) {
+            s2.X[k] = off(o.A_hi, ah); s2.Z[k] = off(o.Y_hi, yh); ++k;
+            s2.X[k] = off(o.A_hi, ah); s2.Z[k] = off(o.Y_lo, yh); ++k;
+        } else {
+            s2.X[k] = off(o.A_hi, ah); s2.Z[k] = off(o.Y_hi, yh); ++k;
+            s2.X[k] = off(o.A_hi, ah); s2.Z[k] = off(o.Y_lo, yh); ++k;
+            s2.X[k] = off(o.A_lo, ah); s2.Z[k] = off(o.Y_hi, yh); ++k;
+        }
+    }
+    s2.nseg = k;
+    return launch_gemm_nt(bf, np, np, np, np, np, s2, L.sym ? 2.0f : 1.0f, OUT_F32, G, ldg, m_valid,
+                          m_valid, nullptr, nullptr, 0, s);
+}
+
+struct Ptrs {
+    char* base;
+    float* P; float* Q; float* GP; float* GQ;
+    void* A_hi; void* A_lo; void* B_hi; void* B_lo;
+    void* P_hi; void* P_lo; void* Y_hi; void* Y_lo;
+    SkState sk;
+    double* red; double* scal; float* fscal; float* g_prev; int32_t* perm_dev;
+};
+
+static Ptrs make_ptrs(const Layout& L, void* ws) {
+    Ptrs p{};
+    char* b = static_cast<char*>(ws);
+    const size_t pl = (size_t)L.np * L.np;
+    const int rows = L.sym ? 1 : 2;
+    p.base = b;
+    p.P = reinterpret_cast<float*>(b + L.P);
+    p.Q = reinterpret_cast<float*>(b + L.Q);
+    p.GP = reinterpret_cast<float*>(b + L.GP);
+    p.GQ = reinterpret_cast<float*>(b + L.GQ);
+    const size_t op_elt = L.prec == GOAT_PREC_FP32 ? 4 : 2;
+    p.A_hi = b + L.opA;
+    p.A_lo = b + L.opA + pl * rows * op_elt;
+    p.B_hi = b + L.opB;
+    p.B_lo = b + L.opB + pl * rows * op_elt;
+    p.P_hi = b + L.opP;
+    p.P_lo = b + L.opP + pl * 2;
+    p.Y_hi = b + L.opY;
+    p.Y_lo = b + L.opY + pl * rows * 2;
+    p.sk.ctrl = reinterpret_cast<SkCtrl*>(b + L.ctrl);
+    p.sk.u = reinterpret_cast<float*>(b + L.u);
+    p.sk.unew = reinterpret_cast<float*>(b + L.unew);
+    p.sk.v = reinterpret_cast<float*>(b + L.v);
+    p.sk.errpart = reinterpret_cast<float*>(b + L.errpart);
+    p.sk.colpart = reinterpret_cast<float*>(b + L.colpart);
+    p.red = reinterpret_cast<double*>(b + L.red);
+    p.scal = reinterpret_cast<double*>(b + L.scal);
+    p.g_prev = reinterpret_cast<float*>(b + L.scal + 64 * 8);
+    p.perm_dev = reinterpret_cast<int32_t*>(b + L.scal + 64 * 8 + (size_t)L.np * 4);
+    p.fscal = reinterpret_cast<float*>(b + L.fscal);
+    return p;
+}
+
+static int pack_graph(const Layout& L, const float* X, int ld, void* hi, void* lo, hipStream_t s) {
+    const int mode = L.prec == GOAT_PREC_FP32 ? PACK_F32 : (L.prec == GOAT_PREC_BF16X2 ? PACK_BF16 : PACK_BF16_SPLIT);
+    const size_t es = L.prec == GOAT_PREC_FP32 ? 4 : 2;
+    const size_t pl = (size_t)L.np * L.np;
+    int rc = launch_pack(X, ld, L.n, L.np, 0, mode, hi, lo, s);
+    if (rc || L.sym) return rc;
+    return launch_pack(X, ld, L.n, L.np, 1, mode, static_cast<char*>(hi) + pl * es,
+                       lo ? static_cast<char*>(lo) + pl * es : nullptr, s);
+}
+
+static GradOps grad_ops(const Ptrs& p) {
+    GradOps o;
+    o.A_hi = p.A_hi; o.A_lo = p.A_lo; o.B_hi = p.B_hi; o.B_lo = p.B_lo;
+    o.P_hi = p.P_hi; o.P_lo = p.P_lo; o.Y_hi = p.Y_hi; o.Y_lo = p.Y_lo;
+    return o;
+}
+
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace goat
+
+using namespace goat;
+
+extern "C" {
+
+int goat_version(void) { return 100; }
+
+const char* goat_last_error(void) { return g_last_error.c_str(); }
+
+size_t goat_workspace_size(int n, int prec, int symmetric) {
+    if (n < 1 || prec < GOAT_PREC_FP32 || prec > GOAT_PREC_BF16X3) return 0;
+    return make_layout(n, prec, symmetric).total;
+}
+
+void goat_default_options(goat_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->eps_rel = 0.03f;
+    opt->sk_tol = 1e-6f;
+    opt->sk_max = 1000;
+    opt->fw_max = 30;
+    opt->fw_tol = 0.0f;
+    opt->prec = GOAT_PREC_FP32;
+    opt->symmetric = 1;
+    opt->proj = 0;
+    opt->warm = 0;
+    opt->stop_on_stall = 1;
+    opt->check_every = 16;
+}
+
+int goat_grad(int n, const float* A, const float* B, int ld, const float* P, int ldp, float* G, int ldg,
+              int prec, int symmetric, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(A && B && P && G && ws, "null pointer");
+    GOAT_CHECK_ARG(ld >= n && ldp >= n && ldg >= n, "leading dimension < n");
+    GOAT_CHECK_ARG(prec >= GOAT_PREC_FP32 && prec <= GOAT_PREC_BF16X3, "unknown precision");
+    const Layout L = make_layout(n, prec, symmetric);
+    if (ws_bytes < L.total) { set_error("goat_grad: workspace too small"); return GOAT_ENOMEM; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ptrs p = make_ptrs(L, ws);
+    int rc = pack_graph(L, A, ld, p.A_hi, p.A_lo, s);
+    if (!rc) rc = pack_graph(L, B, ld, p.B_hi, p.B_lo, s);
+    if (rc) return rc;
+    if (prec == GOAT_PREC_FP32) rc = launch_copy_pad(n, P, ldp, static_cast<float*>(p.P_hi), L.np, L.np, s);
+    else rc = launch_split_bf16(n, L.np, P, ldp, static_cast<uint16_t*>(p.P_hi), static_cast<uint16_t*>(p.P_lo), s);
+    if (rc) return rc;
+    return grad_packed(L, grad_ops(p), G, ldg, n, s);
+}
+
+int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float eps_rel, float* f, float* g,
+                  int init, int max_iter, float tol, float* Q, int ldq, int* iters_dev, float* err_dev,
+                  float* eps_out, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(G && ws, "null pointer");
+    GOAT_CHECK_ARG(ldg >= n && (!Q || ldq >= n), "leading dimension < n");
+    GOAT_CHECK_ARG(init == GOAT_INIT_COLD || (init == GOAT_INIT_G && g), "bad init");
+    GOAT_CHECK_ARG(max_iter >= 0, "max_iter < 0");
+    GOAT_CHECK_ARG(std::isfinite(tol) && tol >= 0.0f, "bad tol");
+    GOAT_CHECK_ARG(eps_dev || (std::isfinite(eps_rel) && eps_rel > 0.0f), "bad eps_rel");
+    const Layout L = make_layout(n, GOAT_PREC_FP32, 1);
+    const bool repack = (ldg % 4) != 0 || !aligned16(G);
+    const size_t need = small_bytes(L) + (repack ? (size_t)L.np * L.np * 4 : 0);
+    if (ws_bytes < need) { set_error("goat_sinkhorn: workspace too small"); return GOAT_ENOMEM; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ptrs p = make_ptrs(L, ws);
+    const float* Gk = G;
+    int ldk = ldg;
+    if (repack) {
+        int rc = launch_copy_pad(n, G, ldg, p.P, L.np, L.np, s);
+        if (rc) return rc;
+        Gk = p.P;
+        ldk = L.np;
+    }
+    int rc = sk_prepare(n, Gk, ldk, eps_dev, eps_rel, init == GOAT_INIT_G ? g : nullptr, tol, p.sk, p.fscal,
+                        p.red, s);
+    if (rc) return rc;
+    for (int k = 0; k < max_iter; ++k) {
+        rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, s);
+        if (rc) return rc;
+    }
+    return sk_finalize(n, L.np, Gk, ldk, p.sk, Q, ldq, nullptr, nullptr, f, g, iters_dev, err_dev, eps_out,
+                       p.red, s);
+}
+
+int goat_linesearch(int n, const float* P, const float* Q, const float* GP, const float* GQ, int ld,
+                    double* out_dev, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(P && Q && GP && GQ && out_dev && ws, "null pointer");
+    GOAT_CHECK_ARG(ld >= n, "leading dimension < n");
+    const Layout L = make_layout(n, GOAT_PREC_FP32, 1);
+    if (ws_bytes < small_bytes(L)) { set_error("goat_linesearch: workspace too small"); return GOAT_ENOMEM; }
+    Ptrs p = make_ptrs(L, ws);
+    return launch_traces(n, P, Q, GP, GQ, ld, p.red, out_dev, static_cast<hipStream_t>(stream));
+}
+
+int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host) {
+    clear_error();
+    return lap_max(n, M_host, ld, perm_host);
+}
+
+int goat_score(int n, const float* A, const float* B, int ld, const int32_t* perm_dev, double* out_dev,
+               void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(A && B && perm_dev && out_dev && ws, "null pointer");
+    GOAT_CHECK_ARG(ld >= n, "leading dimension < n");
+    const Layout L = make_layout(n, GOAT_PREC_FP32, 1);
+    if (ws_bytes < small_bytes(L)) { set_error("goat_score: workspace too small"); return GOAT_ENOMEM; }
+    Ptrs p = make_ptrs(L, ws);
+    return launch_score(n, A, B, ld, perm_dev, p.red, out_dev, static_cast<hipStream_t>(stream));
+}
+
+int goat_solve(int n, const float* A, const float* B, int ld, const float* P0, const goat_options* opt_in,
+               int32_t* perm_host, goat_stats* stats_host, goat_iter_record* hist_host, int hist_cap,
+               float* P_out, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    const auto wall0 = std::chrono::steady_clock::now();
+    goat_options opt;
+    if (opt_in) opt = *opt_in; else goat_default_options(&opt);
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(A && B && perm_host && ws, "null pointer");
+    GOAT_CHECK_ARG(ld >= n, "leading dimension < n");
+    GOAT_CHECK_ARG(opt.prec >= GOAT_PREC_FP32 && opt.prec <= GOAT_PREC_BF16X3, "unknown precision");
+    GOAT_CHECK_ARG(std::isfinite(opt.eps_rel) && opt.eps_rel > 0.0f, "eps_rel must be > 0");
+    GOAT_CHECK_ARG(std::isfinite(opt.sk_tol) && opt.sk_tol >= 0.0f, "bad sk_tol");
+    GOAT_CHECK_ARG(opt.sk_max >= 1 && opt.fw_max >= 1, "sk_max and fw_max must be >= 1");
+    GOAT_CHECK_ARG(std::isfinite(opt.fw_tol) && opt.fw_tol >= 0.0f, "bad fw_tol");
+    GOAT_CHECK_ARG(hist_cap >= 0 && (hist_cap == 0 || hist_host), "bad history buffer");
+    const int check_every = opt.check_every > 0 ? opt.check_every : 16;
+    const Layout L = make_layout(n, opt.prec, opt.symmetric);
+    if (ws_bytes < L.total) { set_error("goat_solve: workspace too small"); return GOAT_ENOMEM; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ptrs p = make_ptrs(L, ws);
+    const int np = L.np;
+    const bool bf = opt.prec != GOAT_PREC_FP32;
+    int rc;
+
+    struct HostBuf {
+        void* ptr = nullptr;
+        ~HostBuf() { if (ptr) (void)hipHostFree(ptr); }
+    } hb;
+    GOAT_HIP(hipHostMalloc(&hb.ptr, 256, hipHostMallocDefault));
+    char* hbuf = static_cast<char*>(hb.ptr);
+    int* hflag = reinterpret_cast<int*>(hbuf + 128);      // two polling slots
+    hipEvent_t ev_poll[2] = {nullptr, nullptr}, ev0 = nullptr, ev1 = nullptr;
+    struct EvGuard {
+        hipEvent_t* e; int k;
+        ~EvGuard() { for (int i = 0; i < k; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
+    };
+    hipEvent_t evs[4];
+    EvGuard eg{evs, 0};
+    for (int i = 0; i < 4; ++i) {
+        GOAT_HIP(hipEventCreate(&evs[i]));
+        eg.k = i + 1;
+    }
+    ev_poll[0] = evs[0]; ev_poll[1] = evs[1]; ev0 = evs[2]; ev1 = evs[3];
+
+    GOAT_HIP(hipMemsetAsync(ws, 0, L.total, s));
+    rc = pack_graph(L, A, ld, p.A_hi, p.A_lo, s);
+    if (!rc) rc = pack_graph(L, B, ld, p.B_hi, p.B_lo, s);
+    if (!rc) rc = P0 ? launch_copy_pad(n, P0, ld, p.P, np, np, s) : launch_fill_barycenter(n, np, p.P, s);
+    if (rc) return rc;
+    // grad f(P0): the P-side operand is P itself (fp32) or its bf16 split.
+    GradOps ops = grad_ops(p);
+    if (bf) {
+        rc = launch_split_bf16(n, np, p.P, np, static_cast<uint16_t*>(p.P_hi), static_cast<uint16_t*>(p.P_lo), s);
+        if (rc) return rc;
+    } else {
+        ops.P_hi = p.P;
+    }
+    GOAT_HIP(hipEventRecord(ev0, s));
+    rc = grad_packed(L, ops, p.GP, np, np, s);
+    if (!rc) rc = launch_absmax(n, p.GP, np, p.fscal + 16, p.fscal, s);
+    if (rc) return rc;
+
+    goat_stats st{};
+    double* ls_dev = p.scal;                                   // 8 doubles
+    int* it_dev = reinterpret_cast<int*>(p.scal + 8);
+    float* err_dev = reinterpret_cast<float*>(p.scal + 9);
+    float* eps_dev = err_dev + 1;
+    double last_ls[8] = {0};
+    int fw = 0;
+    for (fw = 1; fw <= opt.fw_max; ++fw) {
+        // LOT direction from G_P (Alg. 3 step 2)
+        const bool warm = opt.warm && fw > 1;
+        rc = sk_prepare(n, p.GP, np, nullptr, opt.eps_rel, warm ? p.g_prev : nullptr, opt.sk_tol, p.sk,
+                        p.fscal, p.red, s);
+        if (rc) return rc;
+        rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, s);
+        if (rc) return rc;
+        int k = 1, chunk = 0;
+        bool stop = false;
+        while (k < opt.sk_max && !stop) {
+            const int m = std::min(check_every, opt.sk_max - k);
+            for (int q = 0; q < m; ++q) {
+                rc = sk_iterate(n, np, p.GP, np, p.sk, 0, 1, s);
+                if (rc) return rc;
+            }
+            k += m;
+            const int slot = chunk & 1;
+            GOAT_HIP(hipMemcpyAsync(&hflag[slot], &p.sk.ctrl->done, sizeof(int), hipMemcpyDeviceToHost, s));
+            GOAT_HIP(hipEventRecord(ev_poll[slot], s));
+            if (chunk >= 1) {
+                GOAT_HIP(hipEventSynchronize(ev_poll[slot ^ 1]));
+                if (hflag[slot ^ 1]) stop = true;
+            }
+            ++chunk;
+        }
+        rc = sk_finalize(n, np, p.GP, np, p.sk, p.Q, np, bf ? static_cast<uint16_t*>(p.P_hi) : nullptr,
+                         bf ? static_cast<uint16_t*>(p.P_lo) : nullptr, nullptr, p.g_prev, it_dev, err_dev,
+                         eps_dev, p.red, s);
+        if (rc) return rc;
+        // grad f(Q) (linearity gives grad f at every point of the segment)
+        if (!bf) ops.P_hi = p.Q;
+        rc = grad_packed(L, ops, p.GQ, np, np, s);
+        if (rc) return rc;
+        // exact step (Alg. 3 step 3) and update (step 4)
+        rc = launch_traces(n, p.P, p.Q, p.GP, p.GQ, np, p.red, ls_dev, s);
+        if (!rc) rc = launch_fw_update(n, p.P, p.Q, p.GP, p.GQ, np, ls_dev, p.fscal + 16, p.fscal, s);
+        if (rc) return rc;
+        GOAT_HIP(hipMemcpyAsync(hbuf, p.scal, 80, hipMemcpyDeviceToHost, s));
+        GOAT_HIP(hipStreamSynchronize(s));
+        double ls[8];
+        std::memcpy(ls, hbuf, sizeof(ls));
+        int skit;
+        float skerr, eps;
+        std::memcpy(&skit, hbuf + 64, 4);
+        std::memcpy(&skerr, hbuf + 72, 4);
+        std::memcpy(&eps, hbuf + 76, 4);
+        std::memcpy(last_ls, ls, sizeof(ls));
+        st.sk_iters_total += skit;
+        if (skit >= opt.sk_max) st.sk_capped += 1;
+        if (fw - 1 < hist_cap) {
+            goat_iter_record& r = hist_host[fw - 1];
+            r.fP = ls[0]; r.fQ = ls[1]; r.c = ls[2]; r.a = ls[3]; r.b = ls[4]; r.t = ls[5]; r.dist2 = ls[6];
+            r.eps = eps; r.sk_err = skerr; r.sk_iters = skit; r.pad = 0;
+        }
+        const double t = ls[5];
+        const double delta = t * std::sqrt(ls[6]) / std::sqrt((double)n);
+        if ((t == 0.0 && opt.stop_on_stall) || (opt.fw_tol > 0.0f && delta < opt.fw_tol)) break;
+    }
+    st.fw_iters = std::min(fw, opt.fw_max);
+    GOAT_HIP(hipEventRecord(ev1, s));
+    GOAT_HIP(hipEventSynchronize(ev1));
+    float ms = 0.0f;
+    GOAT_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+    st.ms_loop = ms;
+    {
+        const double t = last_ls[5];
+        st.f_final = last_ls[0] + last_ls[4] * t + last_ls[3] * t * t;
+    }
+    if (P_out) GOAT_HIP(hipMemcpy2DAsync(P_out, (size_t)ld * 4, p.P, (size_t)np * 4, (size_t)n * 4, n,
+                                         hipMemcpyDeviceToDevice, s));
+    // final projection (Alg. 3 return line) on the host
+    std::vector<float> hm((size_t)n * n);
+    GOAT_HIP(hipMemcpy2DAsync(hm.data(), (size_t)n * 4, opt.proj ? p.GP : p.P, (size_t)np * 4, (size_t)n * 4, n,
+                              hipMemcpyDeviceToHost, s));
+    GOAT_HIP(hipStreamSynchronize(s));
+    const auto lap0 = std::chrono::steady_clock::now();
+    {
+        std::vector<double> md(hm.begin(), hm.end());
+        std::vector<float>().swap(hm);
+        rc = lap_max(n, md.data(), n, perm_host);
+        if (rc) return rc;
+    }
+    st.ms_lap = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - lap0).count();
+    GOAT_HIP(hipMemcpyAsync(p.perm_dev, perm_host, (size_t)n * 4, hipMemcpyHostToDevice, s));
+    rc = launch_score(n, A, B, ld, p.perm_dev, p.red, p.scal + 10, s);
+    if (rc) return rc;
+    GOAT_HIP(hipMemcpyAsync(hbuf, p.scal + 10, 8, hipMemcpyDeviceToHost, s));
+    GOAT_HIP(hipStreamSynchronize(s));
+    std::memcpy(&st.score, hbuf, 8);
+    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+    if (stats_host) *stats_host = st;
+    return GOAT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+// Internal declarations shared by the libgoat translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/goat.h"
+
+namespace goat {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string& msg);
+void clear_error();
+
+#define GOAT_CHECK_ARG(cond, msg)                     \
+    do {                                              \
+        if (!(cond)) {                                \
+            ::goat::set_error(std::string(__func__) + ": " + (msg)); \
+            return GOAT_EINVAL;                       \
+        }                                             \
+    } while (0)
+
+#define GOAT_HIP(call)                                                      \
+    do {                                                                    \
+        hipError_t e_ = (call);                                             \
+        if (e_ != hipSuccess) {                                             \
+            ::goat::set_error(std::string(#call) + ": " + hipGetErrorString(e_)); \
+            return GOAT_EHIP;                                               \
+        }                                                                   \
+    } while (0)
+
+// ---------------------------------------------------------------- sizes
+
+constexpr int kPad = 256;          // internal matrices are np x np, np = ceil(n/kPad)*kPad
+constexpr int kSkWG = 512;         // max row strips (workgroups) of a Sinkhorn sweep
+constexpr int kRedWG = 1024;       // max workgroups of a float64 reduction pass
+
+inline int pad_n(int n) { return (n + kPad - 1) / kPad * kPad; }
+
+struct SkCtrl {                    // Sinkhorn control block (device)
+    float kappa;                   // log2(e) / eps
+    float eps;
+    int   done;                    // 1 converged, 2 eps == 0 (Q = J)
+    int   iters;                   // completed column updates
+    float err;                     // last checked row-marginal error
+    float tol;
+    int   pad[2];
+};
+
+// Workspace layout. All internal matrices have leading dimension np.
+struct Layout {
+    int n = 0, np = 0, prec = 0, sym = 1;
+    size_t opA = 0, opB = 0;       // packed A and B ([X; X^T] when general)
+    size_t opP = 0;                // packed P-side operand
+    size_t opY = 0;                // intermediate product (transposed layout)
+    size_t P = 0, Q = 0, GP = 0, GQ = 0;   // solver matrices (fp32)
+    size_t u = 0, unew = 0, v = 0, colpart = 0, errpart = 0, ctrl = 0;
+    size_t red = 0;                // float64 reduction partials
+    size_t scal = 0;               // float64 scalars (line search etc.)
+    size_t fscal = 0;              // float scalars (absmax, eps)
+    size_t total = 0;
+};
+
+Layout make_layout(int n, int prec, int sym);
+
+inline size_t plane_bytes(int np, int rows_mult, int elt) {
+    return (size_t)np * np * rows_mult * elt;
+}
+
+// ---------------------------------------------------------------- bf16
+
+__host__ __device__ inline uint16_t f32_to_bf16_rne(float x) {
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_to_f32(uint16_t h) {
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+// ---------------------------------------------------------------- launchers
+
+// Operand packing into padded internal planes (pack.hip).
+enum PackMode { PACK_F32 = 0, PACK_BF16 = 1, PACK_BF16_SPLIT = 2 };
+int launch_pack(const float* src, int ld, int n, int np, int transpose, int mode,
+                void* dst_hi, void* dst_lo, hipStream_t s);
+
+// C[i][j] = alpha * sum_s sum_k X_s[i][k] Z_s[j][k]  (gemm.hip)
+enum OutMode { OUT_F32 = 0, OUT_BF16_SPLIT = 1 };
+constexpr int kMaxSeg = 6;
+struct GemmSegs {
+    const void* X[kMaxSeg];
+    const void* Z[kMaxSeg];
+    int nseg;
+};
+int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz,
+                   const GemmSegs& segs, float alpha,
+                   int out_mode, float* C, int ldc, int m_valid, int n_valid,
+                   uint16_t* C_hi, uint16_t* C_lo, int ld_split,
+                   hipStream_t s);
+
+// Gradient driver on already-packed operands (grad.cpp).
+struct GradOps {
+    const void* A_hi; const void* A_lo;     // [A; A^T] when general
+    const void* B_hi; const void* B_lo;     // [B; B^T] when general
+    const void* P_hi; const void* P_lo;     // P-side operand (fp32 in P_hi for FP32)
+    void* Y_hi; void* Y_lo;                 // intermediate
+};
+int grad_packed(const Layout& L, const GradOps& ops, float* G, int ldg, int m_valid,
+                hipStream_t s);
+
+// Sinkhorn (sinkhorn.hip)
+struct SkState {
+    float* u; float* unew; float* v; float* colpart; float* errpart; SkCtrl* ctrl;
+};
+int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_rel,
+               const float* g_init, float tol, SkState st, float* fscal, double* red,
+               hipStream_t s);
+int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check,
+               hipStream_t s);
+// Form Q (fp32 and optional bf16 split), its row-marginal error, potentials
+// in natural units, and (when P != NULL) the traces <Q,G>, <P,G>, ||Q-P||^2.
+int sk_finalize(int n, int np, const float* G, int ldg, SkState st,
+                float* Q, int ldq, uint16_t* Q_hi, uint16_t* Q_lo,
+                float* f, float* g, int* iters_out, float* err_out, float* eps_out,
+                double* red, hipStream_t s);
+
+// Elementwise / reductions (fw.hip)
+int launch_absmax(int n, const float* G, int ldg, float* partial, float* out, hipStream_t s);
+int launch_traces(int n, const float* P, const float* Q, const float* GP, const float* GQ,
+                  int ld, double* red, double* out8, hipStream_t s);
+int launch_fw_update(int n, float* P, const float* Q, float* GP, const float* GQ, int ld,
+                     const double* ls8, float* absmax_partial, float* absmax_out,
+                     hipStream_t s);
+int launch_fill_barycenter(int n, int np, float* P, hipStream_t s);
+int launch_copy_pad(int n, const float* src, int lds, float* dst, int ldd, int np, hipStream_t s);
+int launch_split_bf16(int n, int np, const float* src, int lds, uint16_t* hi, uint16_t* lo,
+                      hipStream_t s);
+int launch_score(int n, const float* A, const float* B, int ld, const int32_t* perm,
+                 double* red, double* out, hipStream_t s);
+
+// Host linear assignment (lap.cpp)
+int lap_max(int n, const double* M, int ld, int32_t* perm);
+
+}  // namespace goat

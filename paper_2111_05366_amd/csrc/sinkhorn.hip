@@ -1,0 +1,423 @@
+// Log-domain Sinkhorn-Knopp scaling for the LOT direction (Alg. 2, with the
+// cost negated for the maximisation of Alg. 3 step 2).
+//
+// Internal units: potentials in base 2 scaled by 1/eps,
+//     u_i = f_i * kappa,  v_j = g_j * kappa,  kappa = log2(e) / eps,
+// so Q_ij = 2^(G_ij kappa + u_i + v_j).
+//
+// One iteration = one read of G:
+//   row pass  (sk_row_kernel):  workgroup w owns a strip of rows. For a row i
+//     it forms e_ij = 2^(G_ij kappa + v_j + u_i) for the whole row (held in
+//     registers), S_i = sum_j e_ij (a block reduction), the new potential
+//     u_i - log2 S_i, and adds e_ij / S_i (the row-normalised plan) into
+//     per-thread column accumulators. S_i is the row sum of the current plan,
+//     so |S_i - 1| is the row-marginal error checked by the stop rule.
+//   merge     (sk_merge_kernel): c_j = sum_w partial_w[j] in fixed order,
+//     v_j <- v_j - log2 c_j, which is the column update
+//     g_j = -eps log sum_i exp((G_ij + f_i)/eps) written as a correction.
+// The first iteration shifts by the exact row maximum instead of u_i (the
+// start potentials are arbitrary). Afterwards every term is a column-
+// normalised plan entry (<= 1) and S_i, c_j lie in [1/n, n], so no further
+// shift is needed.
+#include "common.h"
+
+namespace goat {
+namespace {
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ inline float wave_sum(float x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+__device__ inline float wave_max(float x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ inline double wave_sum_d(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Block-wide sum / max; `red` holds T/64 floats and alternates between two
+// halves so consecutive reductions need one barrier each.
+template <int T>
+__device__ inline float block_sum(float x, float* red) {
+    x = wave_sum(x);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    float s = 0.0f;
+#pragma unroll
+    for (int w = 0; w < T / 64; ++w) s += red[w];
+    return s;
+}
+template <int T>
+__device__ inline float block_max(float x, float* red) {
+    x = wave_max(x);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    float s = -INFINITY;
+#pragma unroll
+    for (int w = 0; w < T / 64; ++w) s = fmaxf(s, red[w]);
+    return s;
+}
+
+struct SkArgs {
+    const float* G;
+    int ldg, n, np, rpw;       // rows per workgroup
+    float* u;
+    float* unew;
+    float* v;
+    float* colpart;            // [W][np]
+    float* errpart;            // [W]
+    SkCtrl* ctrl;
+};
+
+template <int T, int C, bool FIRST>
+__global__ __launch_bounds__(T) void sk_row_kernel(SkArgs a) {
+    if (a.ctrl->done) return;
+    __shared__ float red[4][T / 64];
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.x * a.rpw;
+    const int r1 = min(a.n, r0 + a.rpw);
+    const float kappa = a.ctrl->kappa;
+
+    float vj[C][4], acc[C][4];
+    bool live[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j4 = tid + T * c;
+        live[c] = 4 * j4 < a.n;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * j4 + e;
+            vj[c][e] = (j < a.n) ? a.v[j] : -INFINITY;
+            acc[c][e] = 0.0f;
+        }
+    }
+    float errmax = 0.0f;
+    float4 x[C], xn[C];
+    auto load_row = [&](int i, float4* dst) {
+        const float4* row = reinterpret_cast<const float4*>(a.G + (size_t)i * a.ldg);
+#pragma unroll
+        for (int c = 0; c < C; ++c) dst[c] = live[c] ? row[tid + T * c] : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    if (r0 < r1) load_row(r0, x);
+    int par = 0;
+    for (int i = r0; i < r1; ++i) {
+        if (i + 1 < r1) load_row(i + 1, xn);
+        float y[C][4];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            y[c][0] = fmaf(x[c].x, kappa, vj[c][0]);
+            y[c][1] = fmaf(x[c].y, kappa, vj[c][1]);
+            y[c][2] = fmaf(x[c].z, kappa, vj[c][2]);
+            y[c][3] = fmaf(x[c].w, kappa, vj[c][3]);
+        }
+        float shift, s = 0.0f;
+        if (FIRST) {
+            float m = -INFINITY;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) m = fmaxf(m, y[c][e]);
+            shift = -block_max<T>(m, red[par]);
+            par ^= 1;
+        } else {
+            shift = a.u[i];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                y[c][e] = exp2f(y[c][e] + shift);
+                s += y[c][e];
+            }
+        const float S = block_sum<T>(s, red[par]);
+        par ^= 1;
+        const float inv = 1.0f / S;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(y[c][e], inv, acc[c][e]);
+        if (!FIRST) errmax = fmaxf(errmax, fabsf(S - 1.0f));
+        if (tid == 0) a.unew[i] = shift - log2f(S);
+        if (i + 1 < r1) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[c] = xn[c];
+        }
+    }
+    float* out = a.colpart + (size_t)blockIdx.x * a.np;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j4 = tid + T * c;
+        if (4 * j4 < a.np)
+            reinterpret_cast<float4*>(out)[j4] = make_float4(acc[c][0], acc[c][1], acc[c][2], acc[c][3]);
+    }
+    if (!FIRST) {
+        const float m = block_max<T>(errmax, red[par]);
+        if (tid == 0) a.errpart[blockIdx.x] = m;
+    }
+}
+
+// 256 threads, 64 columns per block; wave q sums strips [q W/4, (q+1) W/4).
+__global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int check) {
+    if (a.ctrl->done) return;
+    __shared__ float part[4][64];
+    __shared__ float red[4];
+    const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+    if (check) {
+        float m = 0.0f;
+        for (int w = tid; w < W; w += 256) m = fmaxf(m, a.errpart[w]);
+        m = wave_max(m);
+        if (lane == 0) red[q] = m;
+        __syncthreads();
+        const float err = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        if (err <= a.ctrl->tol) {
+            if (blockIdx.x == 0 && tid == 0) {
+                a.ctrl->err = err;
+                a.ctrl->done = 1;
+            }
+            return;
+        }
+        if (blockIdx.x == 0 && tid == 0) a.ctrl->err = err;
+    }
+    const int j = blockIdx.x * 64 + lane;
+    const int w0 = q * W / 4, w1 = (q + 1) * W / 4;
+    float s = 0.0f;
+    if (j < a.n)
+        for (int w = w0; w < w1; ++w) s += a.colpart[(size_t)w * a.np + j];
+    part[q][lane] = s;
+    __syncthreads();
+    if (q == 0 && j < a.n) {
+        const float c = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+        a.v[j] -= log2f(fmaxf(c, 1.17549435e-38f));
+        a.u[j] = a.unew[j];
+    }
+    if (blockIdx.x == 0 && tid == 0) a.ctrl->iters += 1;
+}
+
+// eps from eps_dev or eps_rel * absmax; potentials initialised.
+__global__ __launch_bounds__(256) void sk_init_kernel(int n, const float* eps_dev, float eps_rel,
+                                                      const float* absmax, const float* g_init,
+                                                      float tol, float* u, float* v, SkCtrl* ctrl) {
+    const float eps = eps_dev ? *eps_dev : eps_rel * (*absmax);
+    const float kappa = eps > 0.0f ? kLog2e / eps : 0.0f;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        u[i] = 0.0f;
+        v[i] = (g_init && eps > 0.0f) ? g_init[i] * kappa : 0.0f;
+    }
+    if (i == 0) {
+        ctrl->kappa = kappa;
+        ctrl->eps = eps;
+        ctrl->done = eps > 0.0f ? 0 : 2;
+        ctrl->iters = 0;
+        ctrl->err = 0.0f;
+        ctrl->tol = tol;
+    }
+}
+
+// Q = 2^(G kappa + u_i + v_j) (or J when eps == 0), its largest row-marginal
+// error, optional bf16 hi/lo planes of Q (np stride), and the potentials in
+// natural units.
+struct FinArgs {
+    SkArgs a;
+    float* Q; int ldq;
+    uint16_t* Qhi; uint16_t* Qlo;
+};
+
+template <int T, int C>
+__global__ __launch_bounds__(T) void sk_finalize_kernel(FinArgs fa) {
+    const SkArgs& a = fa.a;
+    __shared__ float red[2][T / 64];
+    const int tid = threadIdx.x;
+    const int r0 = blockIdx.x * a.rpw;
+    const int r1 = min(a.n, r0 + a.rpw);
+    const float kappa = a.ctrl->kappa;
+    const bool flat = a.ctrl->done == 2;
+    const float jval = 1.0f / (float)a.n;
+    float vj[C][4];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * (tid + T * c) + e;
+            vj[c][e] = (j < a.n) ? a.v[j] : -INFINITY;
+        }
+    float errmax = 0.0f;
+    int par = 0;
+    for (int i = r0; i < r1; ++i) {
+        const float ui = a.u[i];
+        const float* grow = a.G + (size_t)i * a.ldg;
+        float s = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int j0 = 4 * (tid + T * c);
+            if (j0 >= a.np && j0 >= a.n) continue;
+            float4 g4 = j0 < a.n ? *reinterpret_cast<const float4*>(grow + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+            float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+            float q[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = j0 + e;
+                q[e] = (j < a.n) ? (flat ? jval : exp2f(fmaf(gv[e], kappa, vj[c][e]) + ui)) : 0.0f;
+                s += q[e];
+                if (j < a.n && fa.Q) fa.Q[(size_t)i * fa.ldq + j] = q[e];
+                if (fa.Qhi && j < a.np) {
+                    const uint16_t h = f32_to_bf16_rne(q[e]);
+                    fa.Qhi[(size_t)i * a.np + j] = h;
+                    fa.Qlo[(size_t)i * a.np + j] = f32_to_bf16_rne(q[e] - bf16_to_f32(h));
+                }
+            }
+        }
+        const float S = block_sum<T>(s, red[par]);
+        par ^= 1;
+        errmax = fmaxf(errmax, fabsf(S - 1.0f));
+    }
+    const float m = block_max<T>(errmax, red[par]);
+    if (tid == 0) a.errpart[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void sk_outputs_kernel(SkArgs a, int W, float* f, float* g,
+                                                         int* iters_out, float* err_out,
+                                                         float* eps_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float kappa = a.ctrl->kappa;
+    const bool flat = a.ctrl->done == 2;
+    if (i < a.n) {
+        if (f) f[i] = flat ? 0.0f : a.u[i] / kappa;
+        if (g) g[i] = flat ? 0.0f : a.v[i] / kappa;
+    }
+    if (i == 0) {
+        float m = 0.0f;
+        for (int w = 0; w < W; ++w) m = fmaxf(m, a.errpart[w]);
+        if (err_out) *err_out = m;
+        if (iters_out) *iters_out = a.ctrl->iters;
+        if (eps_out) *eps_out = a.ctrl->eps;
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+struct Geometry {
+    int T, C, W, rpw;
+};
+
+// Threads per strip: the smallest of 256 / 512 / 1024 that keeps a row's
+// share per thread at <= 40 columns (register budget without spills);
+// beyond n = 20480 the 1024-thread variant is used and spills.
+Geometry geometry(int n) {
+    Geometry g;
+    const int n4 = (n + 3) / 4;
+    g.T = n4 <= 256 * 10 ? 256 : (n4 <= 512 * 10 ? 512 : 1024);
+    g.C = (n4 + g.T - 1) / g.T;
+    const int cs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
+    for (int c : cs)
+        if (c >= g.C) { g.C = c; break; }
+    g.W = n < kSkWG ? n : kSkWG;
+    g.rpw = (n + g.W - 1) / g.W;
+    g.W = (n + g.rpw - 1) / g.rpw;
+    return g;
+}
+
+template <int T, bool FIRST>
+int launch_row_T(const Geometry& g, const SkArgs& a, hipStream_t s) {
+    dim3 grid(g.W), block(T);
+    switch (g.C) {
+#define GOAT_SK_C(CC) case CC: hipLaunchKernelGGL((sk_row_kernel<T, CC, FIRST>), grid, block, 0, s, a); break;
+        GOAT_SK_C(1) GOAT_SK_C(2) GOAT_SK_C(3) GOAT_SK_C(4) GOAT_SK_C(5) GOAT_SK_C(6)
+        GOAT_SK_C(8) GOAT_SK_C(10) GOAT_SK_C(12) GOAT_SK_C(16)
+#undef GOAT_SK_C
+        default: set_error("sinkhorn: unsupported n"); return GOAT_ENOTSUP;
+    }
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+template <int T>
+int launch_fin_T(const Geometry& g, const FinArgs& fa, hipStream_t s) {
+    dim3 grid(g.W), block(T);
+    switch (g.C) {
+#define GOAT_SK_C(CC) case CC: hipLaunchKernelGGL((sk_finalize_kernel<T, CC>), grid, block, 0, s, fa); break;
+        GOAT_SK_C(1) GOAT_SK_C(2) GOAT_SK_C(3) GOAT_SK_C(4) GOAT_SK_C(5) GOAT_SK_C(6)
+        GOAT_SK_C(8) GOAT_SK_C(10) GOAT_SK_C(12) GOAT_SK_C(16)
+#undef GOAT_SK_C
+        default: set_error("sinkhorn: unsupported n"); return GOAT_ENOTSUP;
+    }
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+SkArgs make_args(int n, int np, const float* G, int ldg, const SkState& st, const Geometry& g) {
+    SkArgs a;
+    a.G = G;
+    a.ldg = ldg;
+    a.n = n;
+    a.np = np;
+    a.rpw = g.rpw;
+    a.u = st.u;
+    a.unew = st.unew;
+    a.v = st.v;
+    a.colpart = st.colpart;
+    a.errpart = st.errpart;
+    a.ctrl = st.ctrl;
+    return a;
+}
+
+}  // namespace
+
+int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_rel,
+               const float* g_init, float tol, SkState st, float* fscal, double* red,
+               hipStream_t s) {
+    (void)red;
+    const float* absmax = nullptr;
+    if (!eps_dev) {
+        int rc = launch_absmax(n, G, ldg, fscal + 16, fscal, s);
+        if (rc) return rc;
+        absmax = fscal;
+    }
+    hipLaunchKernelGGL(sk_init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, eps_dev, eps_rel,
+                       absmax, g_init, tol, st.u, st.v, st.ctrl);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check,
+               hipStream_t s) {
+    const Geometry g = geometry(n);
+    const SkArgs a = make_args(n, np, G, ldg, st, g);
+    int rc;
+    if (g.T == 256) rc = first ? launch_row_T<256, true>(g, a, s) : launch_row_T<256, false>(g, a, s);
+    else if (g.T == 512) rc = first ? launch_row_T<512, true>(g, a, s) : launch_row_T<512, false>(g, a, s);
+    else rc = first ? launch_row_T<1024, true>(g, a, s) : launch_row_T<1024, false>(g, a, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(sk_merge_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a, g.W, check);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+int sk_finalize(int n, int np, const float* G, int ldg, SkState st, float* Q, int ldq,
+                uint16_t* Q_hi, uint16_t* Q_lo, float* f, float* g, int* iters_out,
+                float* err_out, float* eps_out, double* red, hipStream_t s) {
+    (void)red;
+    const Geometry geo = geometry(n);
+    FinArgs fa;
+    fa.a = make_args(n, np, G, ldg, st, geo);
+    fa.Q = Q;
+    fa.ldq = ldq;
+    fa.Qhi = Q_hi;
+    fa.Qlo = Q_lo;
+    int rc = geo.T == 256 ? launch_fin_T<256>(geo, fa, s)
+             : (geo.T == 512 ? launch_fin_T<512>(geo, fa, s) : launch_fin_T<1024>(geo, fa, s));
+    if (rc) return rc;
+    hipLaunchKernelGGL(sk_outputs_kernel, dim3((n + 255) / 256), dim3(256), 0, s, fa.a, geo.W, f, g,
+                       iters_out, err_out, eps_out);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+}  // namespace goat

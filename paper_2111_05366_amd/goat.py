@@ -1,0 +1,278 @@
+"""Thin ctypes binding of libgoat (include/goat.h).
+
+Argument marshalling only: every step of the GOAT path runs in the HIP
+library. PyTorch supplies device memory (tensors' data pointers) and the
+current HIP stream. Functions raise GoatError on a negative status and
+RuntimeError if the library has not been built - there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgoat.so")
+
+GOAT_OK, GOAT_EINVAL, GOAT_EHIP, GOAT_ENOMEM, GOAT_ENOTSUP = 0, -1, -2, -3, -4
+PREC = {"fp32": 0, "bf16x2": 1, "bf16x3": 2}
+INIT_COLD, INIT_G = 0, 1
+
+
+class GoatError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"goat status {status}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("eps_rel", ctypes.c_float), ("sk_tol", ctypes.c_float), ("sk_max", ctypes.c_int),
+                ("fw_max", ctypes.c_int), ("fw_tol", ctypes.c_float), ("prec", ctypes.c_int),
+                ("symmetric", ctypes.c_int), ("proj", ctypes.c_int), ("warm", ctypes.c_int),
+                ("stop_on_stall", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
+
+
+class IterRecord(ctypes.Structure):
+    _fields_ = [("fP", ctypes.c_double), ("fQ", ctypes.c_double), ("c", ctypes.c_double),
+                ("a", ctypes.c_double), ("b", ctypes.c_double), ("t", ctypes.c_double),
+                ("dist2", ctypes.c_double), ("eps", ctypes.c_float), ("sk_err", ctypes.c_float),
+                ("sk_iters", ctypes.c_int), ("pad", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("fw_iters", ctypes.c_int), ("sk_iters_total", ctypes.c_int),
+                ("sk_capped", ctypes.c_int), ("pad", ctypes.c_int),
+                ("f_final", ctypes.c_double), ("score", ctypes.c_double),
+                ("ms_loop", ctypes.c_double), ("ms_lap", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
+_lib = None
+_VP, _I, _F, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
+
+
+def lib():
+    """Load libgoat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2111_05366_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.goat_version.restype = _I
+    L.goat_last_error.restype = ctypes.c_char_p
+    L.goat_workspace_size.restype = _SZ
+    L.goat_workspace_size.argtypes = [_I, _I, _I]
+    L.goat_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.goat_grad.restype = _I
+    L.goat_grad.argtypes = [_I, _VP, _VP, _I, _VP, _I, _VP, _I, _I, _I, _VP, _SZ, _VP]
+    L.goat_sinkhorn.restype = _I
+    L.goat_sinkhorn.argtypes = [_I, _VP, _I, _VP, _F, _VP, _VP, _I, _I, _F, _VP, _I, _VP, _VP, _VP,
+                                _VP, _SZ, _VP]
+    L.goat_linesearch.restype = _I
+    L.goat_linesearch.argtypes = [_I, _VP, _VP, _VP, _VP, _I, _VP, _VP, _SZ, _VP]
+    L.goat_solve.restype = _I
+    L.goat_solve.argtypes = [_I, _VP, _VP, _I, _VP, ctypes.POINTER(Options), _VP,
+                             ctypes.POINTER(Stats), ctypes.POINTER(IterRecord), _I, _VP, _VP, _SZ, _VP]
+    L.goat_lap_max.restype = _I
+    L.goat_lap_max.argtypes = [_I, _VP, _I, _VP]
+    L.goat_score.restype = _I
+    L.goat_score.argtypes = [_I, _VP, _VP, _I, _VP, _VP, _VP, _SZ, _VP]
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != GOAT_OK:
+        raise GoatError(status, lib().goat_last_error().decode())
+
+
+def version() -> int:
+    return lib().goat_version()
+
+
+def workspace_size(n: int, prec: str = "fp32", symmetric: bool = True) -> int:
+    return int(lib().goat_workspace_size(n, PREC[prec], int(symmetric)))
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().goat_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "prec" and isinstance(v, str):
+            v = PREC[v]
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+# --------------------------------------------------------------- torch side
+
+def _torch():
+    import torch
+    return torch
+
+
+_ws_cache: dict = {}
+
+
+def workspace(n: int, prec: str = "fp32", symmetric: bool = True, device=None):
+    """A cached device workspace tensor sized for every call at (n, prec)."""
+    torch = _torch()
+    device = device or torch.device("cuda", torch.cuda.current_device())
+    need = workspace_size(n, prec, symmetric)
+    key = (str(device),)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < need:
+        _ws_cache.pop(key, None)
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def release_workspace():
+    _ws_cache.clear()
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _mat(t, name):
+    torch = _torch()
+    if t.dtype != torch.float32 or not t.is_cuda or t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name}: need a row-major float32 CUDA matrix")
+    return t
+
+
+def grad(A, B, P, prec: str = "fp32", symmetric: bool = True, out=None):
+    """G = A P B^T + A^T P B on the device (goat_grad)."""
+    torch = _torch()
+    n = A.shape[0]
+    for nm, t in (("A", A), ("B", B), ("P", P)):
+        _mat(t, nm)
+    if A.stride(0) != B.stride(0):
+        raise ValueError("A and B must share a leading dimension")
+    G = out if out is not None else torch.empty((n, n), dtype=torch.float32, device=A.device)
+    ws = workspace(n, prec, symmetric, A.device)
+    _check(lib().goat_grad(n, _ptr(A), _ptr(B), A.stride(0), _ptr(P), P.stride(0), _ptr(G), G.stride(0),
+                           PREC[prec], int(symmetric), _ptr(ws), ws.numel(), _stream()))
+    return G
+
+
+@dataclass
+class SinkhornOut:
+    f: object
+    g: object
+    Q: object
+    iters: object     # device int32[1]
+    err: object       # device float32[1]
+    eps: object       # device float32[1]
+
+
+def sinkhorn(G, eps_rel: float = 0.03, max_iter: int = 1000, tol: float = 1e-6, g0=None, eps=None,
+             want_Q: bool = True) -> SinkhornOut:
+    """LOT direction on the device (goat_sinkhorn)."""
+    torch = _torch()
+    _mat(G, "G")
+    n = G.shape[0]
+    dev = G.device
+    f = torch.empty(n, dtype=torch.float32, device=dev)
+    g = torch.empty(n, dtype=torch.float32, device=dev) if g0 is None else g0.clone()
+    Q = torch.empty((n, n), dtype=torch.float32, device=dev) if want_Q else None
+    it = torch.zeros(1, dtype=torch.int32, device=dev)
+    err = torch.zeros(1, dtype=torch.float32, device=dev)
+    eps_out = torch.zeros(1, dtype=torch.float32, device=dev)
+    eps_t = None
+    if eps is not None:
+        eps_t = torch.tensor([eps], dtype=torch.float32, device=dev)
+    ws = workspace(n, "fp32", True, dev)
+    _check(lib().goat_sinkhorn(n, _ptr(G), G.stride(0), _ptr(eps_t), float(eps_rel), _ptr(f), _ptr(g),
+                               INIT_G if g0 is not None else INIT_COLD, int(max_iter), float(tol),
+                               _ptr(Q), Q.stride(0) if Q is not None else n, _ptr(it), _ptr(err),
+                               _ptr(eps_out), _ptr(ws), ws.numel(), _stream()))
+    return SinkhornOut(f, g, Q, it, err, eps_out)
+
+
+def linesearch(P, Q, GP, GQ):
+    """[fP, fQ, c, a, b, t, ||Q-P||^2, 0] as a device float64 tensor."""
+    torch = _torch()
+    n = P.shape[0]
+    for nm, t in (("P", P), ("Q", Q), ("GP", GP), ("GQ", GQ)):
+        _mat(t, nm)
+    ld = P.stride(0)
+    if not (Q.stride(0) == GP.stride(0) == GQ.stride(0) == ld):
+        raise ValueError("P, Q, GP, GQ must share a leading dimension")
+    out = torch.zeros(8, dtype=torch.float64, device=P.device)
+    ws = workspace(n, "fp32", True, P.device)
+    _check(lib().goat_linesearch(n, _ptr(P), _ptr(Q), _ptr(GP), _ptr(GQ), ld, _ptr(out), _ptr(ws),
+                                 ws.numel(), _stream()))
+    return out
+
+
+def score(A, B, perm):
+    """tr(A^T Pi B Pi^T) for a permutation (goat_score), float64 on device."""
+    torch = _torch()
+    n = A.shape[0]
+    p = torch.as_tensor(np.asarray(perm, dtype=np.int32), device=A.device)
+    out = torch.zeros(1, dtype=torch.float64, device=A.device)
+    ws = workspace(n, "fp32", True, A.device)
+    _check(lib().goat_score(n, _ptr(A), _ptr(B), A.stride(0), _ptr(p), _ptr(out), _ptr(ws), ws.numel(),
+                            _stream()))
+    return out
+
+
+def lap_max(M: np.ndarray) -> np.ndarray:
+    """Host linear assignment maximising sum_i M[i, perm[i]] (goat_lap_max)."""
+    M = np.ascontiguousarray(M, dtype=np.float64)
+    n = M.shape[0]
+    perm = np.empty(n, dtype=np.int32)
+    _check(lib().goat_lap_max(n, M.ctypes.data_as(ctypes.c_void_p), n, perm.ctypes.data_as(ctypes.c_void_p)))
+    return perm
+
+
+@dataclass
+class SolveResult:
+    perm: np.ndarray
+    stats: Stats
+    history: list
+    P: object
+
+
+def solve(A, B, P0=None, return_P: bool = False, **opts) -> SolveResult:
+    """Full GOAT for one pair (goat_solve). Options as in goat_options."""
+    torch = _torch()
+    _mat(A, "A"); _mat(B, "B")
+    n = A.shape[0]
+    if A.stride(0) != B.stride(0):
+        raise ValueError("A and B must share a leading dimension")
+    o = default_options(**opts)
+    prec = {v: k for k, v in PREC.items()}[o.prec]
+    ws = workspace(n, prec, bool(o.symmetric), A.device)
+    perm = np.empty(n, dtype=np.int32)
+    st = Stats()
+    cap = max(o.fw_max, 1)
+    hist = (IterRecord * cap)()
+    Pout = torch.empty((n, n), dtype=torch.float32, device=A.device) if return_P else None
+    if P0 is not None:
+        _mat(P0, "P0")
+        if P0.stride(0) != A.stride(0):
+            raise ValueError("P0 must share A's leading dimension")
+    _check(lib().goat_solve(n, _ptr(A), _ptr(B), A.stride(0), _ptr(P0), ctypes.byref(o),
+                            perm.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st), hist, cap,
+                            _ptr(Pout), _ptr(ws), ws.numel(), _stream()))
+    h = []
+    for k in range(st.fw_iters):
+        r = hist[k]
+        h.append(dict(fP=r.fP, fQ=r.fQ, c=r.c, a=r.a, b=r.b, t=r.t, dist2=r.dist2, eps=r.eps,
+                      sk_err=r.sk_err, sk_iters=r.sk_iters))
+    return SolveResult(perm.astype(np.int64), st, h, Pout)

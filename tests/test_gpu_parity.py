@@ -1,0 +1,230 @@
+"""GPU-versus-oracle parity of every C-ABI call, on identical seeded inputs
+(float32 on the device, promoted exactly to float64 for the oracle).
+
+Tolerances: gradient and Q relative Frobenius error <= 1e-4 (the FP32
+bound), relaxed objective <= 1e-5 relative, permutations bit-exact given the
+same P when the assignment optimum is unique."""
+import numpy as np
+import pytest
+
+from oracle import goat_oracle as O
+from paper_2111_05366_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_05366_amd import goat
+    goat.lib()
+    yield goat
+    goat.release_workspace()
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rel_fro(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _pair(kind, n, seed):
+    if kind == "er":
+        g = I.rho_er_pair(n, min(0.5, 12.0 / n), 0.8, seed)
+        return g.A, g.B
+    if kind == "wsbm":
+        k = 4
+        sizes = [n // k + (1 if r < n % k else 0) for r in range(k)]
+        bp = np.full((k, k), 0.05); np.fill_diagonal(bp, 0.2)
+        g = I.weighted_sbm_pair(sizes, bp, 0.1, seed)
+        return g.A, g.B
+    A = I.random_matrix(n, n, seed, -1, 1)
+    B = I.random_matrix(n, n, seed + 1, -1, 1)
+    return A, B
+
+
+GRAD_CASES = [
+    ("fp32", True, "er"), ("fp32", True, "wsbm"), ("fp32", False, "gen"),
+    ("bf16x2", True, "er"), ("bf16x3", True, "wsbm"), ("bf16x3", False, "gen"),
+]
+
+
+@pytest.mark.parametrize("n", [64, 300, 1000])
+@pytest.mark.parametrize("prec,sym,kind", GRAD_CASES)
+def test_grad_parity(G, n, prec, sym, kind):
+    print(f"grad prec={prec} sym={sym} kind={kind} n={n}", flush=True)
+    A, B = _pair(kind, n, 10 + n)
+    P = I.uniform_matrix(n, 20 + n) / n
+    Gd = G.grad(dev(A), dev(B), dev(P), prec=prec, symmetric=sym)
+    ref = O.gradient(A.astype(np.float64), B.astype(np.float64), P.astype(np.float64))
+    got = host(Gd)
+    err = rel_fro(got, ref)
+    maxrel = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+    print(f"  rel_fro={err:.3e} max_rel={maxrel:.3e}")
+    assert err <= 1e-4
+    if prec == "fp32":
+        assert err <= 1e-5
+
+
+def test_grad_barycenter_and_permutation(G):
+    n = 300
+    g = I.rho_er_pair(n, 0.05, 0.9, 5)
+    A, B = dev(g.A), dev(g.B)
+    J = torch.full((n, n), 1.0 / n, device="cuda")
+    got = host(G.grad(A, B, J))
+    ref = O.gradient(g.A.astype(float), g.B.astype(float), O.barycenter(n))
+    assert rel_fro(got, ref) <= 1e-5
+    perm = np.random.default_rng(3).permutation(n)
+    Pi = O.perm_matrix(perm)
+    got = host(G.grad(A, B, dev(Pi), prec="bf16x2"))
+    ref = O.gradient(g.A.astype(float), g.B.astype(float), Pi)
+    assert np.max(np.abs(got - ref)) == 0.0       # integer-valued: exact in bf16 with fp32 accumulation
+
+
+def _sk_problem(n, seed):
+    g = I.rho_er_pair(n, min(0.5, 12.0 / n), 0.9, seed)
+    P = I.uniform_matrix(n, seed + 1).astype(np.float64)
+    P = O.sinkhorn_knopp(P + 0.05)
+    Gm = O.gradient(g.A.astype(float), g.B.astype(float), 0.5 * (P + O.barycenter(n)))
+    return Gm.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [64, 257, 1000])
+@pytest.mark.parametrize("iters", [1, 7, 60, 300])
+def test_sinkhorn_parity_fixed_iterations(G, n, iters):
+    print(f"sinkhorn n={n} iters={iters}", flush=True)
+    Gm = _sk_problem(n, 40 + n)
+    out = G.sinkhorn(dev(Gm), eps_rel=0.03, max_iter=iters, tol=0.0)
+    eps = float(host(out.eps)[0])
+    ref = O.log_sinkhorn_max(Gm.astype(np.float64), eps, tol=0.0, max_iter=iters)
+    assert int(out.iters.item()) == iters == ref.iters
+    err = rel_fro(host(out.Q), ref.Q)
+    df = np.max(np.abs(host(out.f) - ref.f)) / eps
+    dg = np.max(np.abs(host(out.g) - ref.g)) / eps
+    print(f"  Q rel_fro={err:.3e} |df|/eps={df:.2e} |dg|/eps={dg:.2e} err={out.err.item():.3e} ref={ref.err:.3e}")
+    assert err <= 1e-4
+    assert df <= 1e-4 and dg <= 1e-4
+    assert abs(float(out.err.item()) - ref.err) <= 1e-4 + 1e-3 * ref.err
+
+
+def test_sinkhorn_stops_like_oracle(G):
+    n = 300
+    Gm = _sk_problem(n, 77)
+    out = G.sinkhorn(dev(Gm), eps_rel=0.1, max_iter=2000, tol=1e-4)
+    eps = float(host(out.eps)[0])
+    ref = O.log_sinkhorn_max(Gm.astype(np.float64), eps, tol=1e-4, max_iter=2000)
+    assert ref.converged
+    assert abs(int(out.iters.item()) - ref.iters) <= 2
+    assert float(out.err.item()) <= 1e-4 * 1.05
+    assert rel_fro(host(out.Q), ref.Q) <= 1e-4
+
+
+def test_sinkhorn_warm_start_parity(G):
+    n = 257
+    Gm = _sk_problem(n, 91)
+    g0 = np.random.default_rng(5).normal(size=n).astype(np.float32) * 0.1
+    out = G.sinkhorn(dev(Gm), eps_rel=0.03, max_iter=40, tol=0.0, g0=torch.as_tensor(g0, device="cuda"))
+    eps = float(host(out.eps)[0])
+    ref = O.log_sinkhorn_max(Gm.astype(np.float64), eps, tol=0.0, max_iter=40, g0=g0.astype(np.float64))
+    assert rel_fro(host(out.Q), ref.Q) <= 1e-4
+
+
+def test_sinkhorn_degenerate(G):
+    n = 33
+    out = G.sinkhorn(torch.zeros((n, n), device="cuda"), max_iter=10)
+    assert int(out.iters.item()) == 0
+    assert np.allclose(host(out.Q), 1.0 / n)
+    # n = 1: the only doubly stochastic matrix is [1]
+    out = G.sinkhorn(torch.full((1, 1), 3.0, device="cuda"), max_iter=5)
+    assert abs(host(out.Q)[0, 0] - 1.0) < 1e-6
+    # caller-given eps, unaligned leading dimension (repacked)
+    Gm = _sk_problem(50, 3)
+    big = torch.zeros((50, 53), device="cuda")
+    big[:, :50] = dev(Gm)
+    view = big[:, :50]
+    out = G.sinkhorn(view, eps=0.5, max_iter=25, tol=0.0)
+    ref = O.log_sinkhorn_max(Gm.astype(np.float64), 0.5, tol=0.0, max_iter=25)
+    assert rel_fro(host(out.Q), ref.Q) <= 1e-4
+
+
+def test_linesearch_parity(G):
+    n = 300
+    g = I.rho_er_pair(n, 0.05, 0.8, 8)
+    A, B = g.A.astype(float), g.B.astype(float)
+    rng = np.random.default_rng(9)
+    P = O.sinkhorn_knopp(rng.random((n, n)) + 0.1).astype(np.float32)
+    Q = O.sinkhorn_knopp(rng.random((n, n)) ** 6 + 1e-4).astype(np.float32)
+    GP = O.gradient(A, B, P.astype(float)).astype(np.float32)
+    GQ = O.gradient(A, B, Q.astype(float)).astype(np.float32)
+    out = host(G.linesearch(dev(P), dev(Q), dev(GP), dev(GQ)))
+    ls = O.linesearch(P, Q, GP, GQ)
+    for k, name in enumerate(["fP", "fQ", "c", "a", "b", "t", "dist2"]):
+        ref = getattr(ls, name)
+        assert out[k] == pytest.approx(ref, rel=1e-12, abs=1e-12), name
+
+
+def test_score_exact(G):
+    n = 500
+    g = I.rho_er_pair(n, 0.05, 0.8, 12)
+    perm = np.random.default_rng(1).permutation(n)
+    s = host(G.score(dev(g.A), dev(g.B), perm))[0]
+    assert s == O.qap_value(g.A, g.B, perm)
+
+
+def test_bitwise_deterministic(G):
+    n = 300
+    A, B = _pair("wsbm", n, 4)
+    P = I.uniform_matrix(n, 5) / n
+    g1 = host(G.grad(dev(A), dev(B), dev(P), prec="bf16x3"))
+    g2 = host(G.grad(dev(A), dev(B), dev(P), prec="bf16x3"))
+    assert np.array_equal(g1, g2)
+    Gm = _sk_problem(n, 6)
+    q1 = G.sinkhorn(dev(Gm), max_iter=50, tol=0.0)
+    q2 = G.sinkhorn(dev(Gm), max_iter=50, tol=0.0)
+    assert np.array_equal(host(q1.Q), host(q2.Q))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+def test_solve_parity_er64(G, prec):
+    g = I.workload_er_small()
+    print(f"solve n=64 prec={prec}", flush=True)
+    r = G.solve(dev(g.A), dev(g.B), prec=prec, sk_max=500, return_P=True)
+    ref = O.goat(g.A, g.B, opt=O.GoatOptions(sk_max=500), record=True)
+    mr_gpu = O.match_ratio(r.perm, g.truth)
+    mr_orc = O.match_ratio(ref.perm, g.truth)
+    print(f"  match gpu={mr_gpu} oracle={mr_orc} fw gpu={r.stats.fw_iters} oracle={ref.fw_iters}")
+    assert abs(mr_gpu - mr_orc) <= 0.005
+    # relaxed objective of the first iterations agrees per step
+    for k in range(min(3, len(r.history), len(ref.history))):
+        assert r.history[k]["fP"] == pytest.approx(ref.history[k]["fP"], rel=1e-5)
+    # final permutation bit-exact from the same P
+    Pf = host(r.P)
+    assert list(O.hungarian_max(Pf)) == list(r.perm)
+    assert r.stats.score == pytest.approx(O.qap_value(g.A, g.B, r.perm))
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_solve_isomorphic_recovery(G, seed):
+    g = I.rho_er_pair(64, 0.1, 1.0, 900 + seed)
+    r = G.solve(dev(g.A), dev(g.B), sk_max=500)
+    assert O.edge_disagreements(g.A, g.B, r.perm) == 0.0
+
+
+def test_solve_general_pair_matches_oracle_first_step(G):
+    n = 80
+    A = I.random_matrix(n, n, 3, 0, 1)
+    B = I.random_matrix(n, n, 4, 0, 1)
+    r = G.solve(dev(A), dev(B), prec="fp32", symmetric=0, sk_max=300, fw_max=2)
+    ref = O.goat(A, B, opt=O.GoatOptions(sk_max=300, fw_max=2), record=True)
+    assert r.history[0]["fP"] == pytest.approx(ref.history[0]["fP"], rel=1e-6)
+    assert r.history[0]["t"] == pytest.approx(ref.history[0]["t"], abs=1e-4)
