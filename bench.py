@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Frank-Wolfe iterations per second of GOAT on one MI355X.
+
+Workload: the weighted 4-block SBM pair at n = 10,000 (block edge
+probabilities 0.02 in-block / 0.005 out, lognormal(0,1) weights, B = A plus
+N(0, 0.1^2) noise on A's edges, nodes of B shuffled), seeded and synthetic;
+it stands in for the paper's 10,000-node weighted email subgraphs.
+
+A step is one Frank-Wolfe iteration of Alg. 3 on the device (gradient
+product, LOT Sinkhorn solve to tolerance 1e-6 or 1000 sweeps, exact step,
+update) with A, B, P resident in HBM. Two forms run on the same pair:
+  plain : fp32 matrix-core gradient, cold Sinkhorn start each iteration;
+  mixed : bf16 hi/lo-split gradient (3 products), Sinkhorn started from the
+          previous iteration's column potentials.
+`value` is the mixed form's rate; the plain one is in `config`.
+
+The dominant kernel is the Sinkhorn row sweep (HBM-bound: it reads G once,
+4 n^2 bytes per launch); its per-launch duration is sampled with HIP events
+on its stream during the timed steps. The CPU baseline times the FP64
+oracle's own gradient and Sinkhorn sweep on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_form(goat, A, B, n, form, warmup, steps, sk_max, sk_tol, prof_stride):
+    import torch
+    prec = "fp32" if form == "plain" else "bf16x3"
+    warm = 0 if form == "plain" else 1
+    run = goat.Run(A, B, prec=prec, warm=warm, stop_on_stall=0, sk_max=sk_max, sk_tol=sk_tol)
+    run.steps(warmup)
+    log(f"{form}: warmup {warmup} done")
+    goat.profile_enable(goat.PROF_SINKHORN_ROW, prof_stride)
+    goat.profile_enable(goat.PROF_GEMM, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = run.steps(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sk_ms, sk_cnt = goat.profile_read(goat.PROF_SINKHORN_ROW)
+    gm_ms, gm_cnt = goat.profile_read(goat.PROF_GEMM)
+    goat.profile_enable(goat.PROF_SINKHORN_ROW, 0)
+    goat.profile_enable(goat.PROF_GEMM, 0)
+    assert done == steps
+    log(f"{form}: timed {steps} steps in {t1 - t0:.2f} s; final assignment on the host ...")
+    res = run.finish()
+    run.close()
+    hist = res.history[warmup:]
+    sk_iters = [h["sk_iters"] for h in hist]
+    np_ = (n + 255) // 256 * 256
+    gemm_exec_flops = (12 if prec == "bf16x3" else 4) * float(np_) ** 3   # per gradient (2 launches)
+    out = dict(
+        form=form, prec=prec, warm=warm,
+        fw_iters_per_s=steps / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / steps,
+        sk_iters_mean=sum(sk_iters) / len(sk_iters), sk_capped=sum(1 for s in sk_iters if s >= sk_max),
+        sk_row_ms=sk_ms / max(sk_cnt, 1), sk_row_samples=sk_cnt,
+        gemm_ms_per_grad=2 * gm_ms / max(gm_cnt, 1), gemm_samples=gm_cnt,
+        gemm_exec_tflops=gemm_exec_flops / (2 * gm_ms / max(gm_cnt, 1) * 1e-3) / 1e12 if gm_cnt else None,
+        gemm_alg_tflops=4.0 * float(n) ** 3 / (2 * gm_ms / max(gm_cnt, 1) * 1e-3) / 1e12 if gm_cnt else None,
+        perm=res.perm, t_hist=[round(h["t"], 6) for h in hist], f_final=res.stats.f_final,
+        score=res.stats.score, lap_ms=res.stats.ms_lap,
+    )
+    log(f"{form}: {out['fw_iters_per_s']:.3f} FW it/s, {out['ms_per_step']:.1f} ms/step, "
+        f"sk iters mean {out['sk_iters_mean']:.1f}, row sweep {out['sk_row_ms']*1e3:.1f} us, "
+        f"grad {out['gemm_ms_per_grad']:.2f} ms")
+    return out
+
+
+def cpu_baseline(pair, n, sk_iters_per_fw):
+    """Time the FP64 oracle on a bounded sample of the same workload: one
+    gradient and two Sinkhorn sweeps, scaled to one FW iteration (two
+    gradients + the measured number of sweeps)."""
+    import numpy as np
+    from oracle import goat_oracle as O
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        cores = max([d.get("num_threads", 1) for d in info] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    A = pair.A.astype(np.float64)
+    B = pair.B.astype(np.float64)
+    P = O.barycenter(n)
+    t0 = time.perf_counter()
+    G = O.gradient(A, B, P)
+    t_grad = time.perf_counter() - t0
+    eps = 0.03 * float(np.max(np.abs(G)))
+    t0 = time.perf_counter()
+    O.log_sinkhorn_max(G, eps, tol=0.0, max_iter=2)
+    t_sk = (time.perf_counter() - t0) / 2
+    t_fw = 2 * t_grad + sk_iters_per_fw * t_sk
+    return dict(value=1.0 / t_fw, unit="FW iters/s", cores=int(cores), kind="oracle",
+                sample=(f"n={n}: 1 oracle gradient ({t_grad:.1f} s) + 2 oracle Sinkhorn sweeps "
+                        f"({t_sk:.2f} s each), scaled to one FW iteration = 2 gradients + "
+                        f"{sk_iters_per_fw:.0f} sweeps (the GPU plain form's mean)"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=10000)
+    ap.add_argument("--sk-max", type=int, default=1000)
+    ap.add_argument("--sk-tol", type=float, default=1e-6)
+    ap.add_argument("--forms", default="plain,mixed")
+    ap.add_argument("--prof-stride", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--json-out", default=None)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+              "(use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2111_05366_amd import goat, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    goat.lib()
+    n = args.n
+    t0 = time.perf_counter()
+    pair = inputs.workload_weighted_sbm(n)
+    log(f"generated weighted SBM pair n={n} in {time.perf_counter() - t0:.1f} s "
+        f"(nnz per graph {int((pair.A != 0).sum())})")
+    A = torch.as_tensor(pair.A, device="cuda")
+    B = torch.as_tensor(pair.B, device="cuda")
+    forms = {}
+    for form in args.forms.split(","):
+        forms[form] = run_form(goat, A, B, n, form, args.warmup, args.steps, args.sk_max, args.sk_tol,
+                               args.prof_stride)
+        forms[form]["match_ratio"] = float(np.mean(forms[form]["perm"] == pair.truth))
+        log(f"{form}: match ratio {forms[form]['match_ratio']:.4f}")
+    main_form = forms.get("mixed") or next(iter(forms.values()))
+    plain = forms.get("plain")
+
+    # roofline of the dominant kernel: the Sinkhorn row sweep reads G (4 n^2 B)
+    alg_bytes = 4.0 * n * n
+    achieved = alg_bytes / (main_form["sk_row_ms"] * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                kernel="sk_row_kernel (Sinkhorn row sweep)",
+                per_launch=f"4*n^2 = {alg_bytes:.3e} B", avg_launch_us=round(main_form["sk_row_ms"] * 1e3, 2),
+                samples=main_form["sk_row_samples"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(pair, n, (plain or main_form)["sk_iters_mean"])
+        log(f"cpu baseline {cpu['value']:.2e} FW it/s on {cpu['cores']} threads")
+
+    def summary(f):
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in f.items()
+                if k not in ("perm", "t_hist")}
+
+    line = {
+        "metric": "FW iters/s at n=10k, mixed+warm-start vs plain FP32, at oracle match ratio",
+        "value": round(main_form["fw_iters_per_s"], 4),
+        "unit": "FW iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_form["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3+f32+f64" if main_form["prec"] == "bf16x3" else "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"weighted 4-block SBM pair n={n}, p_in=0.02, p_out=0.005, lognormal(0,1) "
+                        f"weights, B = A + N(0,0.1^2) on A's edges, shuffled",
+            "n": n, "eps_rel": 0.03, "sk_tol": args.sk_tol, "sk_max": args.sk_max,
+            "form": main_form["form"],
+            "forms": {k: summary(v) for k, v in forms.items()},
+            "speedup_vs_plain_fp32": (round(main_form["fw_iters_per_s"] / plain["fw_iters_per_s"], 3)
+                                      if plain and main_form is not plain else None),
+            "gemm_roofline": {
+                "bound": "mfma", "kernel": "gemm_nt (2 launches per gradient)",
+                "achieved_exec": round(main_form["gemm_exec_tflops"], 1) if main_form["gemm_exec_tflops"] else None,
+                "peak": MFMA_PEAK_TFLOPS["bf16" if main_form["prec"] != "fp32" else "fp32"],
+                "unit": "TFLOP/s",
+            },
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    txt = json.dumps(line)
+    print(txt, flush=True)
+    if args.json_out:
+        with open(args.json_out, "w") as fh:
+            fh.write(txt + "\n")
+
+
+if __name__ == "__main__":
+    main()

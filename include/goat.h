@@ -186,10 +186,47 @@ int goat_solve(int n, const float* A, const float* B, int ld,
                void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Stepwise form of goat_solve, for callers that time or inspect a fixed
+ * number of Frank-Wolfe iterations (Alg. 3 loop body):
+ *  goat_run_begin   packs A and B, sets P0 (NULL = barycenter) and computes
+ *                   grad f(P0); the workspace must stay untouched until
+ *                   goat_run_free. *run receives a host handle.
+ *  goat_run_steps   runs up to k iterations (fewer once stopped by a stall
+ *                   or fw_tol when those stops are enabled); hist_host gets
+ *                   one record per iteration run, *done_out their number.
+ *                   opt->fw_max does not limit this call.
+ *  goat_run_finish  final assignment on P (or grad f(P)), the score of the
+ *                   permutation, optional copy of P to P_out (ldp).
+ *  goat_run_free    releases the handle (host memory, events).
+ * All host-synchronous on the stream given to goat_run_begin.
+ */
+typedef struct goat_run goat_run;
+int  goat_run_begin(int n, const float* A, const float* B, int ld,
+                    const float* P0, const goat_options* opt,
+                    void* ws, size_t ws_bytes, void* stream, goat_run** run);
+int  goat_run_steps(goat_run* run, int k, goat_iter_record* hist_host,
+                    int hist_cap, int* done_out);
+int  goat_run_finish(goat_run* run, int32_t* perm_host, goat_stats* stats_host,
+                     float* P_out, int ldp);
+void goat_run_free(goat_run* run);
+
+/*
+ * Kernel timing hook (measurement only). which = 0: Sinkhorn row sweep;
+ * which = 1: gradient product (one matrix-core launch). With stride > 0,
+ * every stride-th such launch made by the calling thread is bracketed by
+ * HIP events on its stream (at most 8192 sampled launches are kept).
+ * goat_profile_read waits for the sampled launches, returns their summed
+ * duration (ms) and count, and clears the samples. stride = 0 disables.
+ */
+int goat_profile_enable(int which, int stride);
+int goat_profile_read(int which, double* ms_total, long long* count);
+
+/*
  * goat_lap_max - host linear assignment (Alg. 3 return line; Alg. 1 step 2
  * uses the same problem): perm maximising sum_i M[i*ld + perm[i]] over
  * permutations, for a host float64 matrix M. Jonker-Volgenant shortest
- * augmenting paths; ties go to the lower column index. O(n^3) worst case.
+ * augmenting paths from a greedy start; deterministic tie-breaking (lowest
+ * column index among equal path lengths). O(n^3) worst case.
  */
 int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
 

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libgoat.so")
 ARCH = os.environ.get("GOAT_OFFLOAD_ARCH", "gfx950")
 
 HIP_SOURCES = ["pack.hip", "gemm.hip", "sinkhorn.hip", "fw.hip"]
-CPP_SOURCES = ["api.cpp", "lap.cpp"]
+CPP_SOURCES = ["api.cpp", "solve.cpp", "profile.cpp", "lap.cpp"]
 
 # packed-fp32 instructions stay disabled for all device code
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

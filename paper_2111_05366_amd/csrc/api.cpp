@@ -54,7 +54,7 @@ Layout make_layout(int n, int prec, int sym) {
     return L;
 }
 
-static size_t small_bytes(const Layout& L) { return L.P; }
+size_t small_bytes(const Layout& L) { return L.P; }
 
 // ---------------------------------------------------------------- gradient
 
@@ -106,16 +106,7 @@ int grad_packed(const Layout& L, const GradOps& o, float* G, int ldg, int m_vali
                           m_valid, nullptr, nullptr, 0, s);
 }
 
-struct Ptrs {
-    char* base;
-    float* P; float* Q; float* GP; float* GQ;
-    void* A_hi; void* A_lo; void* B_hi; void* B_lo;
-    void* P_hi; void* P_lo; void* Y_hi; void* Y_lo;
-    SkState sk;
-    double* red; double* scal; float* fscal; float* g_prev; int32_t* perm_dev;
-};
-
-static Ptrs make_ptrs(const Layout& L, void* ws) {
+Ptrs make_ptrs(const Layout& L, void* ws) {
     Ptrs p{};
     char* b = static_cast<char*>(ws);
     const size_t pl = (size_t)L.np * L.np;
@@ -148,7 +139,7 @@ static Ptrs make_ptrs(const Layout& L, void* ws) {
     return p;
 }
 
-static int pack_graph(const Layout& L, const float* X, int ld, void* hi, void* lo, hipStream_t s) {
+int pack_graph(const Layout& L, const float* X, int ld, void* hi, void* lo, hipStream_t s) {
     const int mode = L.prec == GOAT_PREC_FP32 ? PACK_F32 : (L.prec == GOAT_PREC_BF16X2 ? PACK_BF16 : PACK_BF16_SPLIT);
     const size_t es = L.prec == GOAT_PREC_FP32 ? 4 : 2;
     const size_t pl = (size_t)L.np * L.np;
@@ -158,7 +149,7 @@ static int pack_graph(const Layout& L, const float* X, int ld, void* hi, void* l
                        lo ? static_cast<char*>(lo) + pl * es : nullptr, s);
 }
 
-static GradOps grad_ops(const Ptrs& p) {
+GradOps grad_ops(const Ptrs& p) {
     GradOps o;
     o.A_hi = p.A_hi; o.A_lo = p.A_lo; o.B_hi = p.B_hi; o.B_lo = p.B_lo;
     o.P_hi = p.P_hi; o.P_lo = p.P_lo; o.Y_hi = p.Y_hi; o.Y_lo = p.Y_lo;
@@ -243,8 +234,8 @@ int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float ep
         Gk = p.P;
         ldk = L.np;
     }
-    int rc = sk_prepare(n, Gk, ldk, eps_dev, eps_rel, init == GOAT_INIT_G ? g : nullptr, tol, p.sk, p.fscal,
-                        p.red, s);
+    int rc = sk_prepare(n, Gk, ldk, eps_dev, eps_rel, nullptr, init == GOAT_INIT_G ? g : nullptr, tol, p.sk,
+                        p.fscal, p.red, s);
     if (rc) return rc;
     for (int k = 0; k < max_iter; ++k) {
         rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, s);
@@ -281,171 +272,6 @@ int goat_score(int n, const float* A, const float* B, int ld, const int32_t* per
     if (ws_bytes < small_bytes(L)) { set_error("goat_score: workspace too small"); return GOAT_ENOMEM; }
     Ptrs p = make_ptrs(L, ws);
     return launch_score(n, A, B, ld, perm_dev, p.red, out_dev, static_cast<hipStream_t>(stream));
-}
-
-int goat_solve(int n, const float* A, const float* B, int ld, const float* P0, const goat_options* opt_in,
-               int32_t* perm_host, goat_stats* stats_host, goat_iter_record* hist_host, int hist_cap,
-               float* P_out, void* ws, size_t ws_bytes, void* stream) {
-    clear_error();
-    const auto wall0 = std::chrono::steady_clock::now();
-    goat_options opt;
-    if (opt_in) opt = *opt_in; else goat_default_options(&opt);
-    GOAT_CHECK_ARG(n >= 1, "n < 1");
-    GOAT_CHECK_ARG(A && B && perm_host && ws, "null pointer");
-    GOAT_CHECK_ARG(ld >= n, "leading dimension < n");
-    GOAT_CHECK_ARG(opt.prec >= GOAT_PREC_FP32 && opt.prec <= GOAT_PREC_BF16X3, "unknown precision");
-    GOAT_CHECK_ARG(std::isfinite(opt.eps_rel) && opt.eps_rel > 0.0f, "eps_rel must be > 0");
-    GOAT_CHECK_ARG(std::isfinite(opt.sk_tol) && opt.sk_tol >= 0.0f, "bad sk_tol");
-    GOAT_CHECK_ARG(opt.sk_max >= 1 && opt.fw_max >= 1, "sk_max and fw_max must be >= 1");
-    GOAT_CHECK_ARG(std::isfinite(opt.fw_tol) && opt.fw_tol >= 0.0f, "bad fw_tol");
-    GOAT_CHECK_ARG(hist_cap >= 0 && (hist_cap == 0 || hist_host), "bad history buffer");
-    const int check_every = opt.check_every > 0 ? opt.check_every : 16;
-    const Layout L = make_layout(n, opt.prec, opt.symmetric);
-    if (ws_bytes < L.total) { set_error("goat_solve: workspace too small"); return GOAT_ENOMEM; }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    Ptrs p = make_ptrs(L, ws);
-    const int np = L.np;
-    const bool bf = opt.prec != GOAT_PREC_FP32;
-    int rc;
-
-    struct HostBuf {
-        void* ptr = nullptr;
-        ~HostBuf() { if (ptr) (void)hipHostFree(ptr); }
-    } hb;
-    GOAT_HIP(hipHostMalloc(&hb.ptr, 256, hipHostMallocDefault));
-    char* hbuf = static_cast<char*>(hb.ptr);
-    int* hflag = reinterpret_cast<int*>(hbuf + 128);      // two polling slots
-    hipEvent_t ev_poll[2] = {nullptr, nullptr}, ev0 = nullptr, ev1 = nullptr;
-    struct EvGuard {
-        hipEvent_t* e; int k;
-        ~EvGuard() { for (int i = 0; i < k; ++i) if (e[i]) (void)hipEventDestroy(e[i]); }
-    };
-    hipEvent_t evs[4];
-    EvGuard eg{evs, 0};
-    for (int i = 0; i < 4; ++i) {
-        GOAT_HIP(hipEventCreate(&evs[i]));
-        eg.k = i + 1;
-    }
-    ev_poll[0] = evs[0]; ev_poll[1] = evs[1]; ev0 = evs[2]; ev1 = evs[3];
-
-    GOAT_HIP(hipMemsetAsync(ws, 0, L.total, s));
-    rc = pack_graph(L, A, ld, p.A_hi, p.A_lo, s);
-    if (!rc) rc = pack_graph(L, B, ld, p.B_hi, p.B_lo, s);
-    if (!rc) rc = P0 ? launch_copy_pad(n, P0, ld, p.P, np, np, s) : launch_fill_barycenter(n, np, p.P, s);
-    if (rc) return rc;
-    // grad f(P0): the P-side operand is P itself (fp32) or its bf16 split.
-    GradOps ops = grad_ops(p);
-    if (bf) {
-        rc = launch_split_bf16(n, np, p.P, np, static_cast<uint16_t*>(p.P_hi), static_cast<uint16_t*>(p.P_lo), s);
-        if (rc) return rc;
-    } else {
-        ops.P_hi = p.P;
-    }
-    GOAT_HIP(hipEventRecord(ev0, s));
-    rc = grad_packed(L, ops, p.GP, np, np, s);
-    if (!rc) rc = launch_absmax(n, p.GP, np, p.fscal + 16, p.fscal, s);
-    if (rc) return rc;
-
-    goat_stats st{};
-    double* ls_dev = p.scal;                                   // 8 doubles
-    int* it_dev = reinterpret_cast<int*>(p.scal + 8);
-    float* err_dev = reinterpret_cast<float*>(p.scal + 9);
-    float* eps_dev = err_dev + 1;
-    double last_ls[8] = {0};
-    int fw = 0;
-    for (fw = 1; fw <= opt.fw_max; ++fw) {
-        // LOT direction from G_P (Alg. 3 step 2)
-        const bool warm = opt.warm && fw > 1;
-        rc = sk_prepare(n, p.GP, np, nullptr, opt.eps_rel, warm ? p.g_prev : nullptr, opt.sk_tol, p.sk,
-                        p.fscal, p.red, s);
-        if (rc) return rc;
-        rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, s);
-        if (rc) return rc;
-        int k = 1, chunk = 0;
-        bool stop = false;
-        while (k < opt.sk_max && !stop) {
-            const int m = std::min(check_every, opt.sk_max - k);
-            for (int q = 0; q < m; ++q) {
-                rc = sk_iterate(n, np, p.GP, np, p.sk, 0, 1, s);
-                if (rc) return rc;
-            }
-            k += m;
-            const int slot = chunk & 1;
-            GOAT_HIP(hipMemcpyAsync(&hflag[slot], &p.sk.ctrl->done, sizeof(int), hipMemcpyDeviceToHost, s));
-            GOAT_HIP(hipEventRecord(ev_poll[slot], s));
-            if (chunk >= 1) {
-                GOAT_HIP(hipEventSynchronize(ev_poll[slot ^ 1]));
-                if (hflag[slot ^ 1]) stop = true;
-            }
-            ++chunk;
-        }
-        rc = sk_finalize(n, np, p.GP, np, p.sk, p.Q, np, bf ? static_cast<uint16_t*>(p.P_hi) : nullptr,
-                         bf ? static_cast<uint16_t*>(p.P_lo) : nullptr, nullptr, p.g_prev, it_dev, err_dev,
-                         eps_dev, p.red, s);
-        if (rc) return rc;
-        // grad f(Q) (linearity gives grad f at every point of the segment)
-        if (!bf) ops.P_hi = p.Q;
-        rc = grad_packed(L, ops, p.GQ, np, np, s);
-        if (rc) return rc;
-        // exact step (Alg. 3 step 3) and update (step 4)
-        rc = launch_traces(n, p.P, p.Q, p.GP, p.GQ, np, p.red, ls_dev, s);
-        if (!rc) rc = launch_fw_update(n, p.P, p.Q, p.GP, p.GQ, np, ls_dev, p.fscal + 16, p.fscal, s);
-        if (rc) return rc;
-        GOAT_HIP(hipMemcpyAsync(hbuf, p.scal, 80, hipMemcpyDeviceToHost, s));
-        GOAT_HIP(hipStreamSynchronize(s));
-        double ls[8];
-        std::memcpy(ls, hbuf, sizeof(ls));
-        int skit;
-        float skerr, eps;
-        std::memcpy(&skit, hbuf + 64, 4);
-        std::memcpy(&skerr, hbuf + 72, 4);
-        std::memcpy(&eps, hbuf + 76, 4);
-        std::memcpy(last_ls, ls, sizeof(ls));
-        st.sk_iters_total += skit;
-        if (skit >= opt.sk_max) st.sk_capped += 1;
-        if (fw - 1 < hist_cap) {
-            goat_iter_record& r = hist_host[fw - 1];
-            r.fP = ls[0]; r.fQ = ls[1]; r.c = ls[2]; r.a = ls[3]; r.b = ls[4]; r.t = ls[5]; r.dist2 = ls[6];
-            r.eps = eps; r.sk_err = skerr; r.sk_iters = skit; r.pad = 0;
-        }
-        const double t = ls[5];
-        const double delta = t * std::sqrt(ls[6]) / std::sqrt((double)n);
-        if ((t == 0.0 && opt.stop_on_stall) || (opt.fw_tol > 0.0f && delta < opt.fw_tol)) break;
-    }
-    st.fw_iters = std::min(fw, opt.fw_max);
-    GOAT_HIP(hipEventRecord(ev1, s));
-    GOAT_HIP(hipEventSynchronize(ev1));
-    float ms = 0.0f;
-    GOAT_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-    st.ms_loop = ms;
-    {
-        const double t = last_ls[5];
-        st.f_final = last_ls[0] + last_ls[4] * t + last_ls[3] * t * t;
-    }
-    if (P_out) GOAT_HIP(hipMemcpy2DAsync(P_out, (size_t)ld * 4, p.P, (size_t)np * 4, (size_t)n * 4, n,
-                                         hipMemcpyDeviceToDevice, s));
-    // final projection (Alg. 3 return line) on the host
-    std::vector<float> hm((size_t)n * n);
-    GOAT_HIP(hipMemcpy2DAsync(hm.data(), (size_t)n * 4, opt.proj ? p.GP : p.P, (size_t)np * 4, (size_t)n * 4, n,
-                              hipMemcpyDeviceToHost, s));
-    GOAT_HIP(hipStreamSynchronize(s));
-    const auto lap0 = std::chrono::steady_clock::now();
-    {
-        std::vector<double> md(hm.begin(), hm.end());
-        std::vector<float>().swap(hm);
-        rc = lap_max(n, md.data(), n, perm_host);
-        if (rc) return rc;
-    }
-    st.ms_lap = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - lap0).count();
-    GOAT_HIP(hipMemcpyAsync(p.perm_dev, perm_host, (size_t)n * 4, hipMemcpyHostToDevice, s));
-    rc = launch_score(n, A, B, ld, p.perm_dev, p.red, p.scal + 10, s);
-    if (rc) return rc;
-    GOAT_HIP(hipMemcpyAsync(hbuf, p.scal + 10, 8, hipMemcpyDeviceToHost, s));
-    GOAT_HIP(hipStreamSynchronize(s));
-    std::memcpy(&st.score, hbuf, 8);
-    st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
-    if (stats_host) *stats_host = st;
-    return GOAT_OK;
 }
 
 }  // extern "C"

@@ -118,9 +118,11 @@ int grad_packed(const Layout& L, const GradOps& ops, float* G, int ldg, int m_va
 struct SkState {
     float* u; float* unew; float* v; float* colpart; float* errpart; SkCtrl* ctrl;
 };
+// eps = *eps_dev if given, else eps_rel * *absmax_dev if given, else
+// eps_rel * max|G| computed here (into fscal[0]).
 int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_rel,
-               const float* g_init, float tol, SkState st, float* fscal, double* red,
-               hipStream_t s);
+               const float* absmax_dev, const float* g_init, float tol, SkState st, float* fscal,
+               double* red, hipStream_t s);
 int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check,
                hipStream_t s);
 // Form Q (fp32 and optional bf16 split), its row-marginal error, potentials
@@ -143,6 +145,25 @@ int launch_split_bf16(int n, int np, const float* src, int lds, uint16_t* hi, ui
                       hipStream_t s);
 int launch_score(int n, const float* A, const float* B, int ld, const int32_t* perm,
                  double* red, double* out, hipStream_t s);
+
+// Workspace pointers (api.cpp)
+struct Ptrs {
+    char* base;
+    float* P; float* Q; float* GP; float* GQ;
+    void* A_hi; void* A_lo; void* B_hi; void* B_lo;
+    void* P_hi; void* P_lo; void* Y_hi; void* Y_lo;
+    SkState sk;
+    double* red; double* scal; float* fscal; float* g_prev; int32_t* perm_dev;
+};
+size_t small_bytes(const Layout& L);
+Ptrs make_ptrs(const Layout& L, void* ws);
+int pack_graph(const Layout& L, const float* X, int ld, void* hi, void* lo, hipStream_t s);
+GradOps grad_ops(const Ptrs& p);
+
+// Sampled per-launch timing (profile.cpp): which = 0 Sinkhorn row sweep,
+// 1 gradient product
+void prof_begin(int which, hipStream_t s);
+void prof_end(int which, hipStream_t s);
 
 // Host linear assignment (lap.cpp)
 int lap_max(int n, const double* M, int ld, int32_t* perm);

@@ -268,6 +268,7 @@ int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz, const Gem
     p.tiles_m = M / BM;
     p.tiles_n = N / BN;
     dim3 grid(p.tiles_m * p.tiles_n), block(256);
+    prof_begin(1, s);
     if (is_bf16) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_F32>, grid, block, 0, s, p);
         else hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_BF16_SPLIT>, grid, block, 0, s, p);
@@ -275,6 +276,7 @@ int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz, const Gem
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_f32_kernel<OUT_F32>, grid, block, 0, s, p);
         else hipLaunchKernelGGL(gemm_nt_f32_kernel<OUT_BF16_SPLIT>, grid, block, 0, s, p);
     }
+    prof_end(1, s);
     GOAT_HIP(hipGetLastError());
     return GOAT_OK;
 }

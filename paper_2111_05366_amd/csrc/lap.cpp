@@ -1,13 +1,13 @@
 // Host linear assignment for the final projection of Alg. 3 (and the
 // direction step of Alg. 1): maximise sum_i M[i][perm[i]] over permutations.
 //
-// Shortest augmenting paths with row/column duals (the Jonker-Volgenant
-// family): costs c = -M; columns are first reduced to their minimum and
-// each column's argmin row is matched when still free (complementary
-// slackness holds for these pairs); every remaining free row is then matched
-// by one Dijkstra search over reduced costs c_ij - u_i - v_j >= 0 followed by
-// a dual update and an augmentation along the found path. Among columns of
-// equal tentative distance the lowest index is scanned first.
+// Successive shortest augmenting paths (the Hungarian / Jonker-Volgenant
+// family) on costs c = -M with row and column duals u, v: a greedy start
+// matches each row to its cheapest column when that column is free; every
+// row still free is matched by one Dijkstra search over reduced costs
+// c_ij - u_i - v_j, a dual update and an augmentation along the found path.
+// Among columns of equal tentative distance the lowest index is scanned
+// first, so results are deterministic.
 #include <cmath>
 #include <limits>
 #include <vector>
@@ -36,18 +36,19 @@ int lap_max(int n, const double* M, int ld, int32_t* perm) {
     std::vector<int> seen_rows;
     seen_rows.reserve(n);
 
-    // Column reduction and free argmin matches.
-    for (int j = 0; j < n; ++j) {
-        int imin = 0;
-        double cmin = cost(0, j);
-        for (int i = 1; i < n; ++i) {
-            const double c = cost(i, j);
-            if (c < cmin) { cmin = c; imin = i; }
-        }
-        v[j] = cmin;
-        if (col_of[imin] < 0) {
-            col_of[imin] = j;
-            row_of[j] = imin;
+    // Greedy start: with column duals v = 0 each row may take its cheapest
+    // column (lowest index on ties) if that column is still free; u_i is then
+    // the row minimum, so reduced costs c_ij - u_i - v_j are >= 0 and vanish
+    // on every matched pair.
+    for (int i = 0; i < n; ++i) {
+        const double* row = M + (size_t)i * ld;
+        int jb = 0;
+        for (int j = 1; j < n; ++j)
+            if (row[j] > row[jb]) jb = j;
+        if (row_of[jb] < 0) {
+            row_of[jb] = i;
+            col_of[i] = jb;
+            u[i] = -row[jb];
         }
     }
 

@@ -371,11 +371,11 @@ SkArgs make_args(int n, int np, const float* G, int ldg, const SkState& st, cons
 }  // namespace
 
 int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_rel,
-               const float* g_init, float tol, SkState st, float* fscal, double* red,
-               hipStream_t s) {
+               const float* absmax_dev, const float* g_init, float tol, SkState st, float* fscal,
+               double* red, hipStream_t s) {
     (void)red;
-    const float* absmax = nullptr;
-    if (!eps_dev) {
+    const float* absmax = absmax_dev;
+    if (!eps_dev && !absmax) {
         int rc = launch_absmax(n, G, ldg, fscal + 16, fscal, s);
         if (rc) return rc;
         absmax = fscal;
@@ -391,9 +391,11 @@ int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, in
     const Geometry g = geometry(n);
     const SkArgs a = make_args(n, np, G, ldg, st, g);
     int rc;
+    prof_begin(0, s);
     if (g.T == 256) rc = first ? launch_row_T<256, true>(g, a, s) : launch_row_T<256, false>(g, a, s);
     else if (g.T == 512) rc = first ? launch_row_T<512, true>(g, a, s) : launch_row_T<512, false>(g, a, s);
     else rc = first ? launch_row_T<1024, true>(g, a, s) : launch_row_T<1024, false>(g, a, s);
+    prof_end(0, s);
     if (rc) return rc;
     hipLaunchKernelGGL(sk_merge_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a, g.W, check);
     GOAT_HIP(hipGetLastError());

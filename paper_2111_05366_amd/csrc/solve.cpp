@@ -1,0 +1,278 @@
+// GOAT end to end (Alg. 3): initialisation, Frank-Wolfe iterations on the
+// device and the final host assignment, exposed as goat_solve and as the
+// begin / steps / finish triple used to time a fixed number of iterations.
+//
+// Per iteration, on the caller's stream:
+//   1. eps = eps_rel * max|G_P| (the max comes from the previous update)
+//   2. LOT: Sinkhorn sweeps on G_P, polled every check_every iterations for
+//      the device-side convergence flag; then Q (and its bf16 split)
+//   3. G_Q = grad f(Q); by linearity grad f(P + t(Q-P)) = G_P + t(G_Q - G_P),
+//      so one gradient product per iteration suffices
+//   4. float64 traces -> exact step t (Alg. 3 step 3)
+//   5. P <- P + t(Q - P), G_P <- G_P + t(G_Q - G_P), next max|G_P|
+// The only host synchronisation per iteration reads back the step scalars.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+namespace goat {
+
+struct Run {
+    Layout L;
+    Ptrs p;
+    GradOps ops;
+    goat_options opt;
+    hipStream_t s = nullptr;
+    const float* A = nullptr;
+    const float* B = nullptr;
+    int ld = 0;
+    int fw = 0;                 // iterations done
+    bool stalled = false;
+    double last_ls[8] = {0};
+    goat_stats st{};
+    void* hbuf = nullptr;       // pinned host scratch
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::chrono::steady_clock::time_point wall0;
+    double loop_ms = 0.0;
+
+    ~Run() {
+        if (hbuf) (void)hipHostFree(hbuf);
+        for (hipEvent_t e : {ev_poll[0], ev_poll[1], ev0, ev1})
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+static int run_sinkhorn(Run& r) {
+    const int n = r.L.n, np = r.L.np;
+    const bool bf = r.opt.prec != GOAT_PREC_FP32;
+    Ptrs& p = r.p;
+    const bool warm = r.opt.warm && r.fw > 0;
+    // eps from the max|G_P| that the previous update (or the start) left in fscal[0]
+    int rc = sk_prepare(n, p.GP, np, nullptr, r.opt.eps_rel, p.fscal, warm ? p.g_prev : nullptr, r.opt.sk_tol,
+                        p.sk, p.fscal, p.red, r.s);
+    if (rc) return rc;
+    rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, r.s);
+    if (rc) return rc;
+    const int check_every = r.opt.check_every > 0 ? r.opt.check_every : 16;
+    int* hflag = reinterpret_cast<int*>(static_cast<char*>(r.hbuf) + 128);
+    int k = 1, chunk = 0;
+    bool stop = false;
+    while (k < r.opt.sk_max && !stop) {
+        const int m = std::min(check_every, r.opt.sk_max - k);
+        for (int q = 0; q < m; ++q) {
+            rc = sk_iterate(n, np, p.GP, np, p.sk, 0, 1, r.s);
+            if (rc) return rc;
+        }
+        k += m;
+        const int slot = chunk & 1;
+        GOAT_HIP(hipMemcpyAsync(&hflag[slot], &p.sk.ctrl->done, sizeof(int), hipMemcpyDeviceToHost, r.s));
+        GOAT_HIP(hipEventRecord(r.ev_poll[slot], r.s));
+        if (chunk >= 1) {
+            GOAT_HIP(hipEventSynchronize(r.ev_poll[slot ^ 1]));
+            if (hflag[slot ^ 1]) stop = true;
+        }
+        ++chunk;
+    }
+    int* it_dev = reinterpret_cast<int*>(p.scal + 8);
+    float* err_dev = reinterpret_cast<float*>(p.scal + 9);
+    return sk_finalize(n, np, p.GP, np, p.sk, p.Q, np, bf ? static_cast<uint16_t*>(p.P_hi) : nullptr,
+                       bf ? static_cast<uint16_t*>(p.P_lo) : nullptr, nullptr, p.g_prev, it_dev, err_dev,
+                       err_dev + 1, p.red, r.s);
+}
+
+static int run_step(Run& r, goat_iter_record* rec) {
+    const int n = r.L.n, np = r.L.np;
+    const bool bf = r.opt.prec != GOAT_PREC_FP32;
+    Ptrs& p = r.p;
+    int rc = run_sinkhorn(r);
+    if (rc) return rc;
+    if (!bf) r.ops.P_hi = p.Q;
+    rc = grad_packed(r.L, r.ops, p.GQ, np, np, r.s);
+    if (rc) return rc;
+    rc = launch_traces(n, p.P, p.Q, p.GP, p.GQ, np, p.red, p.scal, r.s);
+    if (!rc) rc = launch_fw_update(n, p.P, p.Q, p.GP, p.GQ, np, p.scal, p.fscal + 16, p.fscal, r.s);
+    if (rc) return rc;
+    GOAT_HIP(hipMemcpyAsync(r.hbuf, p.scal, 80, hipMemcpyDeviceToHost, r.s));
+    GOAT_HIP(hipStreamSynchronize(r.s));
+    const char* hb = static_cast<const char*>(r.hbuf);
+    double ls[8];
+    std::memcpy(ls, hb, sizeof(ls));
+    int skit;
+    float skerr, eps;
+    std::memcpy(&skit, hb + 64, 4);
+    std::memcpy(&skerr, hb + 72, 4);
+    std::memcpy(&eps, hb + 76, 4);
+    std::memcpy(r.last_ls, ls, sizeof(ls));
+    r.st.sk_iters_total += skit;
+    if (skit >= r.opt.sk_max) r.st.sk_capped += 1;
+    if (rec) {
+        rec->fP = ls[0]; rec->fQ = ls[1]; rec->c = ls[2]; rec->a = ls[3]; rec->b = ls[4];
+        rec->t = ls[5]; rec->dist2 = ls[6]; rec->eps = eps; rec->sk_err = skerr; rec->sk_iters = skit;
+        rec->pad = 0;
+    }
+    r.fw += 1;
+    const double t = ls[5];
+    const double delta = t * std::sqrt(ls[6]) / std::sqrt((double)n);
+    if ((t == 0.0 && r.opt.stop_on_stall) || (r.opt.fw_tol > 0.0f && delta < r.opt.fw_tol)) r.stalled = true;
+    return GOAT_OK;
+}
+
+}  // namespace goat
+
+using namespace goat;
+
+struct goat_run {
+    Run r;
+};
+
+extern "C" {
+
+int goat_run_begin(int n, const float* A, const float* B, int ld, const float* P0, const goat_options* opt_in,
+                   void* ws, size_t ws_bytes, void* stream, goat_run** run_out) {
+    clear_error();
+    GOAT_CHECK_ARG(run_out, "null run pointer");
+    *run_out = nullptr;
+    goat_options opt;
+    if (opt_in) opt = *opt_in; else goat_default_options(&opt);
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(A && B && ws, "null pointer");
+    GOAT_CHECK_ARG(ld >= n, "leading dimension < n");
+    GOAT_CHECK_ARG(opt.prec >= GOAT_PREC_FP32 && opt.prec <= GOAT_PREC_BF16X3, "unknown precision");
+    GOAT_CHECK_ARG(std::isfinite(opt.eps_rel) && opt.eps_rel > 0.0f, "eps_rel must be > 0");
+    GOAT_CHECK_ARG(std::isfinite(opt.sk_tol) && opt.sk_tol >= 0.0f, "bad sk_tol");
+    GOAT_CHECK_ARG(opt.sk_max >= 1 && opt.fw_max >= 1, "sk_max and fw_max must be >= 1");
+    GOAT_CHECK_ARG(std::isfinite(opt.fw_tol) && opt.fw_tol >= 0.0f, "bad fw_tol");
+    const Layout L = make_layout(n, opt.prec, opt.symmetric);
+    if (ws_bytes < L.total) { set_error("goat_run_begin: workspace too small"); return GOAT_ENOMEM; }
+
+    goat_run* h = new (std::nothrow) goat_run();
+    if (!h) { set_error("goat_run_begin: out of host memory"); return GOAT_ENOMEM; }
+    Run& r = h->r;
+    r.wall0 = std::chrono::steady_clock::now();
+    r.L = L;
+    r.p = make_ptrs(L, ws);
+    r.opt = opt;
+    r.s = static_cast<hipStream_t>(stream);
+    r.A = A;
+    r.B = B;
+    r.ld = ld;
+    auto fail = [&](int rc) { delete h; return rc; };
+#define RUN_HIP(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));                \
+            return fail(GOAT_EHIP);                                                      \
+        }                                                                                \
+    } while (0)
+    RUN_HIP(hipHostMalloc(&r.hbuf, 256, hipHostMallocDefault));
+    for (hipEvent_t* e : {&r.ev_poll[0], &r.ev_poll[1], &r.ev0, &r.ev1}) RUN_HIP(hipEventCreate(e));
+    Ptrs& p = r.p;
+    const int np = L.np;
+    RUN_HIP(hipMemsetAsync(ws, 0, L.total, r.s));
+    int rc = pack_graph(L, A, ld, p.A_hi, p.A_lo, r.s);
+    if (!rc) rc = pack_graph(L, B, ld, p.B_hi, p.B_lo, r.s);
+    if (!rc) rc = P0 ? launch_copy_pad(n, P0, ld, p.P, np, np, r.s) : launch_fill_barycenter(n, np, p.P, r.s);
+    if (rc) return fail(rc);
+    r.ops = grad_ops(p);
+    if (opt.prec != GOAT_PREC_FP32) {
+        rc = launch_split_bf16(n, np, p.P, np, static_cast<uint16_t*>(p.P_hi), static_cast<uint16_t*>(p.P_lo), r.s);
+        if (rc) return fail(rc);
+    } else {
+        r.ops.P_hi = p.P;
+    }
+    rc = grad_packed(L, r.ops, p.GP, np, np, r.s);
+    if (!rc) rc = launch_absmax(n, p.GP, np, p.fscal + 16, p.fscal, r.s);
+    if (rc) return fail(rc);
+    RUN_HIP(hipStreamSynchronize(r.s));
+#undef RUN_HIP
+    *run_out = h;
+    return GOAT_OK;
+}
+
+int goat_run_steps(goat_run* h, int k, goat_iter_record* hist_host, int hist_cap, int* done_out) {
+    clear_error();
+    GOAT_CHECK_ARG(h, "null run");
+    GOAT_CHECK_ARG(k >= 0, "k < 0");
+    GOAT_CHECK_ARG(hist_cap >= 0 && (hist_cap == 0 || hist_host), "bad history buffer");
+    Run& r = h->r;
+    int done = 0;
+    GOAT_HIP(hipEventRecord(r.ev0, r.s));
+    while (done < k && !r.stalled) {
+        int rc = run_step(r, done < hist_cap ? &hist_host[done] : nullptr);
+        if (rc) return rc;
+        ++done;
+    }
+    GOAT_HIP(hipEventRecord(r.ev1, r.s));
+    GOAT_HIP(hipEventSynchronize(r.ev1));
+    float ms = 0.0f;
+    GOAT_HIP(hipEventElapsedTime(&ms, r.ev0, r.ev1));
+    r.loop_ms += ms;
+    if (done_out) *done_out = done;
+    return GOAT_OK;
+}
+
+int goat_run_finish(goat_run* h, int32_t* perm_host, goat_stats* stats_host, float* P_out, int ldp) {
+    clear_error();
+    GOAT_CHECK_ARG(h && perm_host, "null pointer");
+    Run& r = h->r;
+    const int n = r.L.n, np = r.L.np;
+    GOAT_CHECK_ARG(!P_out || ldp >= n, "leading dimension < n");
+    Ptrs& p = r.p;
+    r.st.fw_iters = r.fw;
+    r.st.ms_loop = r.loop_ms;
+    const double t = r.last_ls[5];
+    r.st.f_final = r.fw ? r.last_ls[0] + r.last_ls[4] * t + r.last_ls[3] * t * t : 0.0;
+    if (P_out)
+        GOAT_HIP(hipMemcpy2DAsync(P_out, (size_t)ldp * 4, p.P, (size_t)np * 4, (size_t)n * 4, n,
+                                  hipMemcpyDeviceToDevice, r.s));
+    // final projection (Alg. 3 return line) on the host
+    std::vector<float> hm((size_t)n * n);
+    GOAT_HIP(hipMemcpy2DAsync(hm.data(), (size_t)n * 4, r.opt.proj ? p.GP : p.P, (size_t)np * 4, (size_t)n * 4, n,
+                              hipMemcpyDeviceToHost, r.s));
+    GOAT_HIP(hipStreamSynchronize(r.s));
+    if (r.fw == 0) {
+        // no iteration ran: f(P0) = <P0, grad f(P0)>/2 is not tracked; report 0
+        r.st.f_final = 0.0;
+    }
+    const auto lap0 = std::chrono::steady_clock::now();
+    {
+        std::vector<double> md(hm.begin(), hm.end());
+        std::vector<float>().swap(hm);
+        int rc = lap_max(n, md.data(), n, perm_host);
+        if (rc) return rc;
+    }
+    r.st.ms_lap = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - lap0).count();
+    GOAT_HIP(hipMemcpyAsync(p.perm_dev, perm_host, (size_t)n * 4, hipMemcpyHostToDevice, r.s));
+    int rc = launch_score(n, r.A, r.B, r.ld, p.perm_dev, p.red, p.scal + 10, r.s);
+    if (rc) return rc;
+    GOAT_HIP(hipMemcpyAsync(r.hbuf, p.scal + 10, 8, hipMemcpyDeviceToHost, r.s));
+    GOAT_HIP(hipStreamSynchronize(r.s));
+    std::memcpy(&r.st.score, r.hbuf, 8);
+    r.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - r.wall0).count();
+    if (stats_host) *stats_host = r.st;
+    return GOAT_OK;
+}
+
+void goat_run_free(goat_run* h) { delete h; }
+
+int goat_solve(int n, const float* A, const float* B, int ld, const float* P0, const goat_options* opt,
+               int32_t* perm_host, goat_stats* stats_host, goat_iter_record* hist_host, int hist_cap,
+               float* P_out, void* ws, size_t ws_bytes, void* stream) {
+    goat_options o;
+    if (opt) o = *opt; else goat_default_options(&o);
+    GOAT_CHECK_ARG(perm_host, "null pointer");
+    goat_run* h = nullptr;
+    int rc = goat_run_begin(n, A, B, ld, P0, &o, ws, ws_bytes, stream, &h);
+    if (rc) return rc;
+    rc = goat_run_steps(h, o.fw_max, hist_host, hist_cap, nullptr);
+    if (!rc) rc = goat_run_finish(h, perm_host, stats_host, P_out, ld);
+    goat_run_free(h);
+    return rc;
+}
+
+}  // extern "C"

@@ -81,6 +81,19 @@ def lib():
     L.goat_lap_max.argtypes = [_I, _VP, _I, _VP]
     L.goat_score.restype = _I
     L.goat_score.argtypes = [_I, _VP, _VP, _I, _VP, _VP, _VP, _SZ, _VP]
+    L.goat_run_begin.restype = _I
+    L.goat_run_begin.argtypes = [_I, _VP, _VP, _I, _VP, ctypes.POINTER(Options), _VP, _SZ, _VP,
+                                 ctypes.POINTER(ctypes.c_void_p)]
+    L.goat_run_steps.restype = _I
+    L.goat_run_steps.argtypes = [_VP, _I, ctypes.POINTER(IterRecord), _I, ctypes.POINTER(ctypes.c_int)]
+    L.goat_run_finish.restype = _I
+    L.goat_run_finish.argtypes = [_VP, _VP, ctypes.POINTER(Stats), _VP, _I]
+    L.goat_run_free.restype = None
+    L.goat_run_free.argtypes = [_VP]
+    L.goat_profile_enable.restype = _I
+    L.goat_profile_enable.argtypes = [_I, _I]
+    L.goat_profile_read.restype = _I
+    L.goat_profile_read.argtypes = [_I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
     _lib = L
     return L
 
@@ -276,3 +289,75 @@ def solve(A, B, P0=None, return_P: bool = False, **opts) -> SolveResult:
         h.append(dict(fP=r.fP, fQ=r.fQ, c=r.c, a=r.a, b=r.b, t=r.t, dist2=r.dist2, eps=r.eps,
                       sk_err=r.sk_err, sk_iters=r.sk_iters))
     return SolveResult(perm.astype(np.int64), st, h, Pout)
+
+
+def _records(hist, k):
+    out = []
+    for i in range(k):
+        r = hist[i]
+        out.append(dict(fP=r.fP, fQ=r.fQ, c=r.c, a=r.a, b=r.b, t=r.t, dist2=r.dist2, eps=r.eps,
+                        sk_err=r.sk_err, sk_iters=r.sk_iters))
+    return out
+
+
+class Run:
+    """Stepwise GOAT (goat_run_begin / steps / finish). A, B and the
+    workspace stay referenced for the run's lifetime."""
+
+    def __init__(self, A, B, P0=None, **opts):
+        torch = _torch()
+        _mat(A, "A"); _mat(B, "B")
+        self.n = A.shape[0]
+        self.A, self.B, self.P0 = A, B, P0
+        self.opt = default_options(**opts)
+        prec = {v: k for k, v in PREC.items()}[self.opt.prec]
+        self.ws = torch.empty(workspace_size(self.n, prec, bool(self.opt.symmetric)), dtype=torch.uint8,
+                              device=A.device)
+        h = ctypes.c_void_p()
+        _check(lib().goat_run_begin(self.n, _ptr(A), _ptr(B), A.stride(0), _ptr(P0), ctypes.byref(self.opt),
+                                    _ptr(self.ws), self.ws.numel(), _stream(), ctypes.byref(h)))
+        self.h = h
+        self.history = []
+
+    def steps(self, k: int) -> int:
+        hist = (IterRecord * max(k, 1))()
+        done = ctypes.c_int(0)
+        _check(lib().goat_run_steps(self.h, k, hist, k, ctypes.byref(done)))
+        self.history += _records(hist, done.value)
+        return done.value
+
+    def finish(self, return_P: bool = False):
+        torch = _torch()
+        perm = np.empty(self.n, dtype=np.int32)
+        st = Stats()
+        Pout = torch.empty((self.n, self.n), dtype=torch.float32, device=self.A.device) if return_P else None
+        _check(lib().goat_run_finish(self.h, perm.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st), _ptr(Pout),
+                                     self.n))
+        return SolveResult(perm.astype(np.int64), st, list(self.history), Pout)
+
+    def close(self):
+        if self.h:
+            lib().goat_run_free(self.h)
+            self.h = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+PROF_SINKHORN_ROW, PROF_GEMM = 0, 1
+
+
+def profile_enable(which: int, stride: int):
+    _check(lib().goat_profile_enable(int(which), int(stride)))
+
+
+def profile_read(which: int):
+    """(summed ms, number of sampled launches) since the last read."""
+    ms = ctypes.c_double(0.0)
+    cnt = ctypes.c_longlong(0)
+    _check(lib().goat_profile_read(int(which), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

@@ -228,3 +228,24 @@ def test_solve_general_pair_matches_oracle_first_step(G):
     ref = O.goat(A, B, opt=O.GoatOptions(sk_max=300, fw_max=2), record=True)
     assert r.history[0]["fP"] == pytest.approx(ref.history[0]["fP"], rel=1e-6)
     assert r.history[0]["t"] == pytest.approx(ref.history[0]["t"], abs=1e-4)
+
+
+def test_run_steps_equal_solve(G):
+    """begin / steps(3) / steps(2) / finish reproduces goat_solve with fw_max=5."""
+    g = I.rho_er_pair(200, 0.06, 0.9, 31)
+    A, B = dev(g.A), dev(g.B)
+    ref = G.solve(A, B, prec="bf16x2", sk_max=200, fw_max=5, stop_on_stall=0)
+    run = G.Run(A, B, prec="bf16x2", sk_max=200, fw_max=5, stop_on_stall=0)
+    assert run.steps(3) == 3 and run.steps(2) == 2
+    G.profile_enable(G.PROF_SINKHORN_ROW, 1)
+    res = run.finish()
+    run.close()
+    assert [h["t"] for h in res.history] == [h["t"] for h in ref.history]
+    assert [h["sk_iters"] for h in res.history] == [h["sk_iters"] for h in ref.history]
+    assert list(res.perm) == list(ref.perm)
+    # profiling hook counts sampled row sweeps
+    out = G.sinkhorn(dev(_sk_problem(100, 2)), max_iter=10, tol=0.0)
+    ms, cnt = G.profile_read(G.PROF_SINKHORN_ROW)
+    G.profile_enable(G.PROF_SINKHORN_ROW, 0)
+    assert cnt == 10 and ms > 0.0
+    assert int(out.iters.item()) == 10
