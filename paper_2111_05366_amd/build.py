@@ -15,6 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgoat.so")
 ARCH = os.environ.get("GOAT_OFFLOAD_ARCH", "gfx950")
+OMP_LIBDIR = "/opt/rocm/lib/llvm/lib"   # host OpenMP runtime of the ROCm clang
 
 HIP_SOURCES = ["pack.hip", "gemm.hip", "sinkhorn.hip", "fw.hip"]
 CPP_SOURCES = ["api.cpp", "solve.cpp", "profile.cpp", "lap.cpp"]
@@ -54,12 +55,13 @@ def build(verbose: bool = False) -> str:
             objs.append(obj)
         for src in CPP_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            cmd = [cc, *COMMON, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-x", "c++", "-c",
+            cmd = [cc, *COMMON, "-fopenmp", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-x", "c++", "-c",
                    os.path.join(CSRC, src), "-o", obj]
             _run(cmd)
             objs.append(obj)
         tmp_lib = os.path.join(tmp, "libgoat.so")
-        _run([cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp_lib])
+        _run([cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-fopenmp",
+              "-Wl,-rpath," + OMP_LIBDIR, "-o", tmp_lib])
         shutil.copyfile(tmp_lib, LIB + ".tmp")
         os.replace(LIB + ".tmp", LIB)
     return LIB

@@ -238,7 +238,7 @@ int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float ep
                         p.fscal, p.red, s);
     if (rc) return rc;
     for (int k = 0; k < max_iter; ++k) {
-        rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, s);
+        rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, k, s);
         if (rc) return rc;
     }
     return sk_finalize(n, L.np, Gk, ldk, p.sk, Q, ldq, nullptr, nullptr, f, g, iters_dev, err_dev, eps_out,

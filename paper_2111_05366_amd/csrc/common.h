@@ -36,7 +36,7 @@ void clear_error();
 // ---------------------------------------------------------------- sizes
 
 constexpr int kPad = 256;          // internal matrices are np x np, np = ceil(n/kPad)*kPad
-constexpr int kSkWG = 512;         // max row strips (workgroups) of a Sinkhorn sweep
+constexpr int kSkWG = 1024;        // max row strips (workgroups) of a Sinkhorn sweep
 constexpr int kRedWG = 1024;       // max workgroups of a float64 reduction pass
 
 inline int pad_n(int n) { return (n + kPad - 1) / kPad * kPad; }
@@ -123,7 +123,9 @@ struct SkState {
 int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_rel,
                const float* absmax_dev, const float* g_init, float tol, SkState st, float* fscal,
                double* red, hipStream_t s);
-int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check,
+// One Sinkhorn iteration (row sweep + column update); iter is its index in
+// the solve (row-walk direction alternates with its parity).
+int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check, int iter,
                hipStream_t s);
 // Form Q (fp32 and optional bf16 split), its row-marginal error, potentials
 // in natural units, and (when P != NULL) the traces <Q,G>, <P,G>, ||Q-P||^2.

@@ -100,53 +100,67 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmParams p) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
 
-    uint4 ra[4], rb[4];
-    auto gload = [&](int t) {
-        const int seg = t / ktiles, kt = t - seg * ktiles;
-        const uint16_t* X = static_cast<const uint16_t*>(p.X[seg]) + (size_t)m0 * p.ldx + kt * BK16;
-        const uint16_t* Z = static_cast<const uint16_t*>(p.Z[seg]) + (size_t)n0 * p.ldz + kt * BK16;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int c = tid + 256 * i, row = c >> 3, kc = c & 7;
-            ra[i] = *reinterpret_cast<const uint4*>(X + (size_t)row * p.ldx + kc * 8);
-            rb[i] = *reinterpret_cast<const uint4*>(Z + (size_t)row * p.ldz + kc * 8);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int c = tid + 256 * i, row = c >> 3, kc = c & 7;
-            *reinterpret_cast<uint4*>(&sA[buf][row * LD16 + kc * 8]) = ra[i];
-            *reinterpret_cast<uint4*>(&sB[buf][row * LD16 + kc * 8]) = rb[i];
-        }
-    };
+    // global -> register staging of one k-tile: 128 rows x 64 bf16 per
+    // operand, four 16-byte chunks per thread (row = c / 8, chunk = c % 8)
+    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+    const int lrow = tid >> 3, lkc = (tid & 7) * 8;
+#define GOAT_GLOAD16(T)                                                                          \
+    do {                                                                                          \
+        const int seg_ = (T) / ktiles, kt_ = (T) - seg_ * ktiles;                                 \
+        const uint16_t* X_ = static_cast<const uint16_t*>(p.X[seg_]) +                            \
+                             (size_t)(m0 + lrow) * p.ldx + kt_ * BK16 + lkc;                     \
+        const uint16_t* Z_ = static_cast<const uint16_t*>(p.Z[seg_]) +                            \
+                             (size_t)(n0 + lrow) * p.ldz + kt_ * BK16 + lkc;                     \
+        const size_t sx_ = (size_t)32 * p.ldx, sz_ = (size_t)32 * p.ldz;                          \
+        ra0 = *reinterpret_cast<const uint4*>(X_);                                                \
+        ra1 = *reinterpret_cast<const uint4*>(X_ + sx_);                                          \
+        ra2 = *reinterpret_cast<const uint4*>(X_ + 2 * sx_);                                      \
+        ra3 = *reinterpret_cast<const uint4*>(X_ + 3 * sx_);                                      \
+        rb0 = *reinterpret_cast<const uint4*>(Z_);                                                \
+        rb1 = *reinterpret_cast<const uint4*>(Z_ + sz_);                                          \
+        rb2 = *reinterpret_cast<const uint4*>(Z_ + 2 * sz_);                                      \
+        rb3 = *reinterpret_cast<const uint4*>(Z_ + 3 * sz_);                                      \
+    } while (0)
+#define GOAT_SSTORE16(BUF)                                                                        \
+    do {                                                                                          \
+        uint16_t* a_ = &sA[BUF][lrow * LD16 + lkc];                                               \
+        uint16_t* b_ = &sB[BUF][lrow * LD16 + lkc];                                               \
+        *reinterpret_cast<uint4*>(a_) = ra0;                                                      \
+        *reinterpret_cast<uint4*>(a_ + 32 * LD16) = ra1;                                          \
+        *reinterpret_cast<uint4*>(a_ + 64 * LD16) = ra2;                                          \
+        *reinterpret_cast<uint4*>(a_ + 96 * LD16) = ra3;                                          \
+        *reinterpret_cast<uint4*>(b_) = rb0;                                                      \
+        *reinterpret_cast<uint4*>(b_ + 32 * LD16) = rb1;                                          \
+        *reinterpret_cast<uint4*>(b_ + 64 * LD16) = rb2;                                          \
+        *reinterpret_cast<uint4*>(b_ + 96 * LD16) = rb3;                                          \
+    } while (0)
 
-    gload(0);
-    sstore(0);
+    GOAT_GLOAD16(0);
+    GOAT_SSTORE16(0);
     __syncthreads();
+    const int arow = (wm * 64 + (lane & 31)) * LD16 + (lane >> 5) * 8;
+    const int brow = (wn * 64 + (lane & 31)) * LD16 + (lane >> 5) * 8;
     for (int t = 0; t < total; ++t) {
         const int buf = t & 1;
-        if (t + 1 < total) gload(t + 1);
+        if (t + 1 < total) GOAT_GLOAD16(t + 1);
+        const uint16_t* sa = sA[buf];
+        const uint16_t* sb = sB[buf];
 #pragma unroll
         for (int ks = 0; ks < BK16 / 16; ++ks) {
-            bf16x8 a[2], b[2];
-#pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
-                a[mi] = *reinterpret_cast<const bf16x8*>(
-                    &sA[buf][(wm * 64 + mi * 32 + (lane & 31)) * LD16 + ks * 16 + (lane >> 5) * 8]);
-#pragma unroll
-            for (int ni = 0; ni < 2; ++ni)
-                b[ni] = *reinterpret_cast<const bf16x8*>(
-                    &sB[buf][(wn * 64 + ni * 32 + (lane & 31)) * LD16 + ks * 16 + (lane >> 5) * 8]);
-#pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < 2; ++ni)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(sa + arow + ks * 16);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(sa + arow + 32 * LD16 + ks * 16);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(sb + brow + ks * 16);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(sb + brow + 32 * LD16 + ks * 16);
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
         }
-        if (t + 1 < total) sstore(buf ^ 1);
+        if (t + 1 < total) GOAT_SSTORE16(buf ^ 1);
         __syncthreads();
     }
+#undef GOAT_GLOAD16
+#undef GOAT_SSTORE16
     store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
@@ -178,64 +192,72 @@ __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmParams p) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
 
-    float4 ra[2], rb[2];
-    auto gload = [&](int t) {
-        const int seg = t / ktiles, kt = t - seg * ktiles;
-        const float* X = static_cast<const float*>(p.X[seg]) + (size_t)m0 * p.ldx + kt * BK32;
-        const float* Z = static_cast<const float*>(p.Z[seg]) + (size_t)n0 * p.ldz + kt * BK32;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int c = tid + 256 * i, row = c >> 2, kc = c & 3;
-            ra[i] = *reinterpret_cast<const float4*>(X + (size_t)row * p.ldx + kc * 4);
-            rb[i] = *reinterpret_cast<const float4*>(Z + (size_t)row * p.ldz + kc * 4);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int c = tid + 256 * i, row = c >> 2, kc = c & 3;
-            float* a = &sA[buf][row * LD32];
-            float* b = &sB[buf][row * LD32];
-            *reinterpret_cast<float2*>(a + 2 * kc) = make_float2(ra[i].x, ra[i].z);
-            *reinterpret_cast<float2*>(a + 8 + 2 * kc) = make_float2(ra[i].y, ra[i].w);
-            *reinterpret_cast<float2*>(b + 2 * kc) = make_float2(rb[i].x, rb[i].z);
-            *reinterpret_cast<float2*>(b + 8 + 2 * kc) = make_float2(rb[i].y, rb[i].w);
-        }
-    };
+    // global -> register staging of one k-tile: 128 rows x 16 floats per
+    // operand, two float4 per thread (row = c / 4, chunk = c % 4)
+    float4 ra0, ra1, rb0, rb1;
+    const int lrow = tid >> 2, lkc = tid & 3;
+#define GOAT_GLOAD32(T)                                                                           \
+    do {                                                                                          \
+        const int seg_ = (T) / ktiles, kt_ = (T) - seg_ * ktiles;                                 \
+        const float* X_ = static_cast<const float*>(p.X[seg_]) + (size_t)(m0 + lrow) * p.ldx +    \
+                          kt_ * BK32 + lkc * 4;                                                  \
+        const float* Z_ = static_cast<const float*>(p.Z[seg_]) + (size_t)(n0 + lrow) * p.ldz +    \
+                          kt_ * BK32 + lkc * 4;                                                  \
+        ra0 = *reinterpret_cast<const float4*>(X_);                                               \
+        ra1 = *reinterpret_cast<const float4*>(X_ + (size_t)64 * p.ldx);                          \
+        rb0 = *reinterpret_cast<const float4*>(Z_);                                               \
+        rb1 = *reinterpret_cast<const float4*>(Z_ + (size_t)64 * p.ldz);                          \
+    } while (0)
+#define GOAT_PUT32(PTR, V)                                                                        \
+    do {                                                                                          \
+        *reinterpret_cast<float2*>((PTR) + 2 * lkc) = make_float2((V).x, (V).z);                  \
+        *reinterpret_cast<float2*>((PTR) + 8 + 2 * lkc) = make_float2((V).y, (V).w);              \
+    } while (0)
+#define GOAT_SSTORE32(BUF)                                                                        \
+    do {                                                                                          \
+        float* a_ = &sA[BUF][lrow * LD32];                                                        \
+        float* b_ = &sB[BUF][lrow * LD32];                                                        \
+        GOAT_PUT32(a_, ra0);                                                                      \
+        GOAT_PUT32(a_ + 64 * LD32, ra1);                                                          \
+        GOAT_PUT32(b_, rb0);                                                                      \
+        GOAT_PUT32(b_ + 64 * LD32, rb1);                                                          \
+    } while (0)
 
-    gload(0);
-    sstore(0);
+    GOAT_GLOAD32(0);
+    GOAT_SSTORE32(0);
     __syncthreads();
+    const int arow = (wm * 64 + (lane & 31)) * LD32 + (lane >> 5) * 8;
+    const int brow = (wn * 64 + (lane & 31)) * LD32 + (lane >> 5) * 8;
     for (int t = 0; t < total; ++t) {
         const int buf = t & 1;
-        if (t + 1 < total) gload(t + 1);
-        float a[2][8], b[2][8];
+        if (t + 1 < total) GOAT_GLOAD32(t + 1);
+        const float* sa = sA[buf];
+        const float* sb = sB[buf];
+        const float4 a0l = *reinterpret_cast<const float4*>(sa + arow);
+        const float4 a0h = *reinterpret_cast<const float4*>(sa + arow + 4);
+        const float4 a1l = *reinterpret_cast<const float4*>(sa + arow + 32 * LD32);
+        const float4 a1h = *reinterpret_cast<const float4*>(sa + arow + 32 * LD32 + 4);
+        const float4 b0l = *reinterpret_cast<const float4*>(sb + brow);
+        const float4 b0h = *reinterpret_cast<const float4*>(sb + brow + 4);
+        const float4 b1l = *reinterpret_cast<const float4*>(sb + brow + 32 * LD32);
+        const float4 b1h = *reinterpret_cast<const float4*>(sb + brow + 32 * LD32 + 4);
+        const float a0[8] = {a0l.x, a0l.y, a0l.z, a0l.w, a0h.x, a0h.y, a0h.z, a0h.w};
+        const float a1[8] = {a1l.x, a1l.y, a1l.z, a1l.w, a1h.x, a1h.y, a1h.z, a1h.w};
+        const float b0[8] = {b0l.x, b0l.y, b0l.z, b0l.w, b0h.x, b0h.y, b0h.z, b0h.w};
+        const float b1[8] = {b1l.x, b1l.y, b1l.z, b1l.w, b1h.x, b1h.y, b1h.z, b1h.w};
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi) {
-            const float* src = &sA[buf][(wm * 64 + mi * 32 + (lane & 31)) * LD32 + (lane >> 5) * 8];
-            const float4 lo = *reinterpret_cast<const float4*>(src);
-            const float4 hi = *reinterpret_cast<const float4*>(src + 4);
-            a[mi][0] = lo.x; a[mi][1] = lo.y; a[mi][2] = lo.z; a[mi][3] = lo.w;
-            a[mi][4] = hi.x; a[mi][5] = hi.y; a[mi][6] = hi.z; a[mi][7] = hi.w;
+        for (int kk = 0; kk < 8; ++kk) {
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[kk], b0[kk], acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[kk], b1[kk], acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], b0[kk], acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[kk], b1[kk], acc[1][1], 0, 0, 0);
         }
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni) {
-            const float* src = &sB[buf][(wn * 64 + ni * 32 + (lane & 31)) * LD32 + (lane >> 5) * 8];
-            const float4 lo = *reinterpret_cast<const float4*>(src);
-            const float4 hi = *reinterpret_cast<const float4*>(src + 4);
-            b[ni][0] = lo.x; b[ni][1] = lo.y; b[ni][2] = lo.z; b[ni][3] = lo.w;
-            b[ni][4] = hi.x; b[ni][5] = hi.y; b[ni][6] = hi.z; b[ni][7] = hi.w;
-        }
-#pragma unroll
-        for (int kk = 0; kk < 8; ++kk)
-#pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                for (int ni = 0; ni < 2; ++ni)
-                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mi][kk], b[ni][kk], acc[mi][ni], 0, 0, 0);
-        if (t + 1 < total) sstore(buf ^ 1);
+        if (t + 1 < total) GOAT_SSTORE32(buf ^ 1);
         __syncthreads();
     }
+#undef GOAT_GLOAD32
+#undef GOAT_PUT32
+#undef GOAT_SSTORE32
     store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 

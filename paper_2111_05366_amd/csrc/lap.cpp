@@ -8,6 +8,9 @@
 // c_ij - u_i - v_j, a dual update and an augmentation along the found path.
 // Among columns of equal tentative distance the lowest index is scanned
 // first, so results are deterministic.
+#include <omp.h>
+
+#include <algorithm>
 #include <cmath>
 #include <limits>
 #include <vector>
@@ -52,6 +55,11 @@ int lap_max(int n, const double* M, int ld, int32_t* perm) {
         }
     }
 
+    // column scans run on several host threads for large n
+    const int nth = n >= 2048 ? std::max(1, omp_get_max_threads()) : 1;
+    std::vector<double> tbest(nth, INF);
+    std::vector<int> tj(nth, -1);
+    int tcount = 1;
     for (int f = 0; f < n; ++f) {
         if (col_of[f] >= 0) continue;
         std::fill(d.begin(), d.end(), INF);
@@ -64,13 +72,37 @@ int lap_max(int n, const double* M, int ld, int32_t* perm) {
             row_seen[i] = 1;
             seen_rows.push_back(i);
             const double ui = u[i];
+            const double* row = M + (size_t)i * ld;
             int jbest = -1;
             double best = INF;
-            for (int j = 0; j < n; ++j) {
-                if (col_done[j]) continue;
-                const double r = dmin + cost(i, j) - ui - v[j];
-                if (r < d[j]) { d[j] = r; pred[j] = i; }
-                if (d[j] < best) { best = d[j]; jbest = j; }
+            if (nth <= 1) {
+                for (int j = 0; j < n; ++j) {
+                    if (col_done[j]) continue;
+                    const double r = dmin - row[j] - ui - v[j];
+                    if (r < d[j]) { d[j] = r; pred[j] = i; }
+                    if (d[j] < best) { best = d[j]; jbest = j; }
+                }
+            } else {
+                // each thread scans one contiguous column range; the ranges are
+                // combined in order, so ties still go to the lowest index
+#pragma omp parallel num_threads(nth)
+                {
+                    const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+                    const int j0 = (int)((long long)n * t / nt), j1 = (int)((long long)n * (t + 1) / nt);
+                    double b = INF;
+                    int jb = -1;
+                    for (int j = j0; j < j1; ++j) {
+                        if (col_done[j]) continue;
+                        const double r = dmin - row[j] - ui - v[j];
+                        if (r < d[j]) { d[j] = r; pred[j] = i; }
+                        if (d[j] < b) { b = d[j]; jb = j; }
+                    }
+                    tbest[t] = b;
+                    tj[t] = jb;
+                    if (t == 0) tcount = nt;
+                }
+                for (int t = 0; t < tcount; ++t)
+                    if (tj[t] >= 0 && tbest[t] < best) { best = tbest[t]; jbest = tj[t]; }
             }
             if (jbest < 0 || best == INF) {
                 set_error("goat_lap_max: no augmenting path (infeasible costs)");

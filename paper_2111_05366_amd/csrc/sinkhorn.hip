@@ -19,6 +19,9 @@
 // start potentials are arbitrary). Afterwards every term is a column-
 // normalised plan entry (<= 1) and S_i, c_j lie in [1/n, n], so no further
 // shift is needed.
+#include <cstdio>
+#include <cstdlib>
+
 #include "common.h"
 
 namespace goat {
@@ -68,6 +71,7 @@ __device__ inline float block_max(float x, float* red) {
 struct SkArgs {
     const float* G;
     int ldg, n, np, rpw;       // rows per workgroup
+    int rev;                   // walk the strip's rows last to first
     float* u;
     float* unew;
     float* v;
@@ -76,80 +80,159 @@ struct SkArgs {
     SkCtrl* ctrl;
 };
 
-template <int T, int C, bool FIRST>
+// Thread t of a strip owns the float4 column groups t, t + T, ..., t + (C-1)T.
+// R rows are processed per step (one block reduction for all R row sums)
+// and the next R rows are loaded while the current ones reduce.
+// VLDS: the column potentials sit in LDS (16 T C bytes) instead of
+// registers, which leaves room for more rows in flight. Rows of a strip are
+// walked forwards or backwards (a.rev): alternating the direction between
+// iterations re-reads first the rows streamed last, which are the ones still
+// held in the memory-side cache when G is larger than it.
+template <int T, int R>
+__device__ inline void block_sum_r(float (&x)[R], float* red) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = wave_sum(x[r]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) red[r * (T / 64) + (threadIdx.x >> 6)] = x[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float s = 0.0f;
+#pragma unroll
+        for (int w = 0; w < T / 64; ++w) s += red[r * (T / 64) + w];
+        x[r] = s;
+    }
+}
+template <int T, int R>
+__device__ inline void block_max_r(float (&x)[R], float* red) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = wave_max(x[r]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) red[r * (T / 64) + (threadIdx.x >> 6)] = x[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float s = -INFINITY;
+#pragma unroll
+        for (int w = 0; w < T / 64; ++w) s = fmaxf(s, red[r * (T / 64) + w]);
+        x[r] = s;
+    }
+}
+
+template <int T, int C, int R, bool FIRST, bool VLDS>
 __global__ __launch_bounds__(T) void sk_row_kernel(SkArgs a) {
     if (a.ctrl->done) return;
-    __shared__ float red[4][T / 64];
+    extern __shared__ float4 sv4[];
+    __shared__ float red[2][R * (T / 64)];
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * a.rpw;
     const int r1 = min(a.n, r0 + a.rpw);
     const float kappa = a.ctrl->kappa;
 
-    float vj[C][4], acc[C][4];
+    float4 vreg[VLDS ? 1 : C];
+    float acc[C][4];
     bool live[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int j4 = tid + T * c;
         live[c] = 4 * j4 < a.n;
+        float vv[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int j = 4 * j4 + e;
-            vj[c][e] = (j < a.n) ? a.v[j] : -INFINITY;
+            vv[e] = (j < a.n) ? a.v[j] : -INFINITY;
             acc[c][e] = 0.0f;
         }
+        const float4 v4 = make_float4(vv[0], vv[1], vv[2], vv[3]);
+        if (VLDS) sv4[j4] = v4;
+        else vreg[VLDS ? 0 : c] = v4;
     }
+    if (VLDS) __syncthreads();
     float errmax = 0.0f;
-    float4 x[C], xn[C];
-    auto load_row = [&](int i, float4* dst) {
-        const float4* row = reinterpret_cast<const float4*>(a.G + (size_t)i * a.ldg);
-#pragma unroll
-        for (int c = 0; c < C; ++c) dst[c] = live[c] ? row[tid + T * c] : make_float4(0.f, 0.f, 0.f, 0.f);
-    };
-    if (r0 < r1) load_row(r0, x);
+    const int nrows = r1 - r0;
+    auto row_of = [&](int k) { return a.rev ? r1 - 1 - k : r0 + k; };
+    float4 x[R][C];
+    // rows k0 .. k0+R-1 of the strip into x (rows past the strip read as zero)
+#define GOAT_LOAD_ROWS(K0)                                                                          \
+    do {                                                                                            \
+        _Pragma("unroll") for (int r = 0; r < R; ++r) {                                             \
+            const bool ok_ = (K0) + r < nrows;                                                      \
+            const float4* row_ = reinterpret_cast<const float4*>(                                   \
+                a.G + (size_t)(ok_ ? row_of((K0) + r) : r0) * a.ldg);                               \
+            _Pragma("unroll") for (int c = 0; c < C; ++c)                                           \
+                x[r][c] = (ok_ && live[c]) ? row_[tid + T * c] : make_float4(0.f, 0.f, 0.f, 0.f);  \
+        }                                                                                           \
+    } while (0)
+    if (nrows > 0) GOAT_LOAD_ROWS(0);
     int par = 0;
-    for (int i = r0; i < r1; ++i) {
-        if (i + 1 < r1) load_row(i + 1, xn);
-        float y[C][4];
+    for (int k0 = 0; k0 < nrows; k0 += R) {
+        // keep the LDS copy of v authoritative: re-read it every step instead
+        // of letting the compiler cache it in registers
+        if (VLDS) asm volatile("" ::: "memory");
+        float y[R][C][4];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            y[c][0] = fmaf(x[c].x, kappa, vj[c][0]);
-            y[c][1] = fmaf(x[c].y, kappa, vj[c][1]);
-            y[c][2] = fmaf(x[c].z, kappa, vj[c][2]);
-            y[c][3] = fmaf(x[c].w, kappa, vj[c][3]);
+            const float4 v4 = VLDS ? sv4[tid + T * c] : vreg[VLDS ? 0 : c];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                y[r][c][0] = fmaf(x[r][c].x, kappa, v4.x);
+                y[r][c][1] = fmaf(x[r][c].y, kappa, v4.y);
+                y[r][c][2] = fmaf(x[r][c].z, kappa, v4.z);
+                y[r][c][3] = fmaf(x[r][c].w, kappa, v4.w);
+            }
         }
-        float shift, s = 0.0f;
+        // x is consumed: prefetch the next R rows into it while these reduce
+        if (k0 + R < nrows) GOAT_LOAD_ROWS(k0 + R);
+        float shift[R], s[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            s[r] = 0.0f;
+            const bool ok = k0 + r < nrows;
+            if (FIRST) {
+                float m = -INFINITY;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) m = fmaxf(m, y[r][c][e]);
+                shift[r] = m;
+            } else {
+                shift[r] = ok ? a.u[row_of(k0 + r)] : 0.0f;
+            }
+        }
         if (FIRST) {
-            float m = -INFINITY;
+            block_max_r<T, R>(shift, red[par]);
+            par ^= 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) shift[r] = (k0 + r < nrows) ? -shift[r] : 0.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
 #pragma unroll
             for (int c = 0; c < C; ++c)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) m = fmaxf(m, y[c][e]);
-            shift = -block_max<T>(m, red[par]);
-            par ^= 1;
-        } else {
-            shift = a.u[i];
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                y[c][e] = exp2f(y[c][e] + shift);
-                s += y[c][e];
-            }
-        const float S = block_sum<T>(s, red[par]);
+                for (int e = 0; e < 4; ++e) {
+                    y[r][c][e] = exp2f(y[r][c][e] + shift[r]);
+                    s[r] += y[r][c][e];
+                }
+        block_sum_r<T, R>(s, red[par]);
         par ^= 1;
-        const float inv = 1.0f / S;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
+        for (int r = 0; r < R; ++r) {
+            if (k0 + r >= nrows) break;
+            const float inv = 1.0f / s[r];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(y[c][e], inv, acc[c][e]);
-        if (!FIRST) errmax = fmaxf(errmax, fabsf(S - 1.0f));
-        if (tid == 0) a.unew[i] = shift - log2f(S);
-        if (i + 1 < r1) {
+            for (int c = 0; c < C; ++c)
 #pragma unroll
-            for (int c = 0; c < C; ++c) x[c] = xn[c];
+                for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(y[r][c][e], inv, acc[c][e]);
+            if (!FIRST) errmax = fmaxf(errmax, fabsf(s[r] - 1.0f));
+            if (tid == 0) a.unew[row_of(k0 + r)] = shift[r] - log2f(s[r]);
         }
     }
+#undef GOAT_LOAD_ROWS
     float* out = a.colpart + (size_t)blockIdx.x * a.np;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -163,10 +246,13 @@ __global__ __launch_bounds__(T) void sk_row_kernel(SkArgs a) {
     }
 }
 
-// 256 threads, 64 columns per block; wave q sums strips [q W/4, (q+1) W/4).
+// Column update: c_j = sum over strips of the partial column sums, summed in
+// a fixed order (strip lane l adds strips l, l + 16, ...; lanes combined in
+// order), then v_j <- v_j - log2 c_j and u <- unew. 256 threads = 16 float4
+// column groups x 16 strip lanes per block.
 __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int check) {
     if (a.ctrl->done) return;
-    __shared__ float part[4][64];
+    __shared__ float4 part[16][16];
     __shared__ float red[4];
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
     if (check) {
@@ -185,17 +271,37 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
         }
         if (blockIdx.x == 0 && tid == 0) a.ctrl->err = err;
     }
-    const int j = blockIdx.x * 64 + lane;
-    const int w0 = q * W / 4, w1 = (q + 1) * W / 4;
-    float s = 0.0f;
-    if (j < a.n)
-        for (int w = w0; w < w1; ++w) s += a.colpart[(size_t)w * a.np + j];
-    part[q][lane] = s;
+    const int cq = tid & 15, sl = tid >> 4;
+    const int j4 = blockIdx.x * 16 + cq;
+    const bool ok = 4 * j4 < a.n;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ok) {
+        const float4* cp = reinterpret_cast<const float4*>(a.colpart);
+        const size_t stride = (size_t)a.np / 4;
+#pragma unroll 4
+        for (int w = sl; w < W; w += 16) {
+            const float4 t = cp[(size_t)w * stride + j4];
+            acc.x += t.x; acc.y += t.y; acc.z += t.z; acc.w += t.w;
+        }
+    }
+    part[sl][cq] = acc;
     __syncthreads();
-    if (q == 0 && j < a.n) {
-        const float c = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-        a.v[j] -= log2f(fmaxf(c, 1.17549435e-38f));
-        a.u[j] = a.unew[j];
+    if (sl == 0 && ok) {
+        float4 c = part[0][cq];
+#pragma unroll
+        for (int l = 1; l < 16; ++l) {
+            const float4 t = part[l][cq];
+            c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
+        }
+        const float cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * j4 + e;
+            if (j < a.n) {
+                a.v[j] -= log2f(fmaxf(cc[e], 1.17549435e-38f));
+                a.u[j] = a.unew[j];
+            }
+        }
     }
     if (blockIdx.x == 0 && tid == 0) a.ctrl->iters += 1;
 }
@@ -304,31 +410,59 @@ __global__ __launch_bounds__(256) void sk_outputs_kernel(SkArgs a, int W, float*
 // ---------------------------------------------------------------- dispatch
 
 struct Geometry {
-    int T, C, W, rpw;
+    int T, C, W, rpw, R;
 };
 
 // Threads per strip: the smallest of 256 / 512 / 1024 that keeps a row's
 // share per thread at <= 40 columns (register budget without spills);
-// beyond n = 20480 the 1024-thread variant is used and spills.
+// beyond n = 20480 the 1024-thread variant is used and spills. The number of
+// strips W defaults to kSkDefaultWG; GOAT_SK_GEOM="T,W" overrides both (a
+// tuning knob for measurements).
+constexpr int kSkDefaultWG = 512;
+
 Geometry geometry(int n) {
+    int env_T = 0, env_W = 0, env_R = 0;
+    if (const char* e = getenv("GOAT_SK_GEOM")) {
+        int t = 0, w = 0, r = 1;
+        const int got = sscanf(e, "%d,%d,%d", &t, &w, &r);
+        if (got >= 2 && (t == 256 || t == 512 || t == 1024) && w >= 1 && w <= kSkWG && (r == 1 || r == 2)) {
+            env_T = t;
+            env_W = w;
+            env_R = r;
+        }
+    }
     Geometry g;
     const int n4 = (n + 3) / 4;
     g.T = n4 <= 256 * 10 ? 256 : (n4 <= 512 * 10 ? 512 : 1024);
+    if (env_T > 0 && n4 <= env_T * 16) g.T = env_T;
     g.C = (n4 + g.T - 1) / g.T;
     const int cs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
     for (int c : cs)
         if (c >= g.C) { g.C = c; break; }
-    g.W = n < kSkWG ? n : kSkWG;
+    const int wmax = env_W > 0 ? env_W : kSkDefaultWG;
+    g.W = n < wmax ? n : wmax;
     g.rpw = (n + g.W - 1) / g.W;
     g.W = (n + g.rpw - 1) / g.rpw;
+    g.R = env_R > 0 ? env_R : 1;
     return g;
 }
 
 template <int T, bool FIRST>
 int launch_row_T(const Geometry& g, const SkArgs& a, hipStream_t s) {
     dim3 grid(g.W), block(T);
+    const size_t lds = (size_t)16 * T * g.C;
+    const bool vlds = lds <= 65536;
     switch (g.C) {
-#define GOAT_SK_C(CC) case CC: hipLaunchKernelGGL((sk_row_kernel<T, CC, FIRST>), grid, block, 0, s, a); break;
+#define GOAT_SK_C(CC)                                                                                     \
+    case CC:                                                                                              \
+        if (g.R == 2 && CC <= 6) {                                                                        \
+            if (vlds) hipLaunchKernelGGL((sk_row_kernel<T, CC, 2, FIRST, true>), grid, block, lds, s, a);    \
+            else hipLaunchKernelGGL((sk_row_kernel<T, CC, 2, FIRST, false>), grid, block, 0, s, a);          \
+        } else {                                                                                          \
+            if (vlds) hipLaunchKernelGGL((sk_row_kernel<T, CC, 1, FIRST, true>), grid, block, lds, s, a);    \
+            else hipLaunchKernelGGL((sk_row_kernel<T, CC, 1, FIRST, false>), grid, block, 0, s, a);          \
+        }                                                                                                 \
+        break;
         GOAT_SK_C(1) GOAT_SK_C(2) GOAT_SK_C(3) GOAT_SK_C(4) GOAT_SK_C(5) GOAT_SK_C(6)
         GOAT_SK_C(8) GOAT_SK_C(10) GOAT_SK_C(12) GOAT_SK_C(16)
 #undef GOAT_SK_C
@@ -359,6 +493,7 @@ SkArgs make_args(int n, int np, const float* G, int ldg, const SkState& st, cons
     a.n = n;
     a.np = np;
     a.rpw = g.rpw;
+    a.rev = 0;
     a.u = st.u;
     a.unew = st.unew;
     a.v = st.v;
@@ -386,10 +521,11 @@ int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_r
     return GOAT_OK;
 }
 
-int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check,
+int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check, int iter,
                hipStream_t s) {
     const Geometry g = geometry(n);
-    const SkArgs a = make_args(n, np, G, ldg, st, g);
+    SkArgs a = make_args(n, np, G, ldg, st, g);
+    a.rev = iter & 1;
     int rc;
     prof_begin(0, s);
     if (g.T == 256) rc = first ? launch_row_T<256, true>(g, a, s) : launch_row_T<256, false>(g, a, s);

@@ -55,7 +55,7 @@ static int run_sinkhorn(Run& r) {
     int rc = sk_prepare(n, p.GP, np, nullptr, r.opt.eps_rel, p.fscal, warm ? p.g_prev : nullptr, r.opt.sk_tol,
                         p.sk, p.fscal, p.red, r.s);
     if (rc) return rc;
-    rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, r.s);
+    rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, 0, r.s);
     if (rc) return rc;
     const int check_every = r.opt.check_every > 0 ? r.opt.check_every : 16;
     int* hflag = reinterpret_cast<int*>(static_cast<char*>(r.hbuf) + 128);
@@ -64,7 +64,7 @@ static int run_sinkhorn(Run& r) {
     while (k < r.opt.sk_max && !stop) {
         const int m = std::min(check_every, r.opt.sk_max - k);
         for (int q = 0; q < m; ++q) {
-            rc = sk_iterate(n, np, p.GP, np, p.sk, 0, 1, r.s);
+            rc = sk_iterate(n, np, p.GP, np, p.sk, 0, 1, k + q, r.s);
             if (rc) return rc;
         }
         k += m;
