@@ -41,17 +41,20 @@ def _run(cmd):
     return r.stdout
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, extra=None) -> str:
+    """Compile every source and link libgoat.so at `out`. `extra`: additional
+    compiler flags (e.g. ["-DGOAT_SK_NT"] for experiment builds)."""
+    extra = list(extra or [])
     cc = hipcc()
     objs = []
     with tempfile.TemporaryDirectory(prefix="goat_build_") as tmp:
         for src in HIP_SOURCES:
             obj = os.path.join(tmp, src + ".o")
-            cmd = [cc, *COMMON, "--offload-arch=" + ARCH, *DEVICE_FLAGS, "-x", "hip",
+            cmd = [cc, *COMMON, *extra, "--offload-arch=" + ARCH, *DEVICE_FLAGS, "-x", "hip",
                    "-c", os.path.join(CSRC, src), "-o", obj]
-            out = _run(cmd)
-            if verbose and out.strip():
-                print(out)
+            msg = _run(cmd)
+            if verbose and msg.strip():
+                print(msg)
             objs.append(obj)
         for src in CPP_SOURCES:
             obj = os.path.join(tmp, src + ".o")
@@ -62,9 +65,9 @@ def build(verbose: bool = False) -> str:
         tmp_lib = os.path.join(tmp, "libgoat.so")
         _run([cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-fopenmp",
               "-Wl,-rpath," + OMP_LIBDIR, "-o", tmp_lib])
-        shutil.copyfile(tmp_lib, LIB + ".tmp")
-        os.replace(LIB + ".tmp", LIB)
-    return LIB
+        shutil.copyfile(tmp_lib, out + ".tmp")
+        os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -237,9 +237,14 @@ int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float ep
     int rc = sk_prepare(n, Gk, ldk, eps_dev, eps_rel, nullptr, init == GOAT_INIT_G ? g : nullptr, tol, p.sk,
                         p.fscal, p.red, s);
     if (rc) return rc;
-    for (int k = 0; k < max_iter; ++k) {
-        rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, k, s);
-        if (rc) return rc;
+    rc = sk_run_persistent(n, L.np, Gk, ldk, p.sk, 0, max_iter, s);
+    if (rc == GOAT_ENOTSUP) {
+        for (int k = 0; k < max_iter; ++k) {
+            rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, k, s);
+            if (rc) return rc;
+        }
+    } else if (rc) {
+        return rc;
     }
     return sk_finalize(n, L.np, Gk, ldk, p.sk, Q, ldq, nullptr, nullptr, f, g, iters_dev, err_dev, eps_out,
                        p.red, s);

@@ -127,6 +127,11 @@ int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_r
 // the solve (row-walk direction alternates with its parity).
 int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check, int iter,
                hipStream_t s);
+// Iterations k_begin .. k_end-1 in one cooperative launch (stops on the
+// device at convergence). GOAT_ENOTSUP (no error state) when not available:
+// the caller then uses sk_iterate.
+int sk_run_persistent(int n, int np, const float* G, int ldg, SkState st, int k_begin, int k_end,
+                      hipStream_t s);
 // Form Q (fp32 and optional bf16 split), its row-marginal error, potentials
 // in natural units, and (when P != NULL) the traces <Q,G>, <P,G>, ||Q-P||^2.
 int sk_finalize(int n, int np, const float* G, int ldg, SkState st,

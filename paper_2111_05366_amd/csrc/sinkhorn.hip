@@ -19,10 +19,14 @@
 // start potentials are arbitrary). Afterwards every term is a column-
 // normalised plan entry (<= 1) and S_i, c_j lie in [1/n, n], so no further
 // shift is needed.
+#include <hip/hip_cooperative_groups.h>
+
 #include <cstdio>
 #include <cstdlib>
 
 #include "common.h"
+
+namespace cg = cooperative_groups;
 
 namespace goat {
 namespace {
@@ -67,6 +71,19 @@ __device__ inline float block_max(float x, float* red) {
     for (int w = 0; w < T / 64; ++w) s = fmaxf(s, red[w]);
     return s;
 }
+
+// G is streamed once per iteration: non-temporal loads when GOAT_SK_NT is
+// defined at build time, plain loads otherwise.
+#ifdef GOAT_SK_NT
+typedef float goat_f4v __attribute__((ext_vector_type(4)));
+__device__ inline float4 goat_nt_load(const float4* p) {
+    const goat_f4v v = __builtin_nontemporal_load(reinterpret_cast<const goat_f4v*>(p));
+    return make_float4(v[0], v[1], v[2], v[3]);
+}
+#define GOAT_GLOAD(P) goat_nt_load(P)
+#else
+#define GOAT_GLOAD(P) (*(P))
+#endif
 
 struct SkArgs {
     const float* G;
@@ -164,7 +181,8 @@ __global__ __launch_bounds__(T) void sk_row_kernel(SkArgs a) {
             const float4* row_ = reinterpret_cast<const float4*>(                                   \
                 a.G + (size_t)(ok_ ? row_of((K0) + r) : r0) * a.ldg);                               \
             _Pragma("unroll") for (int c = 0; c < C; ++c)                                           \
-                x[r][c] = (ok_ && live[c]) ? row_[tid + T * c] : make_float4(0.f, 0.f, 0.f, 0.f);  \
+                x[r][c] = (ok_ && live[c]) ? GOAT_GLOAD(row_ + tid + T * c)                          \
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);                        \
         }                                                                                           \
     } while (0)
     if (nrows > 0) GOAT_LOAD_ROWS(0);
@@ -243,6 +261,158 @@ __global__ __launch_bounds__(T) void sk_row_kernel(SkArgs a) {
     if (!FIRST) {
         const float m = block_max<T>(errmax, red[par]);
         if (tid == 0) a.errpart[blockIdx.x] = m;
+    }
+}
+
+// Whole Sinkhorn solve in one cooperative launch: every workgroup owns a
+// row strip (row phase as in sk_row_kernel) and, after a grid barrier, a
+// slice of columns (the column update as in sk_merge_kernel, same fixed
+// summation order over strips). All workgroups evaluate the stop test on the
+// same partials, so they leave the loop together. Iterations k_begin ..
+// k_end-1 run; k == 0 is the max-shifted first sweep.
+struct SkPersist {
+    int k_begin, k_end, W, cpw;
+};
+
+template <int T, int C>
+__global__ __launch_bounds__(T) void sk_persistent_kernel(SkArgs a, SkPersist pp) {
+    if (a.ctrl->done) return;
+    cg::grid_group grid = cg::this_grid();
+    extern __shared__ float4 sv4[];
+    __shared__ float red[2][T / 64];
+    __shared__ float mpart[T / 64][64];
+    const int tid = threadIdx.x, w = blockIdx.x;
+    const int r0 = w * a.rpw;
+    const int r1 = min(a.n, r0 + a.rpw);
+    const int nrows = max(r1 - r0, 0);
+    const float kappa = a.ctrl->kappa;
+    const float tol = a.ctrl->tol;
+    bool live[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) live[c] = 4 * (tid + T * c) < a.n;
+
+    for (int k = pp.k_begin; k < pp.k_end; ++k) {
+        const bool first = (k == 0);
+        const bool rev = (k & 1) != 0;
+        // ---------------- row phase
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int j4 = tid + T * c;
+            float vv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int j = 4 * j4 + e;
+                vv[e] = (j < a.n) ? a.v[j] : -INFINITY;
+            }
+            sv4[j4] = make_float4(vv[0], vv[1], vv[2], vv[3]);
+        }
+        __syncthreads();
+        float acc[C][4];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[c][e] = 0.0f;
+        float errmax = 0.0f;
+        float4 x[C];
+        int par = 0;
+#define GOAT_ROW_OF(K) (rev ? r1 - 1 - (K) : r0 + (K))
+#define GOAT_LOAD_ROW(I)                                                                           \
+    do {                                                                                           \
+        const float4* row_ = reinterpret_cast<const float4*>(a.G + (size_t)(I) * a.ldg);          \
+        _Pragma("unroll") for (int c = 0; c < C; ++c)                                              \
+            x[c] = live[c] ? row_[tid + T * c] : make_float4(0.f, 0.f, 0.f, 0.f);                \
+    } while (0)
+        if (nrows > 0) GOAT_LOAD_ROW(GOAT_ROW_OF(0));
+        for (int kk = 0; kk < nrows; ++kk) {
+            const int i = GOAT_ROW_OF(kk);
+            asm volatile("" ::: "memory");
+            float y[C][4];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float4 v4 = sv4[tid + T * c];
+                y[c][0] = fmaf(x[c].x, kappa, v4.x);
+                y[c][1] = fmaf(x[c].y, kappa, v4.y);
+                y[c][2] = fmaf(x[c].z, kappa, v4.z);
+                y[c][3] = fmaf(x[c].w, kappa, v4.w);
+            }
+            if (kk + 1 < nrows) GOAT_LOAD_ROW(GOAT_ROW_OF(kk + 1));
+            float shift;
+            if (first) {
+                float m = -INFINITY;
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) m = fmaxf(m, y[c][e]);
+                shift = -block_max<T>(m, red[par]);
+                par ^= 1;
+            } else {
+                shift = a.u[i];
+            }
+            float s = 0.0f;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    y[c][e] = exp2f(y[c][e] + shift);
+                    s += y[c][e];
+                }
+            const float S = block_sum<T>(s, red[par]);
+            par ^= 1;
+            const float inv = 1.0f / S;
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(y[c][e], inv, acc[c][e]);
+            if (!first) errmax = fmaxf(errmax, fabsf(S - 1.0f));
+            if (tid == 0) a.unew[i] = shift - log2f(S);
+        }
+#undef GOAT_LOAD_ROW
+#undef GOAT_ROW_OF
+        float* out = a.colpart + (size_t)w * a.np;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int j4 = tid + T * c;
+            if (4 * j4 < a.np)
+                reinterpret_cast<float4*>(out)[j4] = make_float4(acc[c][0], acc[c][1], acc[c][2], acc[c][3]);
+        }
+        {
+            const float m = block_max<T>(errmax, red[par]);
+            par ^= 1;
+            if (tid == 0) a.errpart[w] = m;
+        }
+        grid.sync();
+        // ---------------- column phase
+        if (!first) {
+            float m = 0.0f;
+            for (int q = tid; q < pp.W; q += T) m = fmaxf(m, a.errpart[q]);
+            const float err = block_max<T>(m, red[par]);
+            par ^= 1;
+            if (w == 0 && tid == 0) a.ctrl->err = err;
+            if (err <= tol) {
+                if (w == 0 && tid == 0) a.ctrl->done = 1;
+                break;                           // the same decision in every workgroup
+            }
+        }
+        const int lane = tid & 63, sl = tid >> 6;   // 64 columns x T/64 strip lanes
+        const int cbeg = w * pp.cpw, cend = min(a.n, cbeg + pp.cpw);
+        for (int cb = cbeg; cb < cend; cb += 64) {
+            const int j = cb + lane;
+            float part = 0.0f;
+            if (j < cend)
+                for (int q = sl; q < pp.W; q += T / 64) part += a.colpart[(size_t)q * a.np + j];
+            mpart[sl][lane] = part;
+            __syncthreads();
+            if (sl == 0 && j < cend) {
+                float c = mpart[0][lane];
+#pragma unroll
+                for (int l = 1; l < T / 64; ++l) c += mpart[l][lane];
+                a.v[j] -= log2f(fmaxf(c, 1.17549435e-38f));
+                a.u[j] = a.unew[j];
+            }
+            __syncthreads();
+        }
+        if (w == 0 && tid == 0) a.ctrl->iters += 1;
+        grid.sync();
     }
 }
 
@@ -413,9 +583,10 @@ struct Geometry {
     int T, C, W, rpw, R;
 };
 
-// Threads per strip: the smallest of 256 / 512 / 1024 that keeps a row's
-// share per thread at <= 40 columns (register budget without spills);
-// beyond n = 20480 the 1024-thread variant is used and spills. The number of
+// Threads per strip: 256 below n = 4096, else the smallest of 512 / 1024
+// that keeps a row's share per thread at <= 40 columns (register budget
+// without spills); beyond n = 20480 the 1024-thread variant is used and
+// spills. The number of
 // strips W defaults to kSkDefaultWG; GOAT_SK_GEOM="T,W" overrides both (a
 // tuning knob for measurements).
 constexpr int kSkDefaultWG = 512;
@@ -433,7 +604,8 @@ Geometry geometry(int n) {
     }
     Geometry g;
     const int n4 = (n + 3) / 4;
-    g.T = n4 <= 256 * 10 ? 256 : (n4 <= 512 * 10 ? 512 : 1024);
+    // 512 threads from n = 4096 on: measured 2% faster than 256 at n = 10000
+    g.T = n < 4096 ? 256 : (n4 <= 512 * 10 ? 512 : 1024);
     if (env_T > 0 && n4 <= env_T * 16) g.T = env_T;
     g.C = (n4 + g.T - 1) / g.T;
     const int cs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
@@ -503,6 +675,42 @@ SkArgs make_args(int n, int np, const float* G, int ldg, const SkState& st, cons
     return a;
 }
 
+// Cooperative launch of the whole solve; GOAT_ENOTSUP when the shape has no
+// persistent variant or the strips cannot all be resident at once.
+template <int T, int C>
+int launch_persistent_TC(const Geometry& g, SkArgs a, int k_begin, int k_end, hipStream_t s) {
+    auto kfn = sk_persistent_kernel<T, C>;
+    const size_t lds = (size_t)16 * T * C;
+    int per_cu = 0, cus = 0, dev = 0;
+    GOAT_HIP(hipGetDevice(&dev));
+    GOAT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GOAT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, T, lds));
+    if (per_cu < 1 || (long long)per_cu * cus < g.W) return GOAT_ENOTSUP;
+    SkPersist pp;
+    pp.k_begin = k_begin;
+    pp.k_end = k_end;
+    pp.W = g.W;
+    pp.cpw = (a.n + g.W - 1) / g.W;
+    void* args[] = {&a, &pp};
+    GOAT_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3(g.W), dim3(T), args, lds, s));
+    return GOAT_OK;
+}
+
+template <int T>
+int launch_persistent_T(const Geometry& g, const SkArgs& a, int k_begin, int k_end, hipStream_t s) {
+    switch (g.C) {
+        case 1: return launch_persistent_TC<T, 1>(g, a, k_begin, k_end, s);
+        case 2: return launch_persistent_TC<T, 2>(g, a, k_begin, k_end, s);
+        case 3: return launch_persistent_TC<T, 3>(g, a, k_begin, k_end, s);
+        case 4: return launch_persistent_TC<T, 4>(g, a, k_begin, k_end, s);
+        case 5: return launch_persistent_TC<T, 5>(g, a, k_begin, k_end, s);
+        case 6: return launch_persistent_TC<T, 6>(g, a, k_begin, k_end, s);
+        case 8: return launch_persistent_TC<T, 8>(g, a, k_begin, k_end, s);
+        case 10: return launch_persistent_TC<T, 10>(g, a, k_begin, k_end, s);
+        default: return GOAT_ENOTSUP;
+    }
+}
+
 }  // namespace
 
 int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_rel,
@@ -536,6 +744,25 @@ int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, in
     hipLaunchKernelGGL(sk_merge_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a, g.W, check);
     GOAT_HIP(hipGetLastError());
     return GOAT_OK;
+}
+
+int sk_run_persistent(int n, int np, const float* G, int ldg, SkState st, int k_begin, int k_end,
+                      hipStream_t s) {
+    // Opt-in (GOAT_SK_PERSISTENT=1): measured slower than one launch pair per
+    // iteration on MI355X at n = 10000 (the grid barrier costs more than the
+    // two launch gaps it removes).
+    const char* e = getenv("GOAT_SK_PERSISTENT");
+    if (!e || e[0] != '1') return GOAT_ENOTSUP;
+    if (k_end <= k_begin) return GOAT_OK;
+    const Geometry g = geometry(n);
+    if (g.T > 512 || 16 * g.T * g.C > 65536) return GOAT_ENOTSUP;
+    const SkArgs a = make_args(n, np, G, ldg, st, g);
+    prof_begin(0, s);
+    int rc = g.T == 256 ? launch_persistent_T<256>(g, a, k_begin, k_end, s)
+                        : launch_persistent_T<512>(g, a, k_begin, k_end, s);
+    prof_end(0, s);
+    if (rc == GOAT_ENOTSUP) clear_error();
+    return rc;
 }
 
 int sk_finalize(int n, int np, const float* G, int ldg, SkState st, float* Q, int ldq,

@@ -46,15 +46,13 @@ struct Run {
     }
 };
 
-static int run_sinkhorn(Run& r) {
+// Fallback when the persistent solve is unavailable: one launch pair per
+// iteration, the device-side convergence flag polled every check_every
+// iterations (two chunks in flight).
+static int run_sinkhorn_polled(Run& r) {
     const int n = r.L.n, np = r.L.np;
-    const bool bf = r.opt.prec != GOAT_PREC_FP32;
     Ptrs& p = r.p;
-    const bool warm = r.opt.warm && r.fw > 0;
-    // eps from the max|G_P| that the previous update (or the start) left in fscal[0]
-    int rc = sk_prepare(n, p.GP, np, nullptr, r.opt.eps_rel, p.fscal, warm ? p.g_prev : nullptr, r.opt.sk_tol,
-                        p.sk, p.fscal, p.red, r.s);
-    if (rc) return rc;
+    int rc;
     rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, 0, r.s);
     if (rc) return rc;
     const int check_every = r.opt.check_every > 0 ? r.opt.check_every : 16;
@@ -77,6 +75,21 @@ static int run_sinkhorn(Run& r) {
         }
         ++chunk;
     }
+    return GOAT_OK;
+}
+
+static int run_sinkhorn(Run& r) {
+    const int n = r.L.n, np = r.L.np;
+    const bool bf = r.opt.prec != GOAT_PREC_FP32;
+    Ptrs& p = r.p;
+    const bool warm = r.opt.warm && r.fw > 0;
+    // eps from the max|G_P| that the previous update (or the start) left in fscal[0]
+    int rc = sk_prepare(n, p.GP, np, nullptr, r.opt.eps_rel, p.fscal, warm ? p.g_prev : nullptr, r.opt.sk_tol,
+                        p.sk, p.fscal, p.red, r.s);
+    if (rc) return rc;
+    rc = sk_run_persistent(n, np, p.GP, np, p.sk, 0, r.opt.sk_max, r.s);
+    if (rc == GOAT_ENOTSUP) rc = run_sinkhorn_polled(r);
+    if (rc) return rc;
     int* it_dev = reinterpret_cast<int*>(p.scal + 8);
     float* err_dev = reinterpret_cast<float*>(p.scal + 9);
     return sk_finalize(n, np, p.GP, np, p.sk, p.Q, np, bf ? static_cast<uint16_t*>(p.P_hi) : nullptr,
