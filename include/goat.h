@@ -135,11 +135,13 @@ typedef struct goat_options {
     int   prec;           /* GOAT_PREC_*                                            */
     int   symmetric;      /* 1: A = A^T and B = B^T                                 */
     int   proj;           /* 0: final LAP on P_final; 1: on grad f(P_final)         */
-    int   warm;           /* 0: cold Sinkhorn each iteration; 1: start from the
-                             previous iteration's column potentials                 */
+    int   warm;           /* Sinkhorn start: 0 cold; 1 the previous iteration's
+                             column potentials; 2 the warm-start network each
+                             iteration; 3 the network first, then as 1            */
     int   stop_on_stall;  /* 1: stop when t == 0 (default); 0: run fw_max iterations */
     int   check_every;    /* Sinkhorn convergence flag polled every k iterations (16) */
     int   reserved[5];
+    const float* mlp_params; /* device float[goat_mlp_param_count()] (warm 2, 3) */
 } goat_options;
 
 /* Per-iteration record of goat_solve (host memory). */
@@ -198,6 +200,7 @@ int goat_solve(int n, const float* A, const float* B, int ld,
  *  goat_run_finish  final assignment on P (or grad f(P)), the score of the
  *                   permutation, optional copy of P to P_out (ldp).
  *  goat_run_free    releases the handle (host memory, events).
+ *  goat_run_gradient copies the current grad f(P) out (device to device).
  * All host-synchronous on the stream given to goat_run_begin.
  */
 typedef struct goat_run goat_run;
@@ -209,6 +212,8 @@ int  goat_run_steps(goat_run* run, int k, goat_iter_record* hist_host,
 int  goat_run_finish(goat_run* run, int32_t* perm_host, goat_stats* stats_host,
                      float* P_out, int ldp);
 void goat_run_free(goat_run* run);
+/* Copy of the run's current gradient grad f(P) (n x n, ldg) into G_out. */
+int  goat_run_gradient(goat_run* run, float* G_out, int ldg);
 
 /*
  * Kernel timing hook (measurement only). which = 0: Sinkhorn row sweep;
@@ -220,6 +225,37 @@ void goat_run_free(goat_run* run);
  */
 int goat_profile_enable(int which, int stride);
 int goat_profile_read(int which, double* ms_total, long long* count);
+
+/*
+ * Learned Sinkhorn warm start (not in the paper; the network replaces the
+ * cold start g = 0 of Alg. 2's Sinkhorn solve, whose fixed point it does not
+ * change). Features of column j of X = G / eps: mean_i, max_i, population
+ * std_i and LSE_i x_ij - log n, each centred over j; network
+ * 4 -> 128 -> 128 -> 1 with ReLU, float32, predicting g_j / eps (centred).
+ * Parameters: device float[goat_mlp_param_count()] packed W1[128][4], b1,
+ * W2[128][128], b2, W3[128], b3.
+ *  goat_mlp_features  F: device float[n][4]; eps_dev: device float; the
+ *                     workspace is the one of goat_workspace_size(n, ...)
+ *                     (G is repacked into it when ld % 4 != 0 or it is
+ *                     not 16-byte aligned); n <= 20480.
+ *  goat_mlp_forward   y[N] = network(F[N][4]).
+ *  goat_mlp_backward  grad = d/dparams of (1/N) sum (y - target)^2 and the
+ *                     loss (loss_dev may be NULL); workspace of
+ *                     goat_mlp_workspace_size(N) bytes; deterministic.
+ *  goat_mlp_adam      one Adam step (beta 0.9 / 0.999, eps 1e-8, bias
+ *                     corrected; step counts from 1) on params, m, v.
+ */
+int    goat_mlp_param_count(void);
+size_t goat_mlp_workspace_size(int n_samples);
+int    goat_mlp_features(int n, const float* G, int ldg, const float* eps_dev,
+                         float* F, void* ws, size_t ws_bytes, void* stream);
+int    goat_mlp_forward(int N, const float* F, const float* params, float* y,
+                        void* stream);
+int    goat_mlp_backward(int N, const float* F, const float* target,
+                         const float* params, float* grad, float* loss_dev,
+                         void* ws, size_t ws_bytes, void* stream);
+int    goat_mlp_adam(const float* grad, float* params, float* m, float* v,
+                     int step, float lr, void* stream);
 
 /*
  * goat_lap_max - host linear assignment (Alg. 3 return line; Alg. 1 step 2

@@ -29,14 +29,13 @@ Layout make_layout(int n, int prec, int sym) {
     auto take = [&](size_t bytes) { const size_t at = o; o = align256(o + bytes); return at; };
     // small state first: offsets depend on n only
     L.ctrl = take(256);
-    L.u = take(np * 4);
-    L.unew = take(np * 4);
-    L.v = take(np * 4);
+    L.pot = take(np * 4 * 6);
     L.errpart = take(kSkWG * 4);
     L.colpart = take((size_t)kSkWG * np * 4);
     L.red = take((size_t)kRedWG * 4 * 8);
     L.scal = take(64 * 8 + np * 4 * 2);   // scalars, then g_prev[np], perm_dev[np]
     L.fscal = take((16 + kRedWG) * 4);
+    L.mlp = take(np * 5 * 4);
     // fp32 solver matrices
     L.P = take(pl * 4);
     L.Q = take(pl * 4);
@@ -126,9 +125,13 @@ Ptrs make_ptrs(const Layout& L, void* ws) {
     p.Y_hi = b + L.opY;
     p.Y_lo = b + L.opY + pl * rows * 2;
     p.sk.ctrl = reinterpret_cast<SkCtrl*>(b + L.ctrl);
-    p.sk.u = reinterpret_cast<float*>(b + L.u);
-    p.sk.unew = reinterpret_cast<float*>(b + L.unew);
-    p.sk.v = reinterpret_cast<float*>(b + L.v);
+    float* pot = reinterpret_cast<float*>(b + L.pot);
+    p.sk.ug = pot;
+    p.sk.us = pot + (size_t)L.np;
+    p.sk.ung = pot + 2 * (size_t)L.np;
+    p.sk.uns = pot + 3 * (size_t)L.np;
+    p.sk.vg = pot + 4 * (size_t)L.np;
+    p.sk.vs = pot + 5 * (size_t)L.np;
     p.sk.errpart = reinterpret_cast<float*>(b + L.errpart);
     p.sk.colpart = reinterpret_cast<float*>(b + L.colpart);
     p.red = reinterpret_cast<double*>(b + L.red);
@@ -136,6 +139,8 @@ Ptrs make_ptrs(const Layout& L, void* ws) {
     p.g_prev = reinterpret_cast<float*>(b + L.scal + 64 * 8);
     p.perm_dev = reinterpret_cast<int32_t*>(b + L.scal + 64 * 8 + (size_t)L.np * 4);
     p.fscal = reinterpret_cast<float*>(b + L.fscal);
+    p.feat = reinterpret_cast<float*>(b + L.mlp);
+    p.pred = p.feat + (size_t)L.np * 4;
     return p;
 }
 
@@ -237,14 +242,12 @@ int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float ep
     int rc = sk_prepare(n, Gk, ldk, eps_dev, eps_rel, nullptr, init == GOAT_INIT_G ? g : nullptr, tol, p.sk,
                         p.fscal, p.red, s);
     if (rc) return rc;
-    rc = sk_run_persistent(n, L.np, Gk, ldk, p.sk, 0, max_iter, s);
-    if (rc == GOAT_ENOTSUP) {
-        for (int k = 0; k < max_iter; ++k) {
-            rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, k, s);
-            if (rc) return rc;
-        }
-    } else if (rc) {
-        return rc;
+    // stream-ordered, so the sweep form is fixed up front: compensated when
+    // the tolerance is below what the plain form certifies
+    const int precise = tol < sk_plain_floor;
+    for (int k = 0; k < max_iter; ++k) {
+        rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, k, precise, s);
+        if (rc) return rc;
     }
     return sk_finalize(n, L.np, Gk, ldk, p.sk, Q, ldq, nullptr, nullptr, f, g, iters_dev, err_dev, eps_out,
                        p.red, s);
@@ -277,6 +280,58 @@ int goat_score(int n, const float* A, const float* B, int ld, const int32_t* per
     if (ws_bytes < small_bytes(L)) { set_error("goat_score: workspace too small"); return GOAT_ENOMEM; }
     Ptrs p = make_ptrs(L, ws);
     return launch_score(n, A, B, ld, perm_dev, p.red, out_dev, static_cast<hipStream_t>(stream));
+}
+
+int goat_mlp_param_count(void) { return mlp_param_count(); }
+
+size_t goat_mlp_workspace_size(int n_samples) {
+    return n_samples < 1 ? 0 : mlp_part_bytes(n_samples);
+}
+
+int goat_mlp_features(int n, const float* G, int ldg, const float* eps_dev, float* F, void* ws, size_t ws_bytes,
+                      void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(G && eps_dev && F && ws, "null pointer");
+    GOAT_CHECK_ARG(ldg >= n, "leading dimension < n");
+    const Layout L = make_layout(n, GOAT_PREC_FP32, 1);
+    const bool repack = (ldg % 4) != 0 || !aligned16(G);
+    const size_t need = small_bytes(L) + (repack ? (size_t)L.np * L.np * 4 : 0);
+    if (ws_bytes < need) { set_error("goat_mlp_features: workspace too small"); return GOAT_ENOMEM; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ptrs p = make_ptrs(L, ws);
+    const float* Gk = G;
+    int ldk = ldg;
+    if (repack) {
+        int rc = launch_copy_pad(n, G, ldg, p.P, L.np, L.np, s);
+        if (rc) return rc;
+        Gk = p.P;
+        ldk = L.np;
+    }
+    return mlp_features(n, L.np, Gk, ldk, eps_dev, p.sk.colpart, F, s);
+}
+
+int goat_mlp_forward(int N, const float* F, const float* params, float* y, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(N >= 1, "N < 1");
+    GOAT_CHECK_ARG(F && params && y, "null pointer");
+    return mlp_forward(N, F, params, y, static_cast<hipStream_t>(stream));
+}
+
+int goat_mlp_backward(int N, const float* F, const float* target, const float* params, float* grad, float* loss_dev,
+                      void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(N >= 1, "N < 1");
+    GOAT_CHECK_ARG(F && target && params && grad && ws, "null pointer");
+    if (ws_bytes < mlp_part_bytes(N)) { set_error("goat_mlp_backward: workspace too small"); return GOAT_ENOMEM; }
+    return mlp_backward(N, F, target, params, grad, loss_dev, ws, static_cast<hipStream_t>(stream));
+}
+
+int goat_mlp_adam(const float* grad, float* params, float* m, float* v, int step, float lr, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(grad && params && m && v, "null pointer");
+    GOAT_CHECK_ARG(step >= 1 && std::isfinite(lr) && lr > 0.0f, "step >= 1 and lr > 0 required");
+    return mlp_adam(grad, params, m, v, step, lr, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -48,7 +48,8 @@ struct SkCtrl {                    // Sinkhorn control block (device)
     int   iters;                   // completed column updates
     float err;                     // last checked row-marginal error
     float tol;
-    int   pad[2];
+    float h;                       // grid step of the compensated potentials
+    int   pad;
 };
 
 // Workspace layout. All internal matrices have leading dimension np.
@@ -58,10 +59,12 @@ struct Layout {
     size_t opP = 0;                // packed P-side operand
     size_t opY = 0;                // intermediate product (transposed layout)
     size_t P = 0, Q = 0, GP = 0, GQ = 0;   // solver matrices (fp32)
-    size_t u = 0, unew = 0, v = 0, colpart = 0, errpart = 0, ctrl = 0;
+    size_t pot = 0;                // potentials: ug, us, ung, uns, vg, vs ([np] each)
+    size_t colpart = 0, errpart = 0, ctrl = 0;
     size_t red = 0;                // float64 reduction partials
     size_t scal = 0;               // float64 scalars (line search etc.)
     size_t fscal = 0;              // float scalars (absmax, eps)
+    size_t mlp = 0;                // warm-start features [np][4] and prediction [np]
     size_t total = 0;
 };
 
@@ -116,7 +119,10 @@ int grad_packed(const Layout& L, const GradOps& ops, float* G, int ldg, int m_va
 
 // Sinkhorn (sinkhorn.hip)
 struct SkState {
-    float* u; float* unew; float* v; float* colpart; float* errpart; SkCtrl* ctrl;
+    float* ug; float* us;          // row potentials: grid part, remainder
+    float* ung; float* uns;        // row potentials of the sweep in flight
+    float* vg; float* vs;          // column potentials
+    float* colpart; float* errpart; SkCtrl* ctrl;
 };
 // eps = *eps_dev if given, else eps_rel * *absmax_dev if given, else
 // eps_rel * max|G| computed here (into fscal[0]).
@@ -125,13 +131,14 @@ int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_r
                double* red, hipStream_t s);
 // One Sinkhorn iteration (row sweep + column update); iter is its index in
 // the solve (row-walk direction alternates with its parity).
+// precise selects the compensated exponent (needed to certify tolerances
+// below sk_plain_floor); the first iteration always uses the plain form.
 int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check, int iter,
-               hipStream_t s);
-// Iterations k_begin .. k_end-1 in one cooperative launch (stops on the
-// device at convergence). GOAT_ENOTSUP (no error state) when not available:
-// the caller then uses sk_iterate.
-int sk_run_persistent(int n, int np, const float* G, int ldg, SkState st, int k_begin, int k_end,
-                      hipStream_t s);
+               int precise, hipStream_t s);
+// Smallest tolerance the plain (uncompensated) sweep certifies reliably.
+constexpr float sk_plain_floor = 1e-5f;
+// GOAT_SK_PRECISE=1 forces compensated sweeps from the second iteration on.
+bool sk_force_precise();
 // Form Q (fp32 and optional bf16 split), its row-marginal error, potentials
 // in natural units, and (when P != NULL) the traces <Q,G>, <P,G>, ||Q-P||^2.
 int sk_finalize(int n, int np, const float* G, int ldg, SkState st,
@@ -161,6 +168,7 @@ struct Ptrs {
     void* P_hi; void* P_lo; void* Y_hi; void* Y_lo;
     SkState sk;
     double* red; double* scal; float* fscal; float* g_prev; int32_t* perm_dev;
+    float* feat; float* pred;
 };
 size_t small_bytes(const Layout& L);
 Ptrs make_ptrs(const Layout& L, void* ws);
@@ -171,6 +179,17 @@ GradOps grad_ops(const Ptrs& p);
 // 1 gradient product
 void prof_begin(int which, hipStream_t s);
 void prof_end(int which, hipStream_t s);
+
+// Learned warm start (mlp.hip)
+int mlp_param_count();
+size_t mlp_part_bytes(int N);
+int mlp_features(int n, int np, const float* G, int ldg, const float* eps_dev, float* part, float* F,
+                 hipStream_t s);
+int mlp_forward(int N, const float* F, const float* p, float* y, hipStream_t s);
+int mlp_backward(int N, const float* F, const float* t, const float* p, float* grad, float* loss, void* part,
+                 hipStream_t s);
+int mlp_adam(const float* grad, float* p, float* m, float* v, int step, float lr, hipStream_t s);
+int warm_seed(int n, const float* pred, const SkCtrl* ctrl, float* vg, float* vs, hipStream_t s);
 
 // Host linear assignment (lap.cpp)
 int lap_max(int n, const double* M, int ld, int32_t* perm);

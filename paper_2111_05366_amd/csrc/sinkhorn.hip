@@ -1,56 +1,76 @@
 // Log-domain Sinkhorn-Knopp scaling for the LOT direction (Alg. 2, with the
 // cost negated for the maximisation of Alg. 3 step 2).
 //
-// Internal units: potentials in base 2 scaled by 1/eps,
+// Units: potentials in base 2 scaled by 1/eps,
 //     u_i = f_i * kappa,  v_j = g_j * kappa,  kappa = log2(e) / eps,
 // so Q_ij = 2^(G_ij kappa + u_i + v_j).
 //
+// Compensated potentials. Each potential is a pair (grid part, remainder):
+// the grid part is a multiple of h = 2^(e - 24), where 2^e bounds
+// max|G kappa| + 64, and the remainder is small (|r| <= h/2). For an entry
+// that matters (exponent near 0) the grid parts satisfy
+// |v_grid + u_grid| < 2^e, so their sum is exact in float32, the fma
+// G kappa + (v_grid + u_grid) rounds only a small result, and the small
+// remainders are added last. This keeps row and column sums accurate to a
+// few 1e-7 (a plain float32 potential of magnitude ~48 alone carries ~2e-6
+// of rounding), so a 1e-6 marginal tolerance can be certified. The plain
+// form adds v_grid + v_rem once per column (one add less per entry, half the
+// LDS); drivers use it far from the tolerance and switch to the compensated
+// form near it.
+//
 // One iteration = one read of G:
-//   row pass  (sk_row_kernel):  workgroup w owns a strip of rows. For a row i
-//     it forms e_ij = 2^(G_ij kappa + v_j + u_i) for the whole row (held in
-//     registers), S_i = sum_j e_ij (a block reduction), the new potential
-//     u_i - log2 S_i, and adds e_ij / S_i (the row-normalised plan) into
-//     per-thread column accumulators. S_i is the row sum of the current plan,
-//     so |S_i - 1| is the row-marginal error checked by the stop rule.
-//   merge     (sk_merge_kernel): c_j = sum_w partial_w[j] in fixed order,
-//     v_j <- v_j - log2 c_j, which is the column update
+//   row sweep (sk_row_kernel): workgroup w owns a strip of rows. For a row i
+//     it forms e_ij = 2^(G_ij kappa + v_j + u_i) for the whole row, S_i =
+//     sum_j e_ij (a block reduction), the new potential u_i - log2 S_i, and
+//     adds e_ij / S_i (the row-normalised plan) into per-thread column
+//     accumulators. S_i is the row sum of the current plan, so |S_i - 1| is
+//     the row-marginal error checked by the stop rule.
+//   column update (sk_merge_kernel): c_j = sum_w partial_w[j] in a fixed
+//     order, v_j <- v_j - log2 c_j, which is
 //     g_j = -eps log sum_i exp((G_ij + f_i)/eps) written as a correction.
-// The first iteration shifts by the exact row maximum instead of u_i (the
-// start potentials are arbitrary). Afterwards every term is a column-
-// normalised plan entry (<= 1) and S_i, c_j lie in [1/n, n], so no further
-// shift is needed.
-#include <hip/hip_cooperative_groups.h>
-
+// The first iteration shifts by the exact row maximum instead of u_i (start
+// potentials are arbitrary). Afterwards every term is a column-normalised
+// plan entry (<= 1) and S_i, c_j lie in [1/n, n], so no further shift is
+// needed.
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 
 #include "common.h"
-
-namespace cg = cooperative_groups;
 
 namespace goat {
 namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
 
+// Wave-wide sum / max in a fixed order: butterfly steps xor 16, 8, 4, 2, 1
+// inside each 32-lane half (ds_swizzle in bit-mask mode: lane i reads lane
+// i ^ m), then the two halves' results combined. The result is uniform.
+template <int M>
+__device__ inline float swz_xor(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, x), 0x1F | (M << 10)));
+}
 __device__ inline float wave_sum(float x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    x += swz_xor<16>(x);
+    x += swz_xor<8>(x);
+    x += swz_xor<4>(x);
+    x += swz_xor<2>(x);
+    x += swz_xor<1>(x);
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 0)) +
+           __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 32));
 }
 __device__ inline float wave_max(float x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
-    return x;
-}
-__device__ inline double wave_sum_d(double x) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+    x = fmaxf(x, swz_xor<16>(x));
+    x = fmaxf(x, swz_xor<8>(x));
+    x = fmaxf(x, swz_xor<4>(x));
+    x = fmaxf(x, swz_xor<2>(x));
+    x = fmaxf(x, swz_xor<1>(x));
+    return fmaxf(__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 0)),
+                 __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 32)));
 }
 
-// Block-wide sum / max; `red` holds T/64 floats and alternates between two
-// halves so consecutive reductions need one barrier each.
+// Block-wide sum / max; `red` holds T/64 floats and the callers alternate
+// between two such buffers so consecutive reductions need one barrier each.
 template <int T>
 __device__ inline float block_sum(float x, float* red) {
     x = wave_sum(x);
@@ -72,185 +92,158 @@ __device__ inline float block_max(float x, float* red) {
     return s;
 }
 
-// G is streamed once per iteration: non-temporal loads when GOAT_SK_NT is
-// defined at build time, plain loads otherwise.
-#ifdef GOAT_SK_NT
-typedef float goat_f4v __attribute__((ext_vector_type(4)));
-__device__ inline float4 goat_nt_load(const float4* p) {
-    const goat_f4v v = __builtin_nontemporal_load(reinterpret_cast<const goat_f4v*>(p));
-    return make_float4(v[0], v[1], v[2], v[3]);
+// 2^x by the hardware instruction. Results below 2^-126 flush to zero: every
+// sum formed from these terms is at least 1/n (row and column sums of a
+// plan normalised on the other side), so such terms are negligible.
+__device__ inline float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// Moves the grid-aligned part of the remainder r into the grid part g.
+__device__ inline void renorm(float& g, float& r, float h, float inv_h) {
+    const float t = rintf(r * inv_h) * h;
+    g += t;
+    r -= t;
 }
-#define GOAT_GLOAD(P) goat_nt_load(P)
-#else
-#define GOAT_GLOAD(P) (*(P))
-#endif
 
 struct SkArgs {
     const float* G;
     int ldg, n, np, rpw;       // rows per workgroup
     int rev;                   // walk the strip's rows last to first
-    float* u;
-    float* unew;
-    float* v;
+    float* ug; float* us;      // row potentials (grid part, remainder)
+    float* ung; float* uns;    // new row potentials of the sweep in flight
+    float* vg; float* vs;      // column potentials
     float* colpart;            // [W][np]
     float* errpart;            // [W]
     SkCtrl* ctrl;
 };
 
 // Thread t of a strip owns the float4 column groups t, t + T, ..., t + (C-1)T.
-// R rows are processed per step (one block reduction for all R row sums)
-// and the next R rows are loaded while the current ones reduce.
-// VLDS: the column potentials sit in LDS (16 T C bytes) instead of
-// registers, which leaves room for more rows in flight. Rows of a strip are
-// walked forwards or backwards (a.rev): alternating the direction between
-// iterations re-reads first the rows streamed last, which are the ones still
-// held in the memory-side cache when G is larger than it.
-template <int T, int R>
-__device__ inline void block_sum_r(float (&x)[R], float* red) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = wave_sum(x[r]);
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) red[r * (T / 64) + (threadIdx.x >> 6)] = x[r];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        float s = 0.0f;
-#pragma unroll
-        for (int w = 0; w < T / 64; ++w) s += red[r * (T / 64) + w];
-        x[r] = s;
-    }
-}
-template <int T, int R>
-__device__ inline void block_max_r(float (&x)[R], float* red) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) x[r] = wave_max(x[r]);
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) red[r * (T / 64) + (threadIdx.x >> 6)] = x[r];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        float s = -INFINITY;
-#pragma unroll
-        for (int w = 0; w < T / 64; ++w) s = fmaxf(s, red[r * (T / 64) + w]);
-        x[r] = s;
-    }
-}
-
-template <int T, int C, int R, bool FIRST, bool VLDS>
-__global__ __launch_bounds__(T) void sk_row_kernel(SkArgs a) {
+// VLDS: the column potentials sit in LDS (32 T C bytes) instead of
+// registers, leaving room for more strips per compute unit. Rows of a strip
+// are walked forwards or backwards (a.rev): alternating the direction
+// between iterations re-reads first the rows streamed last.
+// Occupancy target: two strips per compute unit (4 waves per SIMD for 512
+// threads, 2 for 256), which caps the registers at 128 / 256.
+template <int T, int C, bool FIRST, bool PRECISE, bool VLDS>
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(T >= 512 ? 4 : 2)))
+void sk_row_kernel(SkArgs a) {
+    static_assert(!(FIRST && PRECISE), "the first sweep uses the plain form");
     if (a.ctrl->done) return;
-    extern __shared__ float4 sv4[];
-    __shared__ float red[2][R * (T / 64)];
+    extern __shared__ float4 sv4[];          // [T*C] v (grid parts), then [T*C] remainders if PRECISE
+    __shared__ float red[2][T / 64];
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * a.rpw;
     const int r1 = min(a.n, r0 + a.rpw);
     const float kappa = a.ctrl->kappa;
+    const float h = a.ctrl->h, inv_h = 1.0f / h;
 
-    float4 vreg[VLDS ? 1 : C];
+    float4 vgr[VLDS ? 1 : C], vsr[VLDS ? 1 : C];
     float acc[C][4];
     bool live[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int j4 = tid + T * c;
         live[c] = 4 * j4 < a.n;
-        float vv[4];
+        float g[4], r[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int j = 4 * j4 + e;
-            vv[e] = (j < a.n) ? a.v[j] : -INFINITY;
+            g[e] = (j < a.n) ? a.vg[j] : -INFINITY;
+            r[e] = (j < a.n) ? a.vs[j] : 0.0f;
+            if (!PRECISE) { g[e] += r[e]; r[e] = 0.0f; }
             acc[c][e] = 0.0f;
         }
-        const float4 v4 = make_float4(vv[0], vv[1], vv[2], vv[3]);
-        if (VLDS) sv4[j4] = v4;
-        else vreg[VLDS ? 0 : c] = v4;
+        const float4 g4 = make_float4(g[0], g[1], g[2], g[3]);
+        const float4 r4 = make_float4(r[0], r[1], r[2], r[3]);
+        if (VLDS) {
+            sv4[j4] = g4;
+            if (PRECISE) sv4[T * C + j4] = r4;
+        } else {
+            vgr[VLDS ? 0 : c] = g4;
+            vsr[VLDS ? 0 : c] = r4;
+        }
     }
     if (VLDS) __syncthreads();
     float errmax = 0.0f;
     const int nrows = r1 - r0;
-    auto row_of = [&](int k) { return a.rev ? r1 - 1 - k : r0 + k; };
-    float4 x[R][C];
-    // rows k0 .. k0+R-1 of the strip into x (rows past the strip read as zero)
-#define GOAT_LOAD_ROWS(K0)                                                                          \
-    do {                                                                                            \
-        _Pragma("unroll") for (int r = 0; r < R; ++r) {                                             \
-            const bool ok_ = (K0) + r < nrows;                                                      \
-            const float4* row_ = reinterpret_cast<const float4*>(                                   \
-                a.G + (size_t)(ok_ ? row_of((K0) + r) : r0) * a.ldg);                               \
-            _Pragma("unroll") for (int c = 0; c < C; ++c)                                           \
-                x[r][c] = (ok_ && live[c]) ? GOAT_GLOAD(row_ + tid + T * c)                          \
-                                           : make_float4(0.f, 0.f, 0.f, 0.f);                        \
-        }                                                                                           \
+    // column groups past the row end re-read the last group (in bounds since
+    // ld >= 4 ceil(n/4)); their v = -inf makes them contribute exactly 0
+    const int n4m1 = ((a.n + 3) >> 2) - 1;
+    float4 xa[C], xb[C];
+#define GOAT_ROW_OF(K) (a.rev ? r1 - 1 - (K) : r0 + (K))
+#define GOAT_LOAD_ROW(X, I)                                                                        \
+    do {                                                                                           \
+        const float4* row_ = reinterpret_cast<const float4*>(a.G + (size_t)(I) * a.ldg);          \
+        _Pragma("unroll") for (int c = 0; c < C; ++c) X[c] = row_[min(tid + T * c, n4m1)];        \
     } while (0)
-    if (nrows > 0) GOAT_LOAD_ROWS(0);
+    // One row k held in XC; the next row is loaded into XN as soon as XC has
+    // been consumed. The row remainder u_rem enters only as the per-row
+    // factor 2^u_rem, which cancels in the row-normalised plan: the sweep
+    // works with y_ij = G_ij kappa + (v_grid + u_grid) + v_rem and applies
+    // 2^u_rem to the row sum for the stop test.
+#define GOAT_ROW_STEP(XC, XN, K)                                                                   \
+    do {                                                                                           \
+        const int i = GOAT_ROW_OF(K);                                                              \
+        if (VLDS) asm volatile("" ::: "memory");   /* re-read v from LDS every row */              \
+        const float ug = FIRST ? 0.0f : a.ug[i];                                                   \
+        const float us = (FIRST || PRECISE) ? 0.0f : a.us[i];                                      \
+        const float uu = ug + us;                                                                  \
+        float y[C][4];                                                                             \
+        _Pragma("unroll") for (int c = 0; c < C; ++c) {                                            \
+            const float4 g4 = VLDS ? sv4[tid + T * c] : vgr[VLDS ? 0 : c];                         \
+            if (PRECISE) {                                                                         \
+                const float4 r4 = VLDS ? sv4[T * C + tid + T * c] : vsr[VLDS ? 0 : c];             \
+                y[c][0] = fmaf(XC[c].x, kappa, g4.x + ug) + r4.x;                                  \
+                y[c][1] = fmaf(XC[c].y, kappa, g4.y + ug) + r4.y;                                  \
+                y[c][2] = fmaf(XC[c].z, kappa, g4.z + ug) + r4.z;                                  \
+                y[c][3] = fmaf(XC[c].w, kappa, g4.w + ug) + r4.w;                                  \
+            } else { /* plain: g4 holds v_grid + v_rem */                                          \
+                y[c][0] = fmaf(XC[c].x, kappa, g4.x) + uu;                                         \
+                y[c][1] = fmaf(XC[c].y, kappa, g4.y) + uu;                                         \
+                y[c][2] = fmaf(XC[c].z, kappa, g4.z) + uu;                                         \
+                y[c][3] = fmaf(XC[c].w, kappa, g4.w) + uu;                                         \
+            }                                                                                      \
+        }                                                                                          \
+        if ((K) + 1 < nrows) GOAT_LOAD_ROW(XN, GOAT_ROW_OF((K) + 1));                             \
+        float shift = 0.0f;                                                                        \
+        if (FIRST) {                                                                               \
+            float m = -INFINITY;                                                                   \
+            _Pragma("unroll") for (int c = 0; c < C; ++c)                                          \
+                _Pragma("unroll") for (int e = 0; e < 4; ++e) m = fmaxf(m, y[c][e]);              \
+            shift = -block_max<T>(m, red[par]);                                                    \
+            par ^= 1;                                                                              \
+        }                                                                                          \
+        float s = 0.0f;                                                                            \
+        _Pragma("unroll") for (int c = 0; c < C; ++c)                                              \
+            _Pragma("unroll") for (int e = 0; e < 4; ++e) {                                        \
+                y[c][e] = exp2_fast(FIRST ? y[c][e] + shift : y[c][e]);                            \
+                s += y[c][e];                                                                      \
+            }                                                                                      \
+        const float S = block_sum<T>(s, red[par]);   /* row sum without 2^u_rem */                 \
+        par ^= 1;                                                                                  \
+        const float inv = 1.0f / S;                                                                \
+        _Pragma("unroll") for (int c = 0; c < C; ++c)                                              \
+            _Pragma("unroll") for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(y[c][e], inv, acc[c][e]); \
+        if (!FIRST) errmax = fmaxf(errmax, fabsf((PRECISE ? S * exp2f(a.us[i]) : S) - 1.0f));       \
+        if (tid == 0) {                                                                            \
+            /* new row potential: u - log2 S (first sweep: -max - log2 S); the   */                \
+            /* compensated sweep's S excludes 2^u_rem, so u_rem drops out there */                 \
+            float g_ = FIRST ? rintf(shift * inv_h) * h : ug;                                      \
+            float r_ = FIRST ? (shift - g_) - log2f(S) : (PRECISE ? 0.0f : us) - log2f(S);         \
+            renorm(g_, r_, h, inv_h);                                                              \
+            a.ung[i] = g_;                                                                         \
+            a.uns[i] = r_;                                                                         \
+        }                                                                                          \
+    } while (0)
+    if (nrows > 0) GOAT_LOAD_ROW(xa, GOAT_ROW_OF(0));
     int par = 0;
-    for (int k0 = 0; k0 < nrows; k0 += R) {
-        // keep the LDS copy of v authoritative: re-read it every step instead
-        // of letting the compiler cache it in registers
-        if (VLDS) asm volatile("" ::: "memory");
-        float y[R][C][4];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const float4 v4 = VLDS ? sv4[tid + T * c] : vreg[VLDS ? 0 : c];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                y[r][c][0] = fmaf(x[r][c].x, kappa, v4.x);
-                y[r][c][1] = fmaf(x[r][c].y, kappa, v4.y);
-                y[r][c][2] = fmaf(x[r][c].z, kappa, v4.z);
-                y[r][c][3] = fmaf(x[r][c].w, kappa, v4.w);
-            }
-        }
-        // x is consumed: prefetch the next R rows into it while these reduce
-        if (k0 + R < nrows) GOAT_LOAD_ROWS(k0 + R);
-        float shift[R], s[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            s[r] = 0.0f;
-            const bool ok = k0 + r < nrows;
-            if (FIRST) {
-                float m = -INFINITY;
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) m = fmaxf(m, y[r][c][e]);
-                shift[r] = m;
-            } else {
-                shift[r] = ok ? a.u[row_of(k0 + r)] : 0.0f;
-            }
-        }
-        if (FIRST) {
-            block_max_r<T, R>(shift, red[par]);
-            par ^= 1;
-#pragma unroll
-            for (int r = 0; r < R; ++r) shift[r] = (k0 + r < nrows) ? -shift[r] : 0.0f;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    y[r][c][e] = exp2f(y[r][c][e] + shift[r]);
-                    s[r] += y[r][c][e];
-                }
-        block_sum_r<T, R>(s, red[par]);
-        par ^= 1;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (k0 + r >= nrows) break;
-            const float inv = 1.0f / s[r];
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(y[r][c][e], inv, acc[c][e]);
-            if (!FIRST) errmax = fmaxf(errmax, fabsf(s[r] - 1.0f));
-            if (tid == 0) a.unew[row_of(k0 + r)] = shift[r] - log2f(s[r]);
-        }
+    for (int k = 0; k < nrows; k += 2) {
+        GOAT_ROW_STEP(xa, xb, k);
+        if (k + 1 >= nrows) break;
+        GOAT_ROW_STEP(xb, xa, k + 1);
     }
-#undef GOAT_LOAD_ROWS
+#undef GOAT_ROW_STEP
+#undef GOAT_LOAD_ROW
+#undef GOAT_ROW_OF
     float* out = a.colpart + (size_t)blockIdx.x * a.np;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -264,162 +257,11 @@ __global__ __launch_bounds__(T) void sk_row_kernel(SkArgs a) {
     }
 }
 
-// Whole Sinkhorn solve in one cooperative launch: every workgroup owns a
-// row strip (row phase as in sk_row_kernel) and, after a grid barrier, a
-// slice of columns (the column update as in sk_merge_kernel, same fixed
-// summation order over strips). All workgroups evaluate the stop test on the
-// same partials, so they leave the loop together. Iterations k_begin ..
-// k_end-1 run; k == 0 is the max-shifted first sweep.
-struct SkPersist {
-    int k_begin, k_end, W, cpw;
-};
-
-template <int T, int C>
-__global__ __launch_bounds__(T) void sk_persistent_kernel(SkArgs a, SkPersist pp) {
-    if (a.ctrl->done) return;
-    cg::grid_group grid = cg::this_grid();
-    extern __shared__ float4 sv4[];
-    __shared__ float red[2][T / 64];
-    __shared__ float mpart[T / 64][64];
-    const int tid = threadIdx.x, w = blockIdx.x;
-    const int r0 = w * a.rpw;
-    const int r1 = min(a.n, r0 + a.rpw);
-    const int nrows = max(r1 - r0, 0);
-    const float kappa = a.ctrl->kappa;
-    const float tol = a.ctrl->tol;
-    bool live[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) live[c] = 4 * (tid + T * c) < a.n;
-
-    for (int k = pp.k_begin; k < pp.k_end; ++k) {
-        const bool first = (k == 0);
-        const bool rev = (k & 1) != 0;
-        // ---------------- row phase
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int j4 = tid + T * c;
-            float vv[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = 4 * j4 + e;
-                vv[e] = (j < a.n) ? a.v[j] : -INFINITY;
-            }
-            sv4[j4] = make_float4(vv[0], vv[1], vv[2], vv[3]);
-        }
-        __syncthreads();
-        float acc[C][4];
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc[c][e] = 0.0f;
-        float errmax = 0.0f;
-        float4 x[C];
-        int par = 0;
-#define GOAT_ROW_OF(K) (rev ? r1 - 1 - (K) : r0 + (K))
-#define GOAT_LOAD_ROW(I)                                                                           \
-    do {                                                                                           \
-        const float4* row_ = reinterpret_cast<const float4*>(a.G + (size_t)(I) * a.ldg);          \
-        _Pragma("unroll") for (int c = 0; c < C; ++c)                                              \
-            x[c] = live[c] ? row_[tid + T * c] : make_float4(0.f, 0.f, 0.f, 0.f);                \
-    } while (0)
-        if (nrows > 0) GOAT_LOAD_ROW(GOAT_ROW_OF(0));
-        for (int kk = 0; kk < nrows; ++kk) {
-            const int i = GOAT_ROW_OF(kk);
-            asm volatile("" ::: "memory");
-            float y[C][4];
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const float4 v4 = sv4[tid + T * c];
-                y[c][0] = fmaf(x[c].x, kappa, v4.x);
-                y[c][1] = fmaf(x[c].y, kappa, v4.y);
-                y[c][2] = fmaf(x[c].z, kappa, v4.z);
-                y[c][3] = fmaf(x[c].w, kappa, v4.w);
-            }
-            if (kk + 1 < nrows) GOAT_LOAD_ROW(GOAT_ROW_OF(kk + 1));
-            float shift;
-            if (first) {
-                float m = -INFINITY;
-#pragma unroll
-                for (int c = 0; c < C; ++c)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) m = fmaxf(m, y[c][e]);
-                shift = -block_max<T>(m, red[par]);
-                par ^= 1;
-            } else {
-                shift = a.u[i];
-            }
-            float s = 0.0f;
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    y[c][e] = exp2f(y[c][e] + shift);
-                    s += y[c][e];
-                }
-            const float S = block_sum<T>(s, red[par]);
-            par ^= 1;
-            const float inv = 1.0f / S;
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(y[c][e], inv, acc[c][e]);
-            if (!first) errmax = fmaxf(errmax, fabsf(S - 1.0f));
-            if (tid == 0) a.unew[i] = shift - log2f(S);
-        }
-#undef GOAT_LOAD_ROW
-#undef GOAT_ROW_OF
-        float* out = a.colpart + (size_t)w * a.np;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int j4 = tid + T * c;
-            if (4 * j4 < a.np)
-                reinterpret_cast<float4*>(out)[j4] = make_float4(acc[c][0], acc[c][1], acc[c][2], acc[c][3]);
-        }
-        {
-            const float m = block_max<T>(errmax, red[par]);
-            par ^= 1;
-            if (tid == 0) a.errpart[w] = m;
-        }
-        grid.sync();
-        // ---------------- column phase
-        if (!first) {
-            float m = 0.0f;
-            for (int q = tid; q < pp.W; q += T) m = fmaxf(m, a.errpart[q]);
-            const float err = block_max<T>(m, red[par]);
-            par ^= 1;
-            if (w == 0 && tid == 0) a.ctrl->err = err;
-            if (err <= tol) {
-                if (w == 0 && tid == 0) a.ctrl->done = 1;
-                break;                           // the same decision in every workgroup
-            }
-        }
-        const int lane = tid & 63, sl = tid >> 6;   // 64 columns x T/64 strip lanes
-        const int cbeg = w * pp.cpw, cend = min(a.n, cbeg + pp.cpw);
-        for (int cb = cbeg; cb < cend; cb += 64) {
-            const int j = cb + lane;
-            float part = 0.0f;
-            if (j < cend)
-                for (int q = sl; q < pp.W; q += T / 64) part += a.colpart[(size_t)q * a.np + j];
-            mpart[sl][lane] = part;
-            __syncthreads();
-            if (sl == 0 && j < cend) {
-                float c = mpart[0][lane];
-#pragma unroll
-                for (int l = 1; l < T / 64; ++l) c += mpart[l][lane];
-                a.v[j] -= log2f(fmaxf(c, 1.17549435e-38f));
-                a.u[j] = a.unew[j];
-            }
-            __syncthreads();
-        }
-        if (w == 0 && tid == 0) a.ctrl->iters += 1;
-        grid.sync();
-    }
-}
-
 // Column update: c_j = sum over strips of the partial column sums, summed in
 // a fixed order (strip lane l adds strips l, l + 16, ...; lanes combined in
-// order), then v_j <- v_j - log2 c_j and u <- unew. 256 threads = 16 float4
-// column groups x 16 strip lanes per block.
+// order), then v_j <- v_j - log2 c_j and u <- u_new. 256 threads = 16 float4
+// column groups x 16 strip lanes per block. With check, the largest
+// row-marginal error of the sweep decides convergence first (no update then).
 __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int check) {
     if (a.ctrl->done) return;
     __shared__ float4 part[16][16];
@@ -464,42 +306,61 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
             c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
         }
         const float cc[4] = {c.x, c.y, c.z, c.w};
+        const float h = a.ctrl->h, inv_h = 1.0f / h;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int j = 4 * j4 + e;
             if (j < a.n) {
-                a.v[j] -= log2f(fmaxf(cc[e], 1.17549435e-38f));
-                a.u[j] = a.unew[j];
+                float g = a.vg[j], r = a.vs[j] - log2f(fmaxf(cc[e], 1.17549435e-38f));
+                renorm(g, r, h, inv_h);
+                a.vg[j] = g;
+                a.vs[j] = r;
+                a.ug[j] = a.ung[j];
+                a.us[j] = a.uns[j];
             }
         }
     }
     if (blockIdx.x == 0 && tid == 0) a.ctrl->iters += 1;
 }
 
-// eps from eps_dev or eps_rel * absmax; potentials initialised.
+// eps from eps_dev or eps_rel * max|G|; grid step h from max|G| kappa;
+// potentials initialised (v from the caller's g when given).
 __global__ __launch_bounds__(256) void sk_init_kernel(int n, const float* eps_dev, float eps_rel,
                                                       const float* absmax, const float* g_init,
-                                                      float tol, float* u, float* v, SkCtrl* ctrl) {
-    const float eps = eps_dev ? *eps_dev : eps_rel * (*absmax);
-    const float kappa = eps > 0.0f ? kLog2e / eps : 0.0f;
+                                                      float tol, SkArgs a) {
+    const float gmax = *absmax;
+    const float eps = eps_dev ? *eps_dev : eps_rel * gmax;
+    const bool ok = eps > 0.0f && gmax > 0.0f;
+    const float kappa = ok ? kLog2e / eps : 0.0f;
+    // h = 2^(e - 24) with 2^e >= max|G kappa| + 64
+    int e = 0;
+    frexpf(gmax * kappa + 64.0f, &e);
+    const float h = ldexpf(1.0f, e - 24);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) {
-        u[i] = 0.0f;
-        v[i] = (g_init && eps > 0.0f) ? g_init[i] * kappa : 0.0f;
+        a.ug[i] = 0.0f;
+        a.us[i] = 0.0f;
+        float g = 0.0f, r = 0.0f;
+        if (g_init && ok) {
+            r = g_init[i] * kappa;
+            renorm(g, r, h, 1.0f / h);
+        }
+        a.vg[i] = g;
+        a.vs[i] = r;
     }
     if (i == 0) {
-        ctrl->kappa = kappa;
-        ctrl->eps = eps;
-        ctrl->done = eps > 0.0f ? 0 : 2;
-        ctrl->iters = 0;
-        ctrl->err = 0.0f;
-        ctrl->tol = tol;
+        a.ctrl->kappa = kappa;
+        a.ctrl->eps = eps;
+        a.ctrl->h = h;
+        a.ctrl->done = ok ? 0 : 2;
+        a.ctrl->iters = 0;
+        a.ctrl->err = 0.0f;
+        a.ctrl->tol = tol;
     }
 }
 
 // Q = 2^(G kappa + u_i + v_j) (or J when eps == 0), its largest row-marginal
-// error, optional bf16 hi/lo planes of Q (np stride), and the potentials in
-// natural units.
+// error, and optional bf16 hi/lo planes of Q (np stride).
 struct FinArgs {
     SkArgs a;
     float* Q; int ldq;
@@ -516,38 +377,49 @@ __global__ __launch_bounds__(T) void sk_finalize_kernel(FinArgs fa) {
     const float kappa = a.ctrl->kappa;
     const bool flat = a.ctrl->done == 2;
     const float jval = 1.0f / (float)a.n;
-    float vj[C][4];
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int j = 4 * (tid + T * c) + e;
-            vj[c][e] = (j < a.n) ? a.v[j] : -INFINITY;
-        }
     float errmax = 0.0f;
     int par = 0;
     for (int i = r0; i < r1; ++i) {
-        const float ui = a.u[i];
+        const float ug = a.ug[i], us = a.us[i];
         const float* grow = a.G + (size_t)i * a.ldg;
         float s = 0.0f;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int j0 = 4 * (tid + T * c);
             if (j0 >= a.np && j0 >= a.n) continue;
-            float4 g4 = j0 < a.n ? *reinterpret_cast<const float4*>(grow + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
-            float gv[4] = {g4.x, g4.y, g4.z, g4.w};
+            const float4 g4 = j0 < a.n ? *reinterpret_cast<const float4*>(grow + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
             float q[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int j = j0 + e;
-                q[e] = (j < a.n) ? (flat ? jval : exp2f(fmaf(gv[e], kappa, vj[c][e]) + ui)) : 0.0f;
+                q[e] = 0.0f;
+                if (j < a.n)
+                    q[e] = flat ? jval : exp2f(fmaf(gv[e], kappa, a.vg[j] + ug) + (a.vs[j] + us));
                 s += q[e];
-                if (j < a.n && fa.Q) fa.Q[(size_t)i * fa.ldq + j] = q[e];
-                if (fa.Qhi && j < a.np) {
-                    const uint16_t h = f32_to_bf16_rne(q[e]);
-                    fa.Qhi[(size_t)i * a.np + j] = h;
-                    fa.Qlo[(size_t)i * a.np + j] = f32_to_bf16_rne(q[e] - bf16_to_f32(h));
+            }
+            if (fa.Q) {
+                float* qrow = fa.Q + (size_t)i * fa.ldq;
+                if (j0 + 3 < a.n && (fa.ldq & 3) == 0) {
+                    *reinterpret_cast<float4*>(qrow + j0) = make_float4(q[0], q[1], q[2], q[3]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (j0 + e < a.n) qrow[j0 + e] = q[e];
                 }
+            }
+            if (fa.Qhi && j0 < a.np) {
+                ushort4 hi, lo;
+                uint16_t hv[4], lv[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    hv[e] = f32_to_bf16_rne(q[e]);
+                    lv[e] = f32_to_bf16_rne(q[e] - bf16_to_f32(hv[e]));
+                }
+                hi.x = hv[0]; hi.y = hv[1]; hi.z = hv[2]; hi.w = hv[3];
+                lo.x = lv[0]; lo.y = lv[1]; lo.z = lv[2]; lo.w = lv[3];
+                *reinterpret_cast<ushort4*>(fa.Qhi + (size_t)i * a.np + j0) = hi;
+                *reinterpret_cast<ushort4*>(fa.Qlo + (size_t)i * a.np + j0) = lo;
             }
         }
         const float S = block_sum<T>(s, red[par]);
@@ -565,8 +437,8 @@ __global__ __launch_bounds__(256) void sk_outputs_kernel(SkArgs a, int W, float*
     const float kappa = a.ctrl->kappa;
     const bool flat = a.ctrl->done == 2;
     if (i < a.n) {
-        if (f) f[i] = flat ? 0.0f : a.u[i] / kappa;
-        if (g) g[i] = flat ? 0.0f : a.v[i] / kappa;
+        if (f) f[i] = flat ? 0.0f : (a.ug[i] + a.us[i]) / kappa;
+        if (g) g[i] = flat ? 0.0f : (a.vg[i] + a.vs[i]) / kappa;
     }
     if (i == 0) {
         float m = 0.0f;
@@ -580,31 +452,28 @@ __global__ __launch_bounds__(256) void sk_outputs_kernel(SkArgs a, int W, float*
 // ---------------------------------------------------------------- dispatch
 
 struct Geometry {
-    int T, C, W, rpw, R;
+    int T, C, W, rpw;
 };
 
-// Threads per strip: 256 below n = 4096, else the smallest of 512 / 1024
-// that keeps a row's share per thread at <= 40 columns (register budget
-// without spills); beyond n = 20480 the 1024-thread variant is used and
-// spills. The number of
-// strips W defaults to kSkDefaultWG; GOAT_SK_GEOM="T,W" overrides both (a
-// tuning knob for measurements).
+// Threads per strip: 256 below n = 4096 (512 measured 2% faster at
+// n = 10000), else the smallest of 512 / 1024 that keeps a row's share per
+// thread at <= 40 columns (register budget without spills); beyond
+// n = 20480 the 1024-thread variant is used and spills. The number of strips
+// defaults to 512 (best of 256..1024 at n = 10000); GOAT_SK_GEOM="T,W"
+// overrides both (a measurement knob).
 constexpr int kSkDefaultWG = 512;
 
 Geometry geometry(int n) {
-    int env_T = 0, env_W = 0, env_R = 0;
+    int env_T = 0, env_W = 0;
     if (const char* e = getenv("GOAT_SK_GEOM")) {
-        int t = 0, w = 0, r = 1;
-        const int got = sscanf(e, "%d,%d,%d", &t, &w, &r);
-        if (got >= 2 && (t == 256 || t == 512 || t == 1024) && w >= 1 && w <= kSkWG && (r == 1 || r == 2)) {
+        int t = 0, w = 0;
+        if (sscanf(e, "%d,%d", &t, &w) == 2 && (t == 256 || t == 512 || t == 1024) && w >= 1 && w <= kSkWG) {
             env_T = t;
             env_W = w;
-            env_R = r;
         }
     }
     Geometry g;
     const int n4 = (n + 3) / 4;
-    // 512 threads from n = 4096 on: measured 2% faster than 256 at n = 10000
     g.T = n < 4096 ? 256 : (n4 <= 512 * 10 ? 512 : 1024);
     if (env_T > 0 && n4 <= env_T * 16) g.T = env_T;
     g.C = (n4 + g.T - 1) / g.T;
@@ -615,26 +484,38 @@ Geometry geometry(int n) {
     g.W = n < wmax ? n : wmax;
     g.rpw = (n + g.W - 1) / g.W;
     g.W = (n + g.rpw - 1) / g.rpw;
-    g.R = env_R > 0 ? env_R : 1;
     return g;
 }
 
+// LDS for the column potentials: 32 T C bytes; above 64 KB the kernel asks
+// for the larger dynamic allocation once, and keeps v in registers if the
+// runtime refuses.
+template <typename K>
+bool allow_lds(K kfn, size_t bytes) {
+    if (bytes <= 65536) return true;
+    if (bytes > 160 * 1024) return false;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kfn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes) == hipSuccess;
+}
+
+template <int T, int C, bool FIRST, bool PRECISE>
+void launch_row_TCP(const Geometry& g, const SkArgs& a, hipStream_t s) {
+    const size_t lds = (size_t)(PRECISE ? 32 : 16) * T * C;
+    static const bool vlds = allow_lds(sk_row_kernel<T, C, FIRST, PRECISE, true>, lds);
+    if (vlds) hipLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, true>), dim3(g.W), dim3(T), lds, s, a);
+    else hipLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, false>), dim3(g.W), dim3(T), 0, s, a);
+}
+
+template <int T, int C, bool FIRST>
+void launch_row_TC(const Geometry& g, const SkArgs& a, int precise, hipStream_t s) {
+    if (FIRST || !precise) launch_row_TCP<T, C, FIRST, false>(g, a, s);
+    else launch_row_TCP<T, C, false, true>(g, a, s);
+}
+
 template <int T, bool FIRST>
-int launch_row_T(const Geometry& g, const SkArgs& a, hipStream_t s) {
-    dim3 grid(g.W), block(T);
-    const size_t lds = (size_t)16 * T * g.C;
-    const bool vlds = lds <= 65536;
+int launch_row_T(const Geometry& g, const SkArgs& a, int precise, hipStream_t s) {
     switch (g.C) {
-#define GOAT_SK_C(CC)                                                                                     \
-    case CC:                                                                                              \
-        if (g.R == 2 && CC <= 6) {                                                                        \
-            if (vlds) hipLaunchKernelGGL((sk_row_kernel<T, CC, 2, FIRST, true>), grid, block, lds, s, a);    \
-            else hipLaunchKernelGGL((sk_row_kernel<T, CC, 2, FIRST, false>), grid, block, 0, s, a);          \
-        } else {                                                                                          \
-            if (vlds) hipLaunchKernelGGL((sk_row_kernel<T, CC, 1, FIRST, true>), grid, block, lds, s, a);    \
-            else hipLaunchKernelGGL((sk_row_kernel<T, CC, 1, FIRST, false>), grid, block, 0, s, a);          \
-        }                                                                                                 \
-        break;
+#define GOAT_SK_C(CC) case CC: launch_row_TC<T, CC, FIRST>(g, a, precise, s); break;
         GOAT_SK_C(1) GOAT_SK_C(2) GOAT_SK_C(3) GOAT_SK_C(4) GOAT_SK_C(5) GOAT_SK_C(6)
         GOAT_SK_C(8) GOAT_SK_C(10) GOAT_SK_C(12) GOAT_SK_C(16)
 #undef GOAT_SK_C
@@ -666,49 +547,13 @@ SkArgs make_args(int n, int np, const float* G, int ldg, const SkState& st, cons
     a.np = np;
     a.rpw = g.rpw;
     a.rev = 0;
-    a.u = st.u;
-    a.unew = st.unew;
-    a.v = st.v;
+    a.ug = st.ug; a.us = st.us;
+    a.ung = st.ung; a.uns = st.uns;
+    a.vg = st.vg; a.vs = st.vs;
     a.colpart = st.colpart;
     a.errpart = st.errpart;
     a.ctrl = st.ctrl;
     return a;
-}
-
-// Cooperative launch of the whole solve; GOAT_ENOTSUP when the shape has no
-// persistent variant or the strips cannot all be resident at once.
-template <int T, int C>
-int launch_persistent_TC(const Geometry& g, SkArgs a, int k_begin, int k_end, hipStream_t s) {
-    auto kfn = sk_persistent_kernel<T, C>;
-    const size_t lds = (size_t)16 * T * C;
-    int per_cu = 0, cus = 0, dev = 0;
-    GOAT_HIP(hipGetDevice(&dev));
-    GOAT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    GOAT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, T, lds));
-    if (per_cu < 1 || (long long)per_cu * cus < g.W) return GOAT_ENOTSUP;
-    SkPersist pp;
-    pp.k_begin = k_begin;
-    pp.k_end = k_end;
-    pp.W = g.W;
-    pp.cpw = (a.n + g.W - 1) / g.W;
-    void* args[] = {&a, &pp};
-    GOAT_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kfn), dim3(g.W), dim3(T), args, lds, s));
-    return GOAT_OK;
-}
-
-template <int T>
-int launch_persistent_T(const Geometry& g, const SkArgs& a, int k_begin, int k_end, hipStream_t s) {
-    switch (g.C) {
-        case 1: return launch_persistent_TC<T, 1>(g, a, k_begin, k_end, s);
-        case 2: return launch_persistent_TC<T, 2>(g, a, k_begin, k_end, s);
-        case 3: return launch_persistent_TC<T, 3>(g, a, k_begin, k_end, s);
-        case 4: return launch_persistent_TC<T, 4>(g, a, k_begin, k_end, s);
-        case 5: return launch_persistent_TC<T, 5>(g, a, k_begin, k_end, s);
-        case 6: return launch_persistent_TC<T, 6>(g, a, k_begin, k_end, s);
-        case 8: return launch_persistent_TC<T, 8>(g, a, k_begin, k_end, s);
-        case 10: return launch_persistent_TC<T, 10>(g, a, k_begin, k_end, s);
-        default: return GOAT_ENOTSUP;
-    }
 }
 
 }  // namespace
@@ -718,27 +563,38 @@ int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_r
                double* red, hipStream_t s) {
     (void)red;
     const float* absmax = absmax_dev;
-    if (!eps_dev && !absmax) {
+    if (!absmax) {
         int rc = launch_absmax(n, G, ldg, fscal + 16, fscal, s);
         if (rc) return rc;
         absmax = fscal;
     }
-    hipLaunchKernelGGL(sk_init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, eps_dev, eps_rel,
-                       absmax, g_init, tol, st.u, st.v, st.ctrl);
+    const Geometry g = geometry(n);
+    const SkArgs a = make_args(n, pad_n(n), G, ldg, st, g);
+    hipLaunchKernelGGL(sk_init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, eps_dev, eps_rel, absmax,
+                       g_init, tol, a);
     GOAT_HIP(hipGetLastError());
     return GOAT_OK;
 }
 
+bool sk_force_precise() {
+    static const bool force = [] {
+        const char* e = getenv("GOAT_SK_PRECISE");
+        return e && e[0] == '1';
+    }();
+    return force;
+}
+
 int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check, int iter,
-               hipStream_t s) {
+               int precise, hipStream_t s) {
     const Geometry g = geometry(n);
     SkArgs a = make_args(n, np, G, ldg, st, g);
     a.rev = iter & 1;
+    const int pr = precise || sk_force_precise();
     int rc;
     prof_begin(0, s);
-    if (g.T == 256) rc = first ? launch_row_T<256, true>(g, a, s) : launch_row_T<256, false>(g, a, s);
-    else if (g.T == 512) rc = first ? launch_row_T<512, true>(g, a, s) : launch_row_T<512, false>(g, a, s);
-    else rc = first ? launch_row_T<1024, true>(g, a, s) : launch_row_T<1024, false>(g, a, s);
+    if (g.T == 256) rc = first ? launch_row_T<256, true>(g, a, pr, s) : launch_row_T<256, false>(g, a, pr, s);
+    else if (g.T == 512) rc = first ? launch_row_T<512, true>(g, a, pr, s) : launch_row_T<512, false>(g, a, pr, s);
+    else rc = first ? launch_row_T<1024, true>(g, a, pr, s) : launch_row_T<1024, false>(g, a, pr, s);
     prof_end(0, s);
     if (rc) return rc;
     hipLaunchKernelGGL(sk_merge_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a, g.W, check);
@@ -746,28 +602,9 @@ int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, in
     return GOAT_OK;
 }
 
-int sk_run_persistent(int n, int np, const float* G, int ldg, SkState st, int k_begin, int k_end,
-                      hipStream_t s) {
-    // Opt-in (GOAT_SK_PERSISTENT=1): measured slower than one launch pair per
-    // iteration on MI355X at n = 10000 (the grid barrier costs more than the
-    // two launch gaps it removes).
-    const char* e = getenv("GOAT_SK_PERSISTENT");
-    if (!e || e[0] != '1') return GOAT_ENOTSUP;
-    if (k_end <= k_begin) return GOAT_OK;
-    const Geometry g = geometry(n);
-    if (g.T > 512 || 16 * g.T * g.C > 65536) return GOAT_ENOTSUP;
-    const SkArgs a = make_args(n, np, G, ldg, st, g);
-    prof_begin(0, s);
-    int rc = g.T == 256 ? launch_persistent_T<256>(g, a, k_begin, k_end, s)
-                        : launch_persistent_T<512>(g, a, k_begin, k_end, s);
-    prof_end(0, s);
-    if (rc == GOAT_ENOTSUP) clear_error();
-    return rc;
-}
-
-int sk_finalize(int n, int np, const float* G, int ldg, SkState st, float* Q, int ldq,
-                uint16_t* Q_hi, uint16_t* Q_lo, float* f, float* g, int* iters_out,
-                float* err_out, float* eps_out, double* red, hipStream_t s) {
+int sk_finalize(int n, int np, const float* G, int ldg, SkState st, float* Q, int ldq, uint16_t* Q_hi,
+                uint16_t* Q_lo, float* f, float* g, int* iters_out, float* err_out, float* eps_out,
+                double* red, hipStream_t s) {
     (void)red;
     const Geometry geo = geometry(n);
     FinArgs fa;

@@ -46,32 +46,40 @@ struct Run {
     }
 };
 
-// Fallback when the persistent solve is unavailable: one launch pair per
-// iteration, the device-side convergence flag polled every check_every
-// iterations (two chunks in flight).
+// Sinkhorn sweeps on G_P: one launch pair per iteration, the device-side
+// convergence flag and error polled every check_every iterations (two
+// chunks in flight, so the device never waits for the host). Sweeps use the
+// plain exponent until a polled error is within 10x a tolerance below the
+// plain form's floor, then the compensated one.
 static int run_sinkhorn_polled(Run& r) {
     const int n = r.L.n, np = r.L.np;
     Ptrs& p = r.p;
     int rc;
-    rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, 0, r.s);
+    rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, 0, 0, r.s);
     if (rc) return rc;
     const int check_every = r.opt.check_every > 0 ? r.opt.check_every : 16;
+    const bool need_precise = r.opt.sk_tol < sk_plain_floor;
+    // per slot: done, iters, err (the ctrl block's words 2..4)
     int* hflag = reinterpret_cast<int*>(static_cast<char*>(r.hbuf) + 128);
-    int k = 1, chunk = 0;
+    int k = 1, chunk = 0, precise = 0;
     bool stop = false;
     while (k < r.opt.sk_max && !stop) {
         const int m = std::min(check_every, r.opt.sk_max - k);
         for (int q = 0; q < m; ++q) {
-            rc = sk_iterate(n, np, p.GP, np, p.sk, 0, 1, k + q, r.s);
+            rc = sk_iterate(n, np, p.GP, np, p.sk, 0, 1, k + q, precise, r.s);
             if (rc) return rc;
         }
         k += m;
         const int slot = chunk & 1;
-        GOAT_HIP(hipMemcpyAsync(&hflag[slot], &p.sk.ctrl->done, sizeof(int), hipMemcpyDeviceToHost, r.s));
+        GOAT_HIP(hipMemcpyAsync(&hflag[4 * slot], &p.sk.ctrl->done, 3 * sizeof(int), hipMemcpyDeviceToHost, r.s));
         GOAT_HIP(hipEventRecord(r.ev_poll[slot], r.s));
         if (chunk >= 1) {
             GOAT_HIP(hipEventSynchronize(r.ev_poll[slot ^ 1]));
-            if (hflag[slot ^ 1]) stop = true;
+            const int* w = &hflag[4 * (slot ^ 1)];
+            if (w[0]) stop = true;
+            float err;
+            std::memcpy(&err, &w[2], sizeof(float));
+            if (need_precise && err <= 10.0f * r.opt.sk_tol) precise = 1;
         }
         ++chunk;
     }
@@ -82,13 +90,21 @@ static int run_sinkhorn(Run& r) {
     const int n = r.L.n, np = r.L.np;
     const bool bf = r.opt.prec != GOAT_PREC_FP32;
     Ptrs& p = r.p;
-    const bool warm = r.opt.warm && r.fw > 0;
+    // warm: 1 previous iteration's column potentials; 2 the network every
+    // iteration; 3 the network on the first iteration, then as 1
+    const bool prev = (r.opt.warm == 1 || r.opt.warm == 3) && r.fw > 0;
+    const bool net = r.opt.mlp_params && (r.opt.warm == 2 || (r.opt.warm == 3 && r.fw == 0));
     // eps from the max|G_P| that the previous update (or the start) left in fscal[0]
-    int rc = sk_prepare(n, p.GP, np, nullptr, r.opt.eps_rel, p.fscal, warm ? p.g_prev : nullptr, r.opt.sk_tol,
+    int rc = sk_prepare(n, p.GP, np, nullptr, r.opt.eps_rel, p.fscal, prev ? p.g_prev : nullptr, r.opt.sk_tol,
                         p.sk, p.fscal, p.red, r.s);
     if (rc) return rc;
-    rc = sk_run_persistent(n, np, p.GP, np, p.sk, 0, r.opt.sk_max, r.s);
-    if (rc == GOAT_ENOTSUP) rc = run_sinkhorn_polled(r);
+    if (net) {
+        rc = mlp_features(n, np, p.GP, np, &p.sk.ctrl->eps, p.sk.colpart, p.feat, r.s);
+        if (!rc) rc = mlp_forward(n, p.feat, r.opt.mlp_params, p.pred, r.s);
+        if (!rc) rc = warm_seed(n, p.pred, p.sk.ctrl, p.sk.vg, p.sk.vs, r.s);
+        if (rc) return rc;
+    }
+    rc = run_sinkhorn_polled(r);
     if (rc) return rc;
     int* it_dev = reinterpret_cast<int*>(p.scal + 8);
     float* err_dev = reinterpret_cast<float*>(p.scal + 9);
@@ -159,6 +175,8 @@ int goat_run_begin(int n, const float* A, const float* B, int ld, const float* P
     GOAT_CHECK_ARG(std::isfinite(opt.sk_tol) && opt.sk_tol >= 0.0f, "bad sk_tol");
     GOAT_CHECK_ARG(opt.sk_max >= 1 && opt.fw_max >= 1, "sk_max and fw_max must be >= 1");
     GOAT_CHECK_ARG(std::isfinite(opt.fw_tol) && opt.fw_tol >= 0.0f, "bad fw_tol");
+    GOAT_CHECK_ARG(opt.warm >= 0 && opt.warm <= 3, "unknown warm-start mode");
+    GOAT_CHECK_ARG(opt.warm < 2 || opt.mlp_params, "warm-start network requested without parameters");
     const Layout L = make_layout(n, opt.prec, opt.symmetric);
     if (ws_bytes < L.total) { set_error("goat_run_begin: workspace too small"); return GOAT_ENOMEM; }
 
@@ -268,6 +286,18 @@ int goat_run_finish(goat_run* h, int32_t* perm_host, goat_stats* stats_host, flo
     std::memcpy(&r.st.score, r.hbuf, 8);
     r.st.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - r.wall0).count();
     if (stats_host) *stats_host = r.st;
+    return GOAT_OK;
+}
+
+int goat_run_gradient(goat_run* h, float* G_out, int ldg) {
+    clear_error();
+    GOAT_CHECK_ARG(h && G_out, "null pointer");
+    Run& r = h->r;
+    const int n = r.L.n, np = r.L.np;
+    GOAT_CHECK_ARG(ldg >= n, "leading dimension < n");
+    GOAT_HIP(hipMemcpy2DAsync(G_out, (size_t)ldg * 4, r.p.GP, (size_t)np * 4, (size_t)n * 4, n,
+                              hipMemcpyDeviceToDevice, r.s));
+    GOAT_HIP(hipStreamSynchronize(r.s));
     return GOAT_OK;
 }
 

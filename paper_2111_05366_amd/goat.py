@@ -32,7 +32,7 @@ class Options(ctypes.Structure):
                 ("fw_max", ctypes.c_int), ("fw_tol", ctypes.c_float), ("prec", ctypes.c_int),
                 ("symmetric", ctypes.c_int), ("proj", ctypes.c_int), ("warm", ctypes.c_int),
                 ("stop_on_stall", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("reserved", ctypes.c_int * 5), ("mlp_params", ctypes.c_void_p)]
 
 
 class IterRecord(ctypes.Structure):
@@ -88,8 +88,21 @@ def lib():
     L.goat_run_steps.argtypes = [_VP, _I, ctypes.POINTER(IterRecord), _I, ctypes.POINTER(ctypes.c_int)]
     L.goat_run_finish.restype = _I
     L.goat_run_finish.argtypes = [_VP, _VP, ctypes.POINTER(Stats), _VP, _I]
+    L.goat_run_gradient.restype = _I
+    L.goat_run_gradient.argtypes = [_VP, _VP, _I]
     L.goat_run_free.restype = None
     L.goat_run_free.argtypes = [_VP]
+    L.goat_mlp_param_count.restype = _I
+    L.goat_mlp_workspace_size.restype = _SZ
+    L.goat_mlp_workspace_size.argtypes = [_I]
+    L.goat_mlp_features.restype = _I
+    L.goat_mlp_features.argtypes = [_I, _VP, _I, _VP, _VP, _VP, _SZ, _VP]
+    L.goat_mlp_forward.restype = _I
+    L.goat_mlp_forward.argtypes = [_I, _VP, _VP, _VP, _VP]
+    L.goat_mlp_backward.restype = _I
+    L.goat_mlp_backward.argtypes = [_I, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]
+    L.goat_mlp_adam.restype = _I
+    L.goat_mlp_adam.argtypes = [_VP, _VP, _VP, _VP, _I, _F, _VP]
     L.goat_profile_enable.restype = _I
     L.goat_profile_enable.argtypes = [_I, _I]
     L.goat_profile_read.restype = _I
@@ -117,6 +130,8 @@ def default_options(**kw) -> Options:
     for k, v in kw.items():
         if k == "prec" and isinstance(v, str):
             v = PREC[v]
+        if k == "mlp_params" and v is not None and not isinstance(v, int):
+            v = v.data_ptr()
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)
@@ -326,6 +341,13 @@ class Run:
         self.history += _records(hist, done.value)
         return done.value
 
+    def gradient(self):
+        """Current grad f(P) of the run as an n x n device tensor."""
+        torch = _torch()
+        G = torch.empty((self.n, self.n), dtype=torch.float32, device=self.A.device)
+        _check(lib().goat_run_gradient(self.h, _ptr(G), self.n))
+        return G
+
     def finish(self, return_P: bool = False):
         torch = _torch()
         perm = np.empty(self.n, dtype=np.int32)
@@ -361,3 +383,46 @@ def profile_read(which: int):
     cnt = ctypes.c_longlong(0)
     _check(lib().goat_profile_read(int(which), ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+# ------------------------------------------------------------ warm start
+
+def mlp_param_count() -> int:
+    return lib().goat_mlp_param_count()
+
+
+def mlp_features(G, eps_dev):
+    """Centred per-column features [n, 4] of G / eps (goat_mlp_features)."""
+    torch = _torch()
+    _mat(G, "G")
+    n = G.shape[0]
+    F = torch.empty((n, 4), dtype=torch.float32, device=G.device)
+    ws = workspace(n, "fp32", True, G.device)
+    _check(lib().goat_mlp_features(n, _ptr(G), G.stride(0), _ptr(eps_dev), _ptr(F), _ptr(ws), ws.numel(), _stream()))
+    return F
+
+
+def mlp_forward(F, params):
+    torch = _torch()
+    N = F.shape[0]
+    y = torch.empty(N, dtype=torch.float32, device=F.device)
+    _check(lib().goat_mlp_forward(N, _ptr(F), _ptr(params), _ptr(y), _stream()))
+    return y
+
+
+def mlp_backward(F, target, params, grad=None, loss=None, ws=None):
+    """(grad [P], loss [1]) of the mean squared error (goat_mlp_backward)."""
+    torch = _torch()
+    N = F.shape[0]
+    grad = grad if grad is not None else torch.empty_like(params)
+    loss = loss if loss is not None else torch.zeros(1, dtype=torch.float32, device=F.device)
+    need = int(lib().goat_mlp_workspace_size(N))
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=F.device)
+    _check(lib().goat_mlp_backward(N, _ptr(F), _ptr(target), _ptr(params), _ptr(grad), _ptr(loss), _ptr(ws),
+                                   ws.numel(), _stream()))
+    return grad, loss
+
+
+def mlp_adam(grad, params, m, v, step: int, lr: float):
+    _check(lib().goat_mlp_adam(_ptr(grad), _ptr(params), _ptr(m), _ptr(v), int(step), float(lr), _stream()))

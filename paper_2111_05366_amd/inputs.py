@@ -165,3 +165,15 @@ def workload_weighted_sbm(n: int = 10000) -> GraphPair:
 def workload_er_5000() -> GraphPair:
     """n=5000 correlated ER pair, p=0.02, rho=0.7."""
     return rho_er_pair(5000, 0.02, 0.7, SEED_BASE + 5)
+
+
+def mlp_init_params(seed: int, hidden: int = 128, nfeat: int = 4) -> np.ndarray:
+    """Packed float32 initial weights of the warm-start network
+    (W1[h][f], b1, W2[h][h], b2, W3[h], b3): normal draws with He scaling,
+    zero biases."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.normal(0.0, np.sqrt(2.0 / nfeat), size=(hidden, nfeat))
+    W2 = rng.normal(0.0, np.sqrt(2.0 / hidden), size=(hidden, hidden))
+    W3 = rng.normal(0.0, np.sqrt(1.0 / hidden), size=(hidden,))
+    z = np.zeros
+    return np.concatenate([W1.ravel(), z(hidden), W2.ravel(), z(hidden), W3, z(1)]).astype(np.float32)

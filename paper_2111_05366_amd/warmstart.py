@@ -1,0 +1,99 @@
+"""Training and use of the learned Sinkhorn warm start.
+
+Training pairs come from the plain solver: on seeded correlated
+Erdos-Renyi pairs, the gradient grad f(P) at each Frank-Wolfe iterate is
+taken from the solver, solved to convergence by goat_sinkhorn (cold start),
+and turned into (centred column features, centred g / eps) samples with
+goat_mlp_features. The network is trained on the GPU by the library's own
+backward and Adam kernels; this module only sequences the calls.
+Parameters are stored with safetensors (flat float32 plus a JSON header).
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import numpy as np
+
+from . import goat, inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_PATH = os.path.join(HERE, "data", "warmstart_mlp.safetensors")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def generate(pairs, fw_iters: int = 6, sk_tol: float = 1e-6, sk_cap: int = 4000, eps_rel: float = 0.03,
+             log=None):
+    """Samples (F [N,4], target [N], solves) from a list of (n, p, rho, seed).
+    Each FW iterate of the plain fp32 solver gives one Sinkhorn problem."""
+    torch = _torch()
+    feats, targs, meta = [], [], []
+    for (n, p, rho, seed) in pairs:
+        g = inputs.rho_er_pair(n, p, rho, seed)
+        A = torch.as_tensor(g.A, device="cuda")
+        B = torch.as_tensor(g.B, device="cuda")
+        run = goat.Run(A, B, prec="fp32", sk_max=1000, stop_on_stall=0, eps_rel=eps_rel)
+        for k in range(fw_iters):
+            G = run.gradient()
+            out = goat.sinkhorn(G, eps_rel=eps_rel, max_iter=sk_cap, tol=sk_tol, want_Q=False)
+            eps = out.eps
+            F = goat.mlp_features(G, eps)
+            t = out.g / eps
+            t = t - t.mean()
+            feats.append(F)
+            targs.append(t)
+            meta.append(dict(n=n, seed=seed, fw=k, iters=int(out.iters.item()), err=float(out.err.item())))
+            run.steps(1)
+        run.close()
+        if log:
+            log(f"warmstart data: n={n} seed={seed} solves={fw_iters} "
+                f"iters={[m['iters'] for m in meta[-fw_iters:]]}")
+    return torch.cat(feats), torch.cat(targs), meta
+
+
+def train(F, t, steps: int = 2000, batch: int = 4096, lr: float = 1e-3, seed: int = 0, params=None, log=None):
+    """Adam on the GPU kernels; returns (params, loss history)."""
+    torch = _torch()
+    N = F.shape[0]
+    if params is None:
+        params = torch.as_tensor(inputs.mlp_init_params(seed), device="cuda")
+    params = params.clone()
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    grad = torch.empty_like(params)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(seed + 1)
+    hist = []
+    for step in range(1, steps + 1):
+        idx = torch.as_tensor(rng.integers(0, N, size=min(batch, N)), device="cuda")
+        Fb = F[idx].contiguous()
+        tb = t[idx].contiguous()
+        goat.mlp_backward(Fb, tb, params, grad, loss)
+        goat.mlp_adam(grad, params, m, v, step, lr)
+        if step % 100 == 0 or step == 1:
+            hist.append((step, float(loss.item())))
+            if log:
+                log(f"warmstart train step {step}: loss {hist[-1][1]:.4f}")
+    return params, hist
+
+
+def save(params, path: str = DEFAULT_PATH, meta: dict | None = None):
+    from safetensors.numpy import save_file
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    arr = params.detach().cpu().numpy().astype(np.float32)
+    save_file({"params": arr}, path, metadata={"layout": "W1[128][4],b1,W2[128][128],b2,W3[128],b3",
+                                               "info": json.dumps(meta or {})})
+
+
+def load(path: str = DEFAULT_PATH, device="cuda"):
+    torch = _torch()
+    from safetensors.numpy import load_file
+    arr = load_file(path)["params"]
+    if arr.shape[0] != goat.mlp_param_count():
+        raise ValueError(f"{path}: {arr.shape[0]} parameters, expected {goat.mlp_param_count()}")
+    return torch.as_tensor(arr, device=device)
