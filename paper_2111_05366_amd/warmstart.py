@@ -27,33 +27,45 @@ def _torch():
     return torch
 
 
-def generate(pairs, fw_iters: int = 6, sk_tol: float = 1e-6, sk_cap: int = 4000, eps_rel: float = 0.03,
+def generate(pairs, fw_iters: int = 6, sk_tol: float = 1e-6, sk_cap: int = 3000, eps_rel: float = 0.03,
              log=None):
     """Samples (F [N,4], target [N], solves) from a list of (n, p, rho, seed).
-    Each FW iterate of the plain fp32 solver gives one Sinkhorn problem."""
+    Each FW iterate of the plain fp32 solver gives one Sinkhorn problem;
+    iterates after a zero step (same G as before) and solves that did not
+    reach sk_tol within sk_cap are skipped (their g is not the fixed point)."""
     torch = _torch()
     feats, targs, meta = [], [], []
     for (n, p, rho, seed) in pairs:
         g = inputs.rho_er_pair(n, p, rho, seed)
         A = torch.as_tensor(g.A, device="cuda")
         B = torch.as_tensor(g.B, device="cuda")
-        run = goat.Run(A, B, prec="fp32", sk_max=1000, stop_on_stall=0, eps_rel=eps_rel)
+        run = goat.Run(A, B, prec="fp32", sk_max=1000, stop_on_stall=1, eps_rel=eps_rel)
+        kept = []
         for k in range(fw_iters):
             G = run.gradient()
             out = goat.sinkhorn(G, eps_rel=eps_rel, max_iter=sk_cap, tol=sk_tol, want_Q=False)
-            eps = out.eps
-            F = goat.mlp_features(G, eps)
-            t = out.g / eps
-            t = t - t.mean()
-            feats.append(F)
-            targs.append(t)
-            meta.append(dict(n=n, seed=seed, fw=k, iters=int(out.iters.item()), err=float(out.err.item())))
-            run.steps(1)
+            iters, err = int(out.iters.item()), float(out.err.item())
+            if err <= sk_tol:
+                eps = out.eps
+                F = goat.mlp_features(G, eps)
+                t = out.g / eps
+                feats.append(F)
+                targs.append(t - t.mean())
+                meta.append(dict(n=n, seed=seed, fw=k, iters=iters, err=err))
+                kept.append(iters)
+            if run.steps(1) == 0 or run.history[-1]["t"] == 0.0:
+                break   # a zero step leaves P, hence G, unchanged
         run.close()
         if log:
-            log(f"warmstart data: n={n} seed={seed} solves={fw_iters} "
-                f"iters={[m['iters'] for m in meta[-fw_iters:]]}")
+            log(f"warmstart data: n={n} seed={seed} kept solves (iters) {kept}")
     return torch.cat(feats), torch.cat(targs), meta
+
+
+def training_pairs(count: int = 48, seed: int = 0):
+    """(n, p, rho, seed) of the learned-part training set: correlated ER
+    pairs with n uniform in [500, 5000], p = 0.02, rho = 0.7."""
+    rng = np.random.default_rng(inputs.SEED_BASE + 600 + seed)
+    return [(int(rng.integers(500, 5001)), 0.02, 0.7, inputs.SEED_BASE + 1000 + i) for i in range(count)]
 
 
 def train(F, t, steps: int = 2000, batch: int = 4096, lr: float = 1e-3, seed: int = 0, params=None, log=None):
@@ -97,3 +109,35 @@ def load(path: str = DEFAULT_PATH, device="cuda"):
     if arr.shape[0] != goat.mlp_param_count():
         raise ValueError(f"{path}: {arr.shape[0]} parameters, expected {goat.mlp_param_count()}")
     return torch.as_tensor(arr, device=device)
+
+
+def main(argv=None):
+    """Generate samples with the plain solver, train on the GPU, save."""
+    import argparse
+    ap = argparse.ArgumentParser(description="train the Sinkhorn warm-start network")
+    ap.add_argument("--pairs", type=int, default=48)
+    ap.add_argument("--fw-iters", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    t0 = time.time()
+    pairs = training_pairs(a.pairs)
+    F, t, meta = generate(pairs, fw_iters=a.fw_iters, log=log)
+    log(f"{F.shape[0]} samples from {len(meta)} converged solves ({time.time() - t0:.0f} s)")
+    params, hist = train(F, t, steps=a.steps, batch=a.batch, lr=a.lr, seed=a.seed)
+    log(f"loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f} ({time.time() - t0:.0f} s)")
+    save(params, a.out, meta=dict(pairs=a.pairs, fw_iters=a.fw_iters, steps=a.steps, batch=a.batch,
+                                  lr=a.lr, seed=a.seed, samples=int(F.shape[0]), solves=len(meta),
+                                  loss_first=hist[0][1], loss_last=hist[-1][1]))
+    log(f"saved {a.out}")
+
+
+if __name__ == "__main__":
+    main()
