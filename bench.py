@@ -10,9 +10,11 @@ A step is one Frank-Wolfe iteration of Alg. 3 on the device (gradient
 product, LOT Sinkhorn solve to tolerance 1e-6 or 1000 sweeps, exact step,
 update) with A, B, P resident in HBM. Two forms run on the same pair:
   plain : fp32 matrix-core gradient, cold Sinkhorn start each iteration;
-  mixed : bf16 hi/lo-split gradient (3 products), Sinkhorn started from the
-          previous iteration's column potentials.
-`value` is the mixed form's rate; the plain one is in `config`.
+  mixed : bf16 hi/lo-split gradient (3 products); Sinkhorn started by the
+          learned warm-start network on the first iteration and from the
+          previous iteration's column potentials afterwards.
+`value` is the mixed form's rate; the plain one is in `config`, with both
+forms' match ratios against the planted permutation.
 
 The dominant kernel is the Sinkhorn row sweep (HBM-bound: it reads G once,
 4 n^2 bytes per launch); its per-launch duration is sampled with HIP events
@@ -34,16 +36,35 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 
+# HBM bytes per launch of the compensated Sinkhorn row sweep at n = 10,000,
+# from two rocprofv3 --pmc passes of paper_2111_05366_amd/counters.py
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+# same counter reads for a device copy of 4 n^2 bytes in the same run. Valid
+# only for the kernel source it was measured on (sha256 of sinkhorn.hip);
+# reported as null otherwise.
+TRAFFIC = {"src_sha256": None, "bytes_per_launch": None}
+
+
+def _traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2111_05366_amd", "csrc", "sinkhorn.hip")
+    with open(src, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    if TRAFFIC["src_sha256"] == digest and TRAFFIC["bytes_per_launch"]:
+        return TRAFFIC["bytes_per_launch"]
+    return None
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_form(goat, A, B, n, form, warmup, steps, sk_max, sk_tol, prof_stride):
+def run_form(goat, A, B, n, form, warmup, steps, sk_max, sk_tol, prof_stride, mlp=None):
     import torch
     prec = "fp32" if form == "plain" else "bf16x3"
-    warm = 0 if form == "plain" else 1
-    run = goat.Run(A, B, prec=prec, warm=warm, stop_on_stall=0, sk_max=sk_max, sk_tol=sk_tol)
+    warm = 0 if form == "plain" else 3
+    run = goat.Run(A, B, prec=prec, warm=warm, stop_on_stall=0, sk_max=sk_max, sk_tol=sk_tol,
+                   mlp_params=None if form == "plain" else mlp)
     run.steps(warmup)
     log(f"{form}: warmup {warmup} done")
     goat.profile_enable(goat.PROF_SINKHORN_ROW, prof_stride)
@@ -131,10 +152,11 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2111_05366_amd import goat, inputs
+    from paper_2111_05366_amd import goat, inputs, warmstart
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     goat.lib()
+    mlp = warmstart.load()
     n = args.n
     t0 = time.perf_counter()
     pair = inputs.workload_weighted_sbm(n)
@@ -142,10 +164,18 @@ def main():
         f"(nnz per graph {int((pair.A != 0).sum())})")
     A = torch.as_tensor(pair.A, device="cuda")
     B = torch.as_tensor(pair.B, device="cuda")
+    # HBM calibration: a plain copy of n^2 floats (reads and writes 4 n^2 B),
+    # untimed; profiler byte counters of the Sinkhorn sweep are scaled by it
+    src = torch.empty((n, n), dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
     forms = {}
     for form in args.forms.split(","):
         forms[form] = run_form(goat, A, B, n, form, args.warmup, args.steps, args.sk_max, args.sk_tol,
-                               args.prof_stride)
+                               args.prof_stride, mlp)
         forms[form]["match_ratio"] = float(np.mean(forms[form]["perm"] == pair.truth))
         log(f"{form}: match ratio {forms[form]['match_ratio']:.4f}")
     main_form = forms.get("mixed") or next(iter(forms.values()))
@@ -155,7 +185,7 @@ def main():
     alg_bytes = 4.0 * n * n
     achieved = alg_bytes / (main_form["sk_row_ms"] * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=_traffic(),
                 kernel="sk_row_kernel (Sinkhorn row sweep)",
                 per_launch=f"4*n^2 = {alg_bytes:.3e} B", avg_launch_us=round(main_form["sk_row_ms"] * 1e3, 2),
                 samples=main_form["sk_row_samples"])
@@ -190,6 +220,8 @@ def main():
             "forms": {k: summary(v) for k, v in forms.items()},
             "speedup_vs_plain_fp32": (round(main_form["fw_iters_per_s"] / plain["fw_iters_per_s"], 3)
                                       if plain and main_form is not plain else None),
+            "match_ratio_gap_vs_plain": (round(abs(main_form["match_ratio"] - plain["match_ratio"]), 5)
+                                         if plain and main_form is not plain else None),
             "gemm_roofline": {
                 "bound": "mfma", "kernel": "gemm_nt (2 launches per gradient)",
                 "achieved_exec": round(main_form["gemm_exec_tflops"], 1) if main_form["gemm_exec_tflops"] else None,

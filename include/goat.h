@@ -102,7 +102,11 @@ int goat_grad(int n, const float* A, const float* B, int ld,
  *  iters_dev, err_dev, eps_out  device int / float / float outputs (each
  *           may be NULL): column updates run, max_i |sum_j Q_ij - 1| of the
  *           returned plan, and the eps used.
- * The call is asynchronous; convergence is decided on the device.
+ * The call is asynchronous; convergence is decided on the device. Every
+ * sweep after the first uses compensated (two-float) potentials, so that
+ * marginal errors near 1e-6 are resolved. G is copied into the workspace
+ * (one extra read and write of G) when ldg is not a multiple of 4, G is not
+ * 16-byte aligned, or ldg is not a multiple of 64 and max_iter >= 8.
  */
 int goat_sinkhorn(int n, const float* G, int ldg,
                   const float* eps_dev, float eps_rel,
@@ -276,6 +280,113 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
 int goat_score(int n, const float* A, const float* B, int ld,
                const int32_t* perm_dev, double* out_dev,
                void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Random starts (GOAT section, random initialisations)
+ * ---------------------------------------------------------------------- */
+
+/*
+ * goat_random_init - P0 = (J + K) / 2, where J = 1 1^T / n is the barycenter
+ * and K = diag(r) U diag(c) is the Sinkhorn-Knopp scaling of a positive n x n
+ * matrix U to a doubly stochastic one. Scaling alternates r = 1 / (U c),
+ * c = 1 / (U^T r) from c = 1 until max_i |(K 1)_i - 1| <= tol (checked from
+ * the second sweep) or max_iter sweeps; float32 on the device.
+ *  U        device n x n (ldu >= n), entries > 0 (e.g. U(0,1) draws).
+ *  P        device n x n output (ldp >= n).
+ *  iters_dev, err_dev  device int / float (may be NULL): sweeps run and the
+ *           final row-sum error of K.
+ * Status: GOAT_EINVAL for n < 1, n > GOAT_BATCH_NMAX, bad ld, null U or P,
+ * tol < 0 or max_iter < 1. Non-positive entries of U are not checked (the
+ * scaling then produces inf or nan).
+ */
+#define GOAT_BATCH_NMAX 1024
+int goat_random_init(int n, const float* U, int ldu, float* P, int ldp, float tol, int max_iter,
+                     int* iters_dev, float* err_dev, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched solve: many graph pairs of uneven size, several starts each
+ * ---------------------------------------------------------------------- */
+
+/* One graph pair of a batch. */
+typedef struct goat_pair {
+    int n;               /* nodes, 1 <= n <= GOAT_BATCH_NMAX                      */
+    int ld;              /* leading dimension of A, B, U (>= n)                   */
+    const float* A;      /* device n x n                                          */
+    const float* B;      /* device n x n                                          */
+    const float* U;      /* device positive draws for the random starts: restart r
+                            uses the n x n matrix at U + r * n * ld and starts at
+                            (J + SK(U_r)) / 2 (see goat_random_init); NULL: every
+                            restart starts at J                                   */
+} goat_pair;
+
+typedef struct goat_batch goat_batch;
+
+typedef struct goat_batch_stats {
+    int    problems;       /* npairs * restarts                                 */
+    int    fw_iters_total; /* FW iterations summed over problems                */
+    long long sk_iters_total; /* Sinkhorn iterations summed over problems       */
+    int    sk_capped;      /* (problem, FW iteration)s whose Sinkhorn hit sk_max */
+    int    launches;       /* kernels in the graph (one per size bucket + packing) */
+    double ms_graph;       /* device time of the graph launch (HIP events)      */
+    double ms_lap;         /* host time of all final assignments                */
+    double ms_total;       /* wall time of goat_batch_results                   */
+} goat_batch_stats;
+
+/*
+ * goat_batch_create - plan a batch: npairs pairs x restarts starts, each a
+ * full GOAT solve (Alg. 3: Frank-Wolfe with the LOT direction, exact step,
+ * final assignment) with the options of opt (eps_rel, sk_tol, sk_max, fw_max,
+ * fw_tol, symmetric, proj, stop_on_stall, warm 0 or 1; prec must be
+ * GOAT_PREC_FP32). One workgroup runs one (pair, start) problem from its
+ * start to its last FW iteration inside a single persistent kernel; problems
+ * are grouped into size buckets, each bucket one kernel with its autotuned
+ * shape (goat_tune), all captured in one HIP graph. The pair descriptors are
+ * copied; A, B, U must stay valid and unchanged until goat_batch_destroy.
+ *  ws, ws_bytes  device workspace of at least goat_batch_workspace_size bytes,
+ *           owned by the caller, in use until goat_batch_destroy.
+ * Status: GOAT_EINVAL (bad pair, restarts < 1, options), GOAT_ENOTSUP
+ * (prec != FP32, warm > 1), GOAT_ENOMEM (workspace too small), GOAT_EHIP.
+ */
+int goat_batch_workspace_size(const goat_pair* pairs, int npairs, int restarts,
+                              const goat_options* opt, size_t* bytes);
+int goat_batch_create(const goat_pair* pairs, int npairs, int restarts,
+                      const goat_options* opt, void* ws, size_t ws_bytes,
+                      goat_batch** out);
+/* Launch the whole batch (one graph launch), stream-ordered on stream. */
+int goat_batch_launch(goat_batch* b, void* stream);
+/*
+ * goat_batch_results - wait for the launch, then the final assignments on the
+ * host (one LAP per problem, problems in parallel), scores
+ * tr(A^T Pi B Pi^T) on the device, and per pair the start with the largest
+ * score (ties to the lowest start index).
+ *  perm_host   int32[sum_p n_p]: kept permutation of each pair, concatenated
+ *              in pair order (may be NULL).
+ *  score_host  double[npairs] (may be NULL); best_host int[npairs] (may be NULL).
+ *  all_score_host double[npairs * restarts], pair-major (may be NULL).
+ *  hist_host   goat_iter_record[npairs * restarts * hist_cap], problem
+ *              (pair-major) then FW iteration; records past a problem's last
+ *              iteration are zeroed (may be NULL).
+ *  fw_iters_host int[npairs * restarts] (may be NULL).
+ */
+int goat_batch_results(goat_batch* b, int32_t* perm_host, double* score_host, int* best_host,
+                       double* all_score_host, goat_iter_record* hist_host, int hist_cap,
+                       int* fw_iters_host, goat_batch_stats* stats_host);
+/* Copy the final P (proj = 0) of problem (pair, restart) to a device n x n
+ * matrix out (ld >= n), stream-ordered. */
+int goat_batch_get_P(goat_batch* b, int pair, int restart, float* out, int ld, void* stream);
+void goat_batch_destroy(goat_batch* b);
+
+/*
+ * goat_tune - autotune the batched kernel's shape (lanes per Sinkhorn row)
+ * for every size bucket up to n_max on the current device: each candidate
+ * runs a synthetic batch of the bucket's largest size and the fastest is
+ * kept in a per-device table that later goat_batch_create calls read
+ * (untuned buckets use a fixed default). reps >= 1 timed launches each.
+ * goat_tune_get reports the shape used for size n: lanes per row (16, 32 or
+ * 64) and waves per workgroup.
+ */
+int goat_tune(int n_max, int reps, void* stream);
+int goat_tune_get(int n, int* lanes_per_row, int* waves);
 
 #ifdef __cplusplus
 }

@@ -226,7 +226,11 @@ int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float ep
     GOAT_CHECK_ARG(std::isfinite(tol) && tol >= 0.0f, "bad tol");
     GOAT_CHECK_ARG(eps_dev || (std::isfinite(eps_rel) && eps_rel > 0.0f), "bad eps_rel");
     const Layout L = make_layout(n, GOAT_PREC_FP32, 1);
-    const bool repack = (ldg % 4) != 0 || !aligned16(G);
+    // rows are swept as float4 and read best at 256-byte alignment: G is
+    // copied into the padded layout when it is misaligned for float4, or when
+    // its rows are not 256-byte multiples and enough sweeps follow to pay back
+    // the copy (one read and one write of G)
+    const bool repack = (ldg % 4) != 0 || !aligned16(G) || ((ldg % 64) != 0 && max_iter >= 8);
     const size_t need = small_bytes(L) + (repack ? (size_t)L.np * L.np * 4 : 0);
     if (ws_bytes < need) { set_error("goat_sinkhorn: workspace too small"); return GOAT_ENOMEM; }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -242,11 +246,8 @@ int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float ep
     int rc = sk_prepare(n, Gk, ldk, eps_dev, eps_rel, nullptr, init == GOAT_INIT_G ? g : nullptr, tol, p.sk,
                         p.fscal, p.red, s);
     if (rc) return rc;
-    // stream-ordered, so the sweep form is fixed up front: compensated when
-    // the tolerance is below what the plain form certifies
-    const int precise = tol < sk_plain_floor;
     for (int k = 0; k < max_iter; ++k) {
-        rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, k, precise, s);
+        rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, k, s);
         if (rc) return rc;
     }
     return sk_finalize(n, L.np, Gk, ldk, p.sk, Q, ldq, nullptr, nullptr, f, g, iters_dev, err_dev, eps_out,

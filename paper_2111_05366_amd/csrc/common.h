@@ -131,14 +131,10 @@ int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_r
                double* red, hipStream_t s);
 // One Sinkhorn iteration (row sweep + column update); iter is its index in
 // the solve (row-walk direction alternates with its parity).
-// precise selects the compensated exponent (needed to certify tolerances
-// below sk_plain_floor); the first iteration always uses the plain form.
+// The first iteration shifts by the row maximum with single-float column
+// potentials; every later one uses the compensated potentials.
 int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check, int iter,
-               int precise, hipStream_t s);
-// Smallest tolerance the plain (uncompensated) sweep certifies reliably.
-constexpr float sk_plain_floor = 1e-5f;
-// GOAT_SK_PRECISE=1 forces compensated sweeps from the second iteration on.
-bool sk_force_precise();
+               hipStream_t s);
 // Form Q (fp32 and optional bf16 split), its row-marginal error, potentials
 // in natural units, and (when P != NULL) the traces <Q,G>, <P,G>, ||Q-P||^2.
 int sk_finalize(int n, int np, const float* G, int ldg, SkState st,

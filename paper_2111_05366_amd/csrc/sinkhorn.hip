@@ -13,10 +13,9 @@
 // G kappa + (v_grid + u_grid) rounds only a small result, and the small
 // remainders are added last. This keeps row and column sums accurate to a
 // few 1e-7 (a plain float32 potential of magnitude ~48 alone carries ~2e-6
-// of rounding), so a 1e-6 marginal tolerance can be certified. The plain
-// form adds v_grid + v_rem once per column (one add less per entry, half the
-// LDS); drivers use it far from the tolerance and switch to the compensated
-// form near it.
+// of rounding), so a 1e-6 marginal tolerance can be certified. The first
+// sweep, which shifts by the row maximum, adds v_grid + v_rem once per
+// column instead; at n = 10,000 both forms sweep at the same speed.
 //
 // One iteration = one read of G:
 //   row sweep (sk_row_kernel): workgroup w owns a strip of rows. For a row i
@@ -506,16 +505,10 @@ void launch_row_TCP(const Geometry& g, const SkArgs& a, hipStream_t s) {
     else hipLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, false>), dim3(g.W), dim3(T), 0, s, a);
 }
 
-template <int T, int C, bool FIRST>
-void launch_row_TC(const Geometry& g, const SkArgs& a, int precise, hipStream_t s) {
-    if (FIRST || !precise) launch_row_TCP<T, C, FIRST, false>(g, a, s);
-    else launch_row_TCP<T, C, false, true>(g, a, s);
-}
-
 template <int T, bool FIRST>
-int launch_row_T(const Geometry& g, const SkArgs& a, int precise, hipStream_t s) {
+int launch_row_T(const Geometry& g, const SkArgs& a, hipStream_t s) {
     switch (g.C) {
-#define GOAT_SK_C(CC) case CC: launch_row_TC<T, CC, FIRST>(g, a, precise, s); break;
+#define GOAT_SK_C(CC) case CC: launch_row_TCP<T, CC, FIRST, !FIRST>(g, a, s); break;
         GOAT_SK_C(1) GOAT_SK_C(2) GOAT_SK_C(3) GOAT_SK_C(4) GOAT_SK_C(5) GOAT_SK_C(6)
         GOAT_SK_C(8) GOAT_SK_C(10) GOAT_SK_C(12) GOAT_SK_C(16)
 #undef GOAT_SK_C
@@ -576,25 +569,16 @@ int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_r
     return GOAT_OK;
 }
 
-bool sk_force_precise() {
-    static const bool force = [] {
-        const char* e = getenv("GOAT_SK_PRECISE");
-        return e && e[0] == '1';
-    }();
-    return force;
-}
-
 int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check, int iter,
-               int precise, hipStream_t s) {
+               hipStream_t s) {
     const Geometry g = geometry(n);
     SkArgs a = make_args(n, np, G, ldg, st, g);
     a.rev = iter & 1;
-    const int pr = precise || sk_force_precise();
     int rc;
     prof_begin(0, s);
-    if (g.T == 256) rc = first ? launch_row_T<256, true>(g, a, pr, s) : launch_row_T<256, false>(g, a, pr, s);
-    else if (g.T == 512) rc = first ? launch_row_T<512, true>(g, a, pr, s) : launch_row_T<512, false>(g, a, pr, s);
-    else rc = first ? launch_row_T<1024, true>(g, a, pr, s) : launch_row_T<1024, false>(g, a, pr, s);
+    if (g.T == 256) rc = first ? launch_row_T<256, true>(g, a, s) : launch_row_T<256, false>(g, a, s);
+    else if (g.T == 512) rc = first ? launch_row_T<512, true>(g, a, s) : launch_row_T<512, false>(g, a, s);
+    else rc = first ? launch_row_T<1024, true>(g, a, s) : launch_row_T<1024, false>(g, a, s);
     prof_end(0, s);
     if (rc) return rc;
     hipLaunchKernelGGL(sk_merge_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a, g.W, check);

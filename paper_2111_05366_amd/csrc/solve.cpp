@@ -47,39 +47,31 @@ struct Run {
 };
 
 // Sinkhorn sweeps on G_P: one launch pair per iteration, the device-side
-// convergence flag and error polled every check_every iterations (two
-// chunks in flight, so the device never waits for the host). Sweeps use the
-// plain exponent until a polled error is within 10x a tolerance below the
-// plain form's floor, then the compensated one.
+// convergence flag polled every check_every iterations (two chunks in
+// flight, so the device never waits for the host).
 static int run_sinkhorn_polled(Run& r) {
     const int n = r.L.n, np = r.L.np;
     Ptrs& p = r.p;
     int rc;
-    rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, 0, 0, r.s);
+    rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, 0, r.s);
     if (rc) return rc;
     const int check_every = r.opt.check_every > 0 ? r.opt.check_every : 16;
-    const bool need_precise = r.opt.sk_tol < sk_plain_floor;
-    // per slot: done, iters, err (the ctrl block's words 2..4)
     int* hflag = reinterpret_cast<int*>(static_cast<char*>(r.hbuf) + 128);
-    int k = 1, chunk = 0, precise = 0;
+    int k = 1, chunk = 0;
     bool stop = false;
     while (k < r.opt.sk_max && !stop) {
         const int m = std::min(check_every, r.opt.sk_max - k);
         for (int q = 0; q < m; ++q) {
-            rc = sk_iterate(n, np, p.GP, np, p.sk, 0, 1, k + q, precise, r.s);
+            rc = sk_iterate(n, np, p.GP, np, p.sk, 0, 1, k + q, r.s);
             if (rc) return rc;
         }
         k += m;
         const int slot = chunk & 1;
-        GOAT_HIP(hipMemcpyAsync(&hflag[4 * slot], &p.sk.ctrl->done, 3 * sizeof(int), hipMemcpyDeviceToHost, r.s));
+        GOAT_HIP(hipMemcpyAsync(&hflag[slot], &p.sk.ctrl->done, sizeof(int), hipMemcpyDeviceToHost, r.s));
         GOAT_HIP(hipEventRecord(r.ev_poll[slot], r.s));
         if (chunk >= 1) {
             GOAT_HIP(hipEventSynchronize(r.ev_poll[slot ^ 1]));
-            const int* w = &hflag[4 * (slot ^ 1)];
-            if (w[0]) stop = true;
-            float err;
-            std::memcpy(&err, &w[2], sizeof(float));
-            if (need_precise && err <= 10.0f * r.opt.sk_tol) precise = 1;
+            if (hflag[slot ^ 1]) stop = true;
         }
         ++chunk;
     }

@@ -50,6 +50,18 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double)]
 
 
+class Pair(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("ld", ctypes.c_int), ("A", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("U", ctypes.c_void_p)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("problems", ctypes.c_int), ("fw_iters_total", ctypes.c_int),
+                ("sk_iters_total", ctypes.c_longlong), ("sk_capped", ctypes.c_int),
+                ("launches", ctypes.c_int), ("ms_graph", ctypes.c_double), ("ms_lap", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
 _lib = None
 _VP, _I, _F, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_size_t
 
@@ -107,6 +119,27 @@ def lib():
     L.goat_profile_enable.argtypes = [_I, _I]
     L.goat_profile_read.restype = _I
     L.goat_profile_read.argtypes = [_I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+    L.goat_random_init.restype = _I
+    L.goat_random_init.argtypes = [_I, _VP, _I, _VP, _I, _F, _I, _VP, _VP, _VP]
+    L.goat_batch_workspace_size.restype = _I
+    L.goat_batch_workspace_size.argtypes = [ctypes.POINTER(Pair), _I, _I, ctypes.POINTER(Options),
+                                            ctypes.POINTER(ctypes.c_size_t)]
+    L.goat_batch_create.restype = _I
+    L.goat_batch_create.argtypes = [ctypes.POINTER(Pair), _I, _I, ctypes.POINTER(Options), _VP, _SZ,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    L.goat_batch_launch.restype = _I
+    L.goat_batch_launch.argtypes = [_VP, _VP]
+    L.goat_batch_results.restype = _I
+    L.goat_batch_results.argtypes = [_VP, _VP, _VP, _VP, _VP, ctypes.POINTER(IterRecord), _I, _VP,
+                                     ctypes.POINTER(BatchStats)]
+    L.goat_batch_get_P.restype = _I
+    L.goat_batch_get_P.argtypes = [_VP, _I, _I, _VP, _I, _VP]
+    L.goat_batch_destroy.restype = None
+    L.goat_batch_destroy.argtypes = [_VP]
+    L.goat_tune.restype = _I
+    L.goat_tune.argtypes = [_I, _I, _VP]
+    L.goat_tune_get.restype = _I
+    L.goat_tune_get.argtypes = [_I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     _lib = L
     return L
 
@@ -426,3 +459,124 @@ def mlp_backward(F, target, params, grad=None, loss=None, ws=None):
 
 def mlp_adam(grad, params, m, v, step: int, lr: float):
     _check(lib().goat_mlp_adam(_ptr(grad), _ptr(params), _ptr(m), _ptr(v), int(step), float(lr), _stream()))
+
+
+# ------------------------------------------------------------ random starts, batches
+
+def random_init(U, tol: float = 1e-6, max_iter: int = 1000):
+    """P0 = (J + SK(U)) / 2 on the device (goat_random_init): (P, iters, err)."""
+    torch = _torch()
+    _mat(U, "U")
+    n = U.shape[0]
+    P = torch.empty((n, n), dtype=torch.float32, device=U.device)
+    it = torch.zeros(1, dtype=torch.int32, device=U.device)
+    err = torch.zeros(1, dtype=torch.float32, device=U.device)
+    _check(lib().goat_random_init(n, _ptr(U), U.stride(0), _ptr(P), P.stride(0), float(tol), int(max_iter),
+                                  _ptr(it), _ptr(err), _stream()))
+    return P, it, err
+
+
+class Batch:
+    """Many pairs x starts in one graph launch (goat_batch_*). `pairs` is a
+    list of (A, B) or (A, B, U) device tensors; U holds `restarts` stacked
+    n x n positive draws (restart r at rows r*n .. r*n+n-1) or is None.
+    Tensors stay referenced for the batch's lifetime."""
+
+    def __init__(self, pairs, restarts: int = 1, **opts):
+        torch = _torch()
+        self.keep = []
+        arr = (Pair * len(pairs))()
+        for k, pr in enumerate(pairs):
+            A, B = pr[0], pr[1]
+            U = pr[2] if len(pr) > 2 else None
+            _mat(A, "A"); _mat(B, "B")
+            if A.stride(0) != B.stride(0):
+                raise ValueError("A and B of a pair must share a leading dimension")
+            n = A.shape[0]
+            if U is not None:
+                if U.dtype != torch.float32 or not U.is_contiguous() or U.shape != (restarts * n, n) \
+                        or A.stride(0) != n:
+                    raise ValueError("U must be a contiguous float32 (restarts*n, n) tensor and ld == n")
+            arr[k] = Pair(n, A.stride(0), _ptr(A), _ptr(B), _ptr(U))
+            self.keep += [A, B, U]
+        self.pairs = arr
+        self.npairs = len(pairs)
+        self.restarts = restarts
+        self.n = [p.n for p in arr]
+        self.opt = default_options(**opts)
+        need = ctypes.c_size_t(0)
+        _check(lib().goat_batch_workspace_size(arr, len(pairs), restarts, ctypes.byref(self.opt),
+                                               ctypes.byref(need)))
+        self.ws = torch.empty(max(need.value, 1), dtype=torch.uint8, device=pairs[0][0].device)
+        h = ctypes.c_void_p()
+        _check(lib().goat_batch_create(arr, len(pairs), restarts, ctypes.byref(self.opt), _ptr(self.ws),
+                                       self.ws.numel(), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self):
+        _check(lib().goat_batch_launch(self.h, _stream()))
+
+    def results(self, hist_cap: int | None = None):
+        cap = hist_cap or self.opt.fw_max
+        N = self.npairs * self.restarts
+        perm = np.empty(sum(self.n), dtype=np.int32)
+        score = np.empty(self.npairs, dtype=np.float64)
+        best = np.empty(self.npairs, dtype=np.int32)
+        allsc = np.empty(N, dtype=np.float64)
+        hist = (IterRecord * (N * cap))()
+        fwd = np.empty(N, dtype=np.int32)
+        st = BatchStats()
+        _check(lib().goat_batch_results(self.h, perm.ctypes.data_as(ctypes.c_void_p),
+                                        score.ctypes.data_as(ctypes.c_void_p), best.ctypes.data_as(ctypes.c_void_p),
+                                        allsc.ctypes.data_as(ctypes.c_void_p), hist, cap,
+                                        fwd.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st)))
+        perms, o = [], 0
+        for n in self.n:
+            perms.append(perm[o:o + n].astype(np.int64))
+            o += n
+        histories = []
+        for k in range(N):
+            recs = [hist[k * cap + f] for f in range(min(int(fwd[k]), cap))]
+            histories.append([dict(fP=r.fP, fQ=r.fQ, c=r.c, a=r.a, b=r.b, t=r.t, dist2=r.dist2, eps=r.eps,
+                                   sk_err=r.sk_err, sk_iters=r.sk_iters) for r in recs])
+        return dict(perm=perms, score=score, best=best, all_scores=allsc.reshape(self.npairs, self.restarts),
+                    history=histories, fw_iters=fwd.reshape(self.npairs, self.restarts), stats=st)
+
+    def get_P(self, pair: int, restart: int = 0):
+        torch = _torch()
+        n = self.n[pair]
+        P = torch.empty((n, n), dtype=torch.float32, device=self.ws.device)
+        _check(lib().goat_batch_get_P(self.h, pair, restart, _ptr(P), n, _stream()))
+        return P
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().goat_batch_destroy(self.h)
+            self.h = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(pairs, restarts: int = 1, **opts):
+    b = Batch(pairs, restarts, **opts)
+    try:
+        b.launch()
+        return b.results()
+    finally:
+        b.close()
+
+
+def tune(n_max: int, reps: int = 3):
+    _check(lib().goat_tune(int(n_max), int(reps), _stream()))
+
+
+def tune_get(n: int):
+    L = ctypes.c_int(0)
+    w = ctypes.c_int(0)
+    _check(lib().goat_tune_get(int(n), ctypes.byref(L), ctypes.byref(w)))
+    return L.value, w.value

@@ -167,6 +167,25 @@ def workload_er_5000() -> GraphPair:
     return rho_er_pair(5000, 0.02, 0.7, SEED_BASE + 5)
 
 
+def workload_batch(npairs: int = 512, restarts: int = 8, n_lo: int = 50, n_hi: int = 400,
+                   seed_offset: int = 4):
+    """Random-start batch: npairs correlated ER pairs with n ~ U{n_lo..n_hi},
+    p ~ U(0.05, 0.3), rho ~ U(0.6, 1.0), each with `restarts` U(0,1) n x n
+    draws for the random starts, stacked as a (restarts*n, n) float32 array.
+    Returns a list of (GraphPair, U)."""
+    rng = np.random.default_rng(SEED_BASE + seed_offset)
+    out = []
+    for _ in range(npairs):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        p = float(rng.uniform(0.05, 0.3))
+        rho = float(rng.uniform(0.6, 1.0))
+        s = int(rng.integers(0, 2 ** 31 - 1))
+        g = rho_er_pair(n, p, rho, s)
+        U = np.random.default_rng(s + 7).random((restarts * n, n)).astype(np.float32)
+        out.append((g, U))
+    return out
+
+
 def mlp_init_params(seed: int, hidden: int = 128, nfeat: int = 4) -> np.ndarray:
     """Packed float32 initial weights of the warm-start network
     (W1[h][f], b1, W2[h][h], b2, W3[h], b3): normal draws with He scaling,

@@ -168,3 +168,33 @@ def test_bad_arguments_rejected_before_device(G):
     s = L.goat_solve(4, ctypes.c_void_p(16), ctypes.c_void_p(16), 4, None, ctypes.byref(o),
                      ctypes.c_void_p(16), None, None, 0, None, ctypes.c_void_p(16), 1 << 30, None)
     assert s == G.GOAT_EINVAL
+
+
+def test_batch_arguments_rejected_before_device(G):
+    L = G.lib()
+    pairs = (G.Pair * 2)(G.Pair(50, 50, 16, 32, None), G.Pair(400, 400, 48, 64, None))
+    need = ctypes.c_size_t(0)
+    o = G.default_options()
+    assert L.goat_batch_workspace_size(pairs, 2, 8, ctypes.byref(o), ctypes.byref(need)) == G.GOAT_OK
+    # 16 problems: at least P, Q, G_P, G_Q, T per problem and A, B per pair
+    np_ = [64, 416]
+    assert need.value >= sum(8 * 5 * 4 * m * m + 2 * 4 * m * m for m in np_)
+    h = ctypes.c_void_p()
+    assert L.goat_batch_create(pairs, 2, 8, ctypes.byref(o), ctypes.c_void_p(256), 1024,
+                               ctypes.byref(h)) == G.GOAT_ENOMEM
+    assert L.goat_batch_workspace_size(pairs, 2, 0, ctypes.byref(o), ctypes.byref(need)) == G.GOAT_EINVAL
+    for bad in (G.Pair(0, 4, 16, 32, None), G.Pair(1025, 1025, 16, 32, None), G.Pair(8, 4, 16, 32, None),
+                G.Pair(8, 8, None, 32, None)):
+        one = (G.Pair * 1)(bad)
+        assert L.goat_batch_workspace_size(one, 1, 1, ctypes.byref(o), ctypes.byref(need)) == G.GOAT_EINVAL
+    for kw, status in ((dict(prec=G.PREC["bf16x3"]), G.GOAT_ENOTSUP), (dict(warm=2), G.GOAT_ENOTSUP),
+                       (dict(sk_max=0), G.GOAT_EINVAL), (dict(fw_max=0), G.GOAT_EINVAL),
+                       (dict(eps_rel=float("nan")), G.GOAT_EINVAL), (dict(proj=2), G.GOAT_EINVAL)):
+        ob = G.default_options(**kw)
+        assert L.goat_batch_workspace_size(pairs, 2, 8, ctypes.byref(ob), ctypes.byref(need)) == status, kw
+    assert L.goat_random_init(0, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 4, ctypes.c_float(1e-6), 10,
+                              None, None, None) == G.GOAT_EINVAL
+    assert L.goat_random_init(4, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 4, ctypes.c_float(1e-6), 0,
+                              None, None, None) == G.GOAT_EINVAL
+    assert L.goat_tune(0, 1, None) == G.GOAT_EINVAL
+    assert L.goat_tune_get(2000, None, None) == G.GOAT_EINVAL

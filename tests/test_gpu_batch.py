@@ -1,0 +1,179 @@
+"""Batched solver (goat_batch_*) and random starts (goat_random_init)
+against the FP64 oracle and the single-problem solver, on seeded inputs.
+
+Tolerances as for the single-problem path: relaxed objective per FW
+iteration <= 1e-5 relative for the first iterations (later ones can drift
+apart once a step is clipped differently), the final permutation
+bit-exact given the same P, scores exact (integer sums for 0/1 graphs)."""
+import numpy as np
+import pytest
+
+from oracle import goat_oracle as O
+from paper_2111_05366_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_05366_amd import goat
+    goat.lib()
+    yield goat
+    goat.release_workspace()
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def is_perm(p, n):
+    return sorted(int(x) for x in p) == list(range(n))
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 257, 1024])
+def test_random_init_parity(G, n):
+    U = I.uniform_matrix(n, 300 + n)
+    P, it, err = G.random_init(dev(U))
+    got = host(P)
+    ref = O.random_init(U.astype(np.float64))
+    rel = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"random init n={n}: sweeps {int(it.item())} err {float(err.item()):.2e} max rel {rel:.2e}")
+    assert rel <= 2e-6
+    assert float(err.item()) <= 1e-6
+    assert np.max(np.abs(got.sum(axis=1) - 1)) <= 1e-5 and np.max(np.abs(got.sum(axis=0) - 1)) <= 1e-5
+
+
+ORACLE_PAIRS = [(64, 0.1, 0.9, I.SEED_BASE + 1), (50, 0.12, 0.8, 77), (97, 0.08, 0.8, 78), (130, 0.1, 0.7, 79)]
+
+
+def test_batch_matches_oracle_from_barycenter(G):
+    graphs = [I.rho_er_pair(n, p, rho, s) for (n, p, rho, s) in ORACLE_PAIRS]
+    b = G.Batch([(dev(g.A), dev(g.B)) for g in graphs], restarts=1, sk_max=500)
+    b.launch()
+    res = b.results()
+    for k, g in enumerate(graphs):
+        n = g.A.shape[0]
+        print(f"batch vs oracle pair {k} n={n}", flush=True)
+        ref = O.goat(g.A, g.B, opt=O.GoatOptions(sk_max=500), record=True)
+        h = res["history"][k]
+        for f in range(min(3, len(h), len(ref.history))):
+            assert h[f]["fP"] == pytest.approx(ref.history[f]["fP"], rel=1e-5), (k, f)
+            assert h[f]["c"] == pytest.approx(ref.history[f]["c"], rel=1e-5), (k, f)
+        # final permutation bit-exact from the same P
+        Pf = host(b.get_P(k, 0))
+        perm = res["perm"][k]
+        assert is_perm(perm, n)
+        assert list(O.hungarian_max(Pf)) == list(perm)
+        assert res["score"][k] == O.qap_value(g.A, g.B, perm)
+        mr_b, mr_o = O.match_ratio(perm, g.truth), O.match_ratio(ref.perm, g.truth)
+        print(f"  fw {int(res['fw_iters'][k][0])} vs {ref.fw_iters}; match {mr_b:.4f} vs {mr_o:.4f}")
+    b.close()
+
+
+def test_batch_matches_single_solver(G):
+    graphs = [I.rho_er_pair(n, p, rho, s) for (n, p, rho, s) in ORACLE_PAIRS]
+    res = G.solve_batch([(dev(g.A), dev(g.B)) for g in graphs], restarts=1, sk_max=500)
+    for k, g in enumerate(graphs):
+        r = G.solve(dev(g.A), dev(g.B), prec="fp32", sk_max=500)
+        h = res["history"][k]
+        print(f"pair {k}: fw batch {len(h)} single {len(r.history)}; sk iters "
+              f"{[x['sk_iters'] for x in h]} vs {[x['sk_iters'] for x in r.history]}")
+        for f in range(min(3, len(h), len(r.history))):
+            assert h[f]["fP"] == pytest.approx(r.history[f]["fP"], rel=1e-5)
+            assert h[f]["t"] == pytest.approx(r.history[f]["t"], abs=1e-4)
+
+
+def test_batch_random_starts_and_choice(G):
+    batch = I.workload_batch(npairs=3, restarts=3, n_lo=40, n_hi=90, seed_offset=40)
+    b = G.Batch([(dev(g.A), dev(g.B), dev(U)) for (g, U) in batch], restarts=3, sk_max=500)
+    b.launch()
+    res = b.results()
+    for k, (g, U) in enumerate(batch):
+        n = g.A.shape[0]
+        scores = res["all_scores"][k]
+        best = int(np.argmax(scores))       # first maximum = lowest start index
+        assert int(res["best"][k]) == best
+        assert res["score"][k] == scores[best]
+        assert res["score"][k] == O.qap_value(g.A, g.B, res["perm"][k])
+        for r in range(3):
+            P0 = O.random_init(U[r * n:(r + 1) * n].astype(np.float64))
+            ref = O.goat(g.A, g.B, P0=P0, opt=O.GoatOptions(sk_max=500, fw_max=2), record=True)
+            h = res["history"][k * 3 + r]
+            print(f"pair {k} n={n} start {r}: fP {h[0]['fP']:.6f} vs {ref.history[0]['fP']:.6f}")
+            assert h[0]["fP"] == pytest.approx(ref.history[0]["fP"], rel=1e-5)
+            assert h[0]["c"] == pytest.approx(ref.history[0]["c"], rel=1e-5)
+    b.close()
+
+
+def test_batch_every_bucket_and_edges(G):
+    sizes = [1, 2, 31, 33, 64, 65, 129, 257, 513, 1024]
+    graphs = [I.rho_er_pair(n, min(0.5, 8.0 / max(n, 2)), 0.9, 500 + n) for n in sizes]
+    res = G.solve_batch([(dev(g.A), dev(g.B)) for g in graphs], restarts=2, sk_max=100, fw_max=3)
+    st = res["stats"]
+    print(f"edges: launches {st.launches}, graph {st.ms_graph:.1f} ms, lap {st.ms_lap:.1f} ms")
+    for k, g in enumerate(graphs):
+        n = sizes[k]
+        h0, h1 = res["history"][2 * k], res["history"][2 * k + 1]
+        assert all(np.isfinite(x["fP"]) and np.isfinite(x["t"]) for x in h0)
+        # both starts are J: identical work, identical results
+        assert h0 == h1
+        assert res["all_scores"][k][0] == res["all_scores"][k][1]
+        assert is_perm(res["perm"][k], n)
+        assert res["score"][k] == O.qap_value(g.A, g.B, res["perm"][k])
+    assert res["history"][0][0]["eps"] == 0.0      # n = 1: grad f = 0, Q = J
+
+
+def test_batch_general_pairs(G):
+    pairs = [(I.random_matrix(n, n, 60 + n, 0, 1), I.random_matrix(n, n, 61 + n, 0, 1)) for n in (40, 70)]
+    res = G.solve_batch([(dev(A), dev(B)) for (A, B) in pairs], restarts=1, symmetric=0, sk_max=300, fw_max=2)
+    for k, (A, B) in enumerate(pairs):
+        ref = O.goat(A, B, opt=O.GoatOptions(sk_max=300, fw_max=2), record=True)
+        h = res["history"][k]
+        assert h[0]["fP"] == pytest.approx(ref.history[0]["fP"], rel=1e-6)
+        assert h[0]["t"] == pytest.approx(ref.history[0]["t"], abs=1e-4)
+        assert res["score"][k] == pytest.approx(O.qap_value(A, B, res["perm"][k]), rel=1e-12)
+
+
+def test_batch_graph_relaunch_deterministic(G):
+    batch = I.workload_batch(npairs=6, restarts=2, n_lo=50, n_hi=200, seed_offset=41)
+    b = G.Batch([(dev(g.A), dev(g.B), dev(U)) for (g, U) in batch], restarts=2, sk_max=300, fw_max=6)
+    outs = []
+    for rep in range(3):
+        b.launch()
+        outs.append(b.results())
+        x = torch.randn(512, 512, device="cuda")          # eager work between replays
+        (x @ x).sum().item()
+    for o in outs[1:]:
+        assert np.array_equal(o["all_scores"], outs[0]["all_scores"])
+        assert o["history"] == outs[0]["history"]
+        for p, q in zip(o["perm"], outs[0]["perm"]):
+            assert np.array_equal(p, q)
+    b.close()
+
+
+def test_tune_then_solve(G):
+    graphs = [I.rho_er_pair(n, 0.1, 0.8, 700 + n) for n in (60, 120, 250)]
+    before = G.solve_batch([(dev(g.A), dev(g.B)) for g in graphs], restarts=1, sk_max=300, fw_max=3)
+    G.tune(300, reps=1)
+    for n in (60, 120, 250):
+        L, w = G.tune_get(n)
+        print(f"tuned n={n}: lanes/row {L}, waves {w}")
+        assert L in (16, 32, 64) and w in (4, 8)
+    after = G.solve_batch([(dev(g.A), dev(g.B)) for g in graphs], restarts=1, sk_max=300, fw_max=3)
+    for k in range(len(graphs)):
+        assert after["history"][k][0]["fP"] == pytest.approx(before["history"][k][0]["fP"], rel=1e-6)
+        assert after["history"][k][0]["c"] == pytest.approx(before["history"][k][0]["c"], rel=1e-5)
+
+
+def test_batch_fw_tol_stops_early(G):
+    g = I.rho_er_pair(80, 0.1, 0.9, 81)
+    res = G.solve_batch([(dev(g.A), dev(g.B))], restarts=1, sk_max=300, fw_max=10, fw_tol=1e9)
+    assert int(res["fw_iters"][0][0]) == 1
