@@ -31,6 +31,7 @@
 // potentials are arbitrary). Afterwards every term is a column-normalised
 // plan entry (<= 1) and S_i, c_j lie in [1/n, n], so no further shift is
 // needed.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -174,17 +175,23 @@ void sk_row_kernel(SkArgs a) {
         const float4* row_ = reinterpret_cast<const float4*>(a.G + (size_t)(I) * a.ldg);          \
         _Pragma("unroll") for (int c = 0; c < C; ++c) X[c] = row_[min(tid + T * c, n4m1)];        \
     } while (0)
-    // One row k held in XC; the next row is loaded into XN as soon as XC has
-    // been consumed. The row remainder u_rem enters only as the per-row
-    // factor 2^u_rem, which cancels in the row-normalised plan: the sweep
-    // works with y_ij = G_ij kappa + (v_grid + u_grid) + v_rem and applies
-    // 2^u_rem to the row sum for the stop test.
-#define GOAT_ROW_STEP(XC, XN, K)                                                                   \
+#define GOAT_LOAD_U(U, I)                                                                          \
+    do {                                                                                           \
+        if (!FIRST) U = make_float2(a.ug[I], a.us[I]);                                             \
+    } while (0)
+    // One row k held in XC with its potential (u_grid, u_rem) in UC; the next
+    // row and its potential are loaded into XN, UN before row k is used, so
+    // no row starts with a dependent memory round trip. The row remainder
+    // u_rem enters only as the per-row factor 2^u_rem, which cancels in the
+    // row-normalised plan: the sweep works with
+    // y_ij = G_ij kappa + (v_grid + u_grid) + v_rem and applies 2^u_rem to
+    // the row sum for the stop test.
+#define GOAT_ROW_STEP(XC, XN, UC, UN, K)                                                           \
     do {                                                                                           \
         const int i = GOAT_ROW_OF(K);                                                              \
         if (VLDS) asm volatile("" ::: "memory");   /* re-read v from LDS every row */              \
-        const float ug = FIRST ? 0.0f : a.ug[i];                                                   \
-        const float us = (FIRST || PRECISE) ? 0.0f : a.us[i];                                      \
+        const float ug = FIRST ? 0.0f : UC.x;                                                      \
+        const float us = FIRST ? 0.0f : UC.y;                                                      \
         const float uu = ug + us;                                                                  \
         float y[C][4];                                                                             \
         _Pragma("unroll") for (int c = 0; c < C; ++c) {                                            \
@@ -202,7 +209,16 @@ void sk_row_kernel(SkArgs a) {
                 y[c][3] = fmaf(XC[c].w, kappa, g4.w) + uu;                                         \
             }                                                                                      \
         }                                                                                          \
-        if ((K) + 1 < nrows) GOAT_LOAD_ROW(XN, GOAT_ROW_OF((K) + 1));                             \
+        /* XC is consumed before the next row's loads are issued: issued     */                    \
+        /* earlier, they would share the wait for XC (the wait counter is    */                    \
+        /* in order), and the prefetch would no longer overlap the row. The  */                    \
+        /* empty asm statements take y as inputs and order the loads after.  */                    \
+        _Pragma("unroll") for (int c = 0; c < C; ++c)                                              \
+            _Pragma("unroll") for (int e = 0; e < 4; ++e) asm volatile("" ::"v"(y[c][e]));         \
+        if ((K) + 1 < nrows) {                                                                     \
+            GOAT_LOAD_ROW(XN, GOAT_ROW_OF((K) + 1));                                               \
+            GOAT_LOAD_U(UN, GOAT_ROW_OF((K) + 1));                                                 \
+        }                                                                                          \
         float shift = 0.0f;                                                                        \
         if (FIRST) {                                                                               \
             float m = -INFINITY;                                                                   \
@@ -222,7 +238,7 @@ void sk_row_kernel(SkArgs a) {
         const float inv = 1.0f / S;                                                                \
         _Pragma("unroll") for (int c = 0; c < C; ++c)                                              \
             _Pragma("unroll") for (int e = 0; e < 4; ++e) acc[c][e] = fmaf(y[c][e], inv, acc[c][e]); \
-        if (!FIRST) errmax = fmaxf(errmax, fabsf((PRECISE ? S * exp2f(a.us[i]) : S) - 1.0f));       \
+        if (!FIRST) errmax = fmaxf(errmax, fabsf((PRECISE ? S * exp2f(us) : S) - 1.0f));           \
         if (tid == 0) {                                                                            \
             /* new row potential: u - log2 S (first sweep: -max - log2 S); the   */                \
             /* compensated sweep's S excludes 2^u_rem, so u_rem drops out there */                 \
@@ -233,14 +249,19 @@ void sk_row_kernel(SkArgs a) {
             a.uns[i] = r_;                                                                         \
         }                                                                                          \
     } while (0)
-    if (nrows > 0) GOAT_LOAD_ROW(xa, GOAT_ROW_OF(0));
+    float2 ua = make_float2(0.0f, 0.0f), ub = ua;
+    if (nrows > 0) {
+        GOAT_LOAD_ROW(xa, GOAT_ROW_OF(0));
+        GOAT_LOAD_U(ua, GOAT_ROW_OF(0));
+    }
     int par = 0;
     for (int k = 0; k < nrows; k += 2) {
-        GOAT_ROW_STEP(xa, xb, k);
+        GOAT_ROW_STEP(xa, xb, ua, ub, k);
         if (k + 1 >= nrows) break;
-        GOAT_ROW_STEP(xb, xa, k + 1);
+        GOAT_ROW_STEP(xb, xa, ub, ua, k + 1);
     }
 #undef GOAT_ROW_STEP
+#undef GOAT_LOAD_U
 #undef GOAT_LOAD_ROW
 #undef GOAT_ROW_OF
     float* out = a.colpart + (size_t)blockIdx.x * a.np;
@@ -257,13 +278,14 @@ void sk_row_kernel(SkArgs a) {
 }
 
 // Column update: c_j = sum over strips of the partial column sums, summed in
-// a fixed order (strip lane l adds strips l, l + 16, ...; lanes combined in
-// order), then v_j <- v_j - log2 c_j and u <- u_new. 256 threads = 16 float4
-// column groups x 16 strip lanes per block. With check, the largest
-// row-marginal error of the sweep decides convergence first (no update then).
+// a fixed order (strip lane l adds strips l, l + 32, ...; lanes combined in
+// order), then v_j <- v_j - log2 c_j and u <- u_new. 256 threads = 8 float4
+// column groups (one 128-byte line of a partial row) x 32 strip lanes per
+// block, n/32 blocks. With check, the largest row-marginal error of the
+// sweep decides convergence first (no update then).
 __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int check) {
     if (a.ctrl->done) return;
-    __shared__ float4 part[16][16];
+    __shared__ float4 part[32][8];
     __shared__ float red[4];
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
     if (check) {
@@ -282,15 +304,15 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
         }
         if (blockIdx.x == 0 && tid == 0) a.ctrl->err = err;
     }
-    const int cq = tid & 15, sl = tid >> 4;
-    const int j4 = blockIdx.x * 16 + cq;
+    const int cq = tid & 7, sl = tid >> 3;
+    const int j4 = blockIdx.x * 8 + cq;
     const bool ok = 4 * j4 < a.n;
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     if (ok) {
         const float4* cp = reinterpret_cast<const float4*>(a.colpart);
         const size_t stride = (size_t)a.np / 4;
-#pragma unroll 4
-        for (int w = sl; w < W; w += 16) {
+#pragma unroll 8
+        for (int w = sl; w < W; w += 32) {
             const float4 t = cp[(size_t)w * stride + j4];
             acc.x += t.x; acc.y += t.y; acc.z += t.z; acc.w += t.w;
         }
@@ -300,7 +322,7 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
     if (sl == 0 && ok) {
         float4 c = part[0][cq];
 #pragma unroll
-        for (int l = 1; l < 16; ++l) {
+        for (int l = 1; l < 32; ++l) {
             const float4 t = part[l][cq];
             c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
         }
@@ -454,13 +476,26 @@ struct Geometry {
     int T, C, W, rpw;
 };
 
-// Threads per strip: 256 below n = 4096 (512 measured 2% faster at
-// n = 10000), else the smallest of 512 / 1024 that keeps a row's share per
-// thread at <= 40 columns (register budget without spills); beyond
-// n = 20480 the 1024-thread variant is used and spills. The number of strips
-// defaults to 512 (best of 256..1024 at n = 10000); GOAT_SK_GEOM="T,W"
-// overrides both (a measurement knob).
-constexpr int kSkDefaultWG = 512;
+// Strips: below n = 4096, 256 threads and up to 512 strips; from n = 4096,
+// 1024 threads (16 waves) and one strip per compute unit, so every strip
+// streams many rows and the per-strip prologue (potentials into LDS) and
+// epilogue (column partials) are amortised (n = 10,000: 68.6 us per sweep
+// against 81.1 us with 512 x 512 threads). GOAT_SK_GEOM="T,W" overrides
+// both (a measurement knob).
+constexpr int kSkSmallWG = 512;
+
+int cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
 
 Geometry geometry(int n) {
     int env_T = 0, env_W = 0;
@@ -473,13 +508,14 @@ Geometry geometry(int n) {
     }
     Geometry g;
     const int n4 = (n + 3) / 4;
-    g.T = n < 4096 ? 256 : (n4 <= 512 * 10 ? 512 : 1024);
+    const bool large = n >= 4096;
+    g.T = large ? 1024 : 256;
     if (env_T > 0 && n4 <= env_T * 16) g.T = env_T;
     g.C = (n4 + g.T - 1) / g.T;
     const int cs[] = {1, 2, 3, 4, 5, 6, 8, 10, 12, 16};
     for (int c : cs)
         if (c >= g.C) { g.C = c; break; }
-    const int wmax = env_W > 0 ? env_W : kSkDefaultWG;
+    const int wmax = env_W > 0 ? env_W : (large ? std::min(cu_count(), kSkWG) : kSkSmallWG);
     g.W = n < wmax ? n : wmax;
     g.rpw = (n + g.W - 1) / g.W;
     g.W = (n + g.rpw - 1) / g.rpw;
@@ -581,7 +617,7 @@ int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, in
     else rc = first ? launch_row_T<1024, true>(g, a, s) : launch_row_T<1024, false>(g, a, s);
     prof_end(0, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(sk_merge_kernel, dim3((n + 63) / 64), dim3(256), 0, s, a, g.W, check);
+    hipLaunchKernelGGL(sk_merge_kernel, dim3((n + 31) / 32), dim3(256), 0, s, a, g.W, check);
     GOAT_HIP(hipGetLastError());
     return GOAT_OK;
 }
