@@ -40,18 +40,25 @@ MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 # from two rocprofv3 --pmc passes of paper_2111_05366_amd/counters.py
 # (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
 # same counter reads for a device copy of 4 n^2 bytes in the same run. Valid
-# only for the kernel source it was measured on (sha256 of sinkhorn.hip);
-# reported as null otherwise.
-TRAFFIC = {"src_sha256": "5f53785f290d6d72f909c3e3fb9e38dbb29e12ca5e02933be169f101e84d8569",
-           "bytes_per_launch": 422261783}
+# only for the kernel source it was measured on (sha256 of the row-sweep
+# kernel's text in sinkhorn.hip, from its template line to the column-update
+# comment); reported as null otherwise.
+TRAFFIC = {"src_sha256": "21d3dc27c685eb62fb41c4be3ea7ddb096004367f9f49e85ad04df94e86ab5ca",
+           "bytes_per_launch": 411325798}
+
+
+def row_kernel_digest():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2111_05366_amd", "csrc", "sinkhorn.hip")
+    with open(src, encoding="utf-8") as fh:
+        text = fh.read()
+    a = text.index("template <int T, int C, bool FIRST, bool PRECISE, bool VLDS>")
+    b = text.index("// Column update:", a)
+    return hashlib.sha256(text[a:b].encode()).hexdigest()
 
 
 def _traffic():
-    import hashlib
-    src = os.path.join(ROOT, "paper_2111_05366_amd", "csrc", "sinkhorn.hip")
-    with open(src, "rb") as fh:
-        digest = hashlib.sha256(fh.read()).hexdigest()
-    if TRAFFIC["src_sha256"] == digest and TRAFFIC["bytes_per_launch"]:
+    if TRAFFIC["src_sha256"] == row_kernel_digest() and TRAFFIC["bytes_per_launch"]:
         return TRAFFIC["bytes_per_launch"]
     return None
 

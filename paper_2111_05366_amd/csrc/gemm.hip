@@ -9,6 +9,8 @@
 // Block tile 128 x 128, four waves in a 2 x 2 arrangement, each wave a
 // 64 x 64 sub-tile made of 2 x 2 MFMA 32x32 blocks. Double-buffered LDS
 // stages with register-staged global loads (one barrier per k-tile).
+#include <cstdlib>
+
 #include "common.h"
 
 namespace goat {
@@ -164,6 +166,134 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmParams p) {
     store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
+// ------------------------------------------------------------------ bf16, 256 x 256
+
+// Block tile 256 x 256 with four waves, each owning a 128 x 128 sub-tile
+// (4 x 4 MFMA 32x32 blocks: 256 accumulator registers, held in the
+// accumulation register file). Per 32-wide k-tile a wave reads 16 KB of
+// operands from LDS for 32 MFMAs - half the LDS bytes per MFMA of the
+// 128 x 128 tile, whose LDS reads and writes outlast its MFMAs. Two LDS
+// stages (80 KB), one barrier per k-tile; the next k-tile's global loads
+// (four 16-byte chunks per operand and thread, 64 contiguous bytes per
+// row) are in flight during the current tile's MFMAs.
+constexpr int BM2 = 256, BN2 = 256, BK2 = 32, LD2 = BK2 + 8;
+constexpr size_t kLds256 = (size_t)2 * 2 * BM2 * LD2 * sizeof(uint16_t);
+
+template <int OUT>
+__device__ inline void store_tile_256(const GemmParams& p, const f32x16 (&acc)[4][4], int m0, int n0, int wm,
+                                      int wn, int lane) {
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * 128 + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn * 128 + ni * 32 + (lane & 31);
+                const float x = p.alpha * acc[mi][ni][r];
+                if (OUT == OUT_F32) {
+                    if (row < p.m_valid && col < p.n_valid) p.C[(size_t)row * p.ldc + col] = x;
+                } else {
+                    const uint16_t h = f32_to_bf16_rne(x);
+                    const size_t idx = (size_t)row * p.ld_split + col;
+                    p.Chi[idx] = h;
+                    p.Clo[idx] = f32_to_bf16_rne(x - bf16_to_f32(h));
+                }
+            }
+}
+
+template <int OUT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gemm_nt_bf16_256_kernel(GemmParams p) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t smem16[];
+    uint16_t* sA = smem16;                       // [2][BM2 * LD2]
+    uint16_t* sB = smem16 + 2 * BM2 * LD2;       // [2][BN2 * LD2]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_of(p, tm, tn);
+    const int m0 = tm * BM2, n0 = tn * BN2;
+    const int ktiles = p.K / BK2;
+    const int total = ktiles * p.nseg;
+
+    f32x16 acc[4][4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
+
+    // chunk q of a thread: row tid / 4 + 64 q, bf16 columns (tid % 4) * 8 .. + 7
+    // (named registers: an array here ends up in scratch memory)
+    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+    const int lrow = tid >> 2, lkc = (tid & 3) * 8;
+#define GOAT_GLOAD256(T)                                                                          \
+    do {                                                                                          \
+        const int seg_ = (T) / ktiles, kt_ = (T) - seg_ * ktiles;                                 \
+        const uint16_t* X_ = static_cast<const uint16_t*>(p.X[seg_]) +                            \
+                             (size_t)(m0 + lrow) * p.ldx + kt_ * BK2 + lkc;                      \
+        const uint16_t* Z_ = static_cast<const uint16_t*>(p.Z[seg_]) +                            \
+                             (size_t)(n0 + lrow) * p.ldz + kt_ * BK2 + lkc;                      \
+        const size_t sx_ = (size_t)64 * p.ldx, sz_ = (size_t)64 * p.ldz;                          \
+        ra0 = *reinterpret_cast<const uint4*>(X_);                                                \
+        ra1 = *reinterpret_cast<const uint4*>(X_ + sx_);                                          \
+        ra2 = *reinterpret_cast<const uint4*>(X_ + 2 * sx_);                                      \
+        ra3 = *reinterpret_cast<const uint4*>(X_ + 3 * sx_);                                      \
+        rb0 = *reinterpret_cast<const uint4*>(Z_);                                                \
+        rb1 = *reinterpret_cast<const uint4*>(Z_ + sz_);                                          \
+        rb2 = *reinterpret_cast<const uint4*>(Z_ + 2 * sz_);                                      \
+        rb3 = *reinterpret_cast<const uint4*>(Z_ + 3 * sz_);                                      \
+    } while (0)
+#define GOAT_SSTORE256(BUF)                                                                       \
+    do {                                                                                          \
+        uint16_t* a_ = sA + (BUF) * BM2 * LD2 + lrow * LD2 + lkc;                                 \
+        uint16_t* b_ = sB + (BUF) * BN2 * LD2 + lrow * LD2 + lkc;                                 \
+        *reinterpret_cast<uint4*>(a_) = ra0;                                                      \
+        *reinterpret_cast<uint4*>(a_ + 64 * LD2) = ra1;                                           \
+        *reinterpret_cast<uint4*>(a_ + 128 * LD2) = ra2;                                          \
+        *reinterpret_cast<uint4*>(a_ + 192 * LD2) = ra3;                                          \
+        *reinterpret_cast<uint4*>(b_) = rb0;                                                      \
+        *reinterpret_cast<uint4*>(b_ + 64 * LD2) = rb1;                                           \
+        *reinterpret_cast<uint4*>(b_ + 128 * LD2) = rb2;                                          \
+        *reinterpret_cast<uint4*>(b_ + 192 * LD2) = rb3;                                          \
+    } while (0)
+
+    GOAT_GLOAD256(0);
+    GOAT_SSTORE256(0);
+    __syncthreads();
+    const int arow = (wm * 128 + (lane & 31)) * LD2 + (lane >> 5) * 8;
+    const int brow = (wn * 128 + (lane & 31)) * LD2 + (lane >> 5) * 8;
+    for (int t = 0; t < total; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < total) GOAT_GLOAD256(t + 1);
+        const uint16_t* sa = sA + buf * BM2 * LD2;
+        const uint16_t* sb = sB + buf * BN2 * LD2;
+#pragma unroll
+        for (int ks = 0; ks < BK2 / 16; ++ks) {
+            bf16x8 a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = *reinterpret_cast<const bf16x8*>(sa + arow + i * 32 * LD2 + ks * 16);
+                b[i] = *reinterpret_cast<const bf16x8*>(sb + brow + i * 32 * LD2 + ks * 16);
+            }
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 4; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+            // one k-step's operands live at a time (hoisting all of them
+            // would push the staging registers out to scratch)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (t + 1 < total) GOAT_SSTORE256(buf ^ 1);
+        __syncthreads();
+    }
+#undef GOAT_GLOAD256
+#undef GOAT_SSTORE256
+    store_tile_256<OUT>(p, acc, m0, n0, wm, wn, lane);
+}
+
 // ------------------------------------------------------------------ fp32
 
 constexpr int BK32 = 16;                 // k-tile (float elements)
@@ -261,6 +391,23 @@ __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmParams p) {
     store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
+// bf16 products use the 128 x 128 tile: the 256 x 256 tile measured slower
+// at n = 10,000 (782 against 957 TFLOP/s executed; one wave per SIMD leaves
+// its LDS and global latencies exposed). GOAT_GEMM_TILE=256 selects it (a
+// measurement knob).
+bool use_tile256(int M, int N, int K) {
+    static const bool want256 = [] {
+        const char* e = getenv("GOAT_GEMM_TILE");
+        return e && e[0] == '2' && e[1] == '5' && e[2] == '6';
+    }();
+    static const bool lds_ok =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_256_kernel<OUT_F32>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds256) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_256_kernel<OUT_BF16_SPLIT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds256) == hipSuccess;
+    return want256 && lds_ok && M % BM2 == 0 && N % BN2 == 0 && K % BK2 == 0;
+}
+
 }  // namespace
 
 int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz, const GemmSegs& segs,
@@ -287,11 +434,15 @@ int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz, const Gem
     p.Chi = C_hi;
     p.Clo = C_lo;
     p.ld_split = ld_split;
-    p.tiles_m = M / BM;
-    p.tiles_n = N / BN;
+    const bool big = is_bf16 && use_tile256(M, N, K);
+    p.tiles_m = M / (big ? BM2 : BM);
+    p.tiles_n = N / (big ? BN2 : BN);
     dim3 grid(p.tiles_m * p.tiles_n), block(256);
     prof_begin(1, s);
-    if (is_bf16) {
+    if (big) {
+        if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_256_kernel<OUT_F32>, grid, block, kLds256, s, p);
+        else hipLaunchKernelGGL(gemm_nt_bf16_256_kernel<OUT_BF16_SPLIT>, grid, block, kLds256, s, p);
+    } else if (is_bf16) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_F32>, grid, block, 0, s, p);
         else hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_BF16_SPLIT>, grid, block, 0, s, p);
     } else {

@@ -288,6 +288,21 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
     __shared__ float4 part[32][8];
     __shared__ float red[4];
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+    // the partial loads are issued before the convergence check so that the
+    // two memory round trips overlap
+    const int cq = tid & 7, sl = tid >> 3;
+    const int j4 = blockIdx.x * 8 + cq;
+    const bool ok = 4 * j4 < a.n;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ok) {
+        const float4* cp = reinterpret_cast<const float4*>(a.colpart);
+        const size_t stride = (size_t)a.np / 4;
+#pragma unroll 8
+        for (int w = sl; w < W; w += 32) {
+            const float4 t = cp[(size_t)w * stride + j4];
+            acc.x += t.x; acc.y += t.y; acc.z += t.z; acc.w += t.w;
+        }
+    }
     if (check) {
         float m = 0.0f;
         for (int w = tid; w < W; w += 256) m = fmaxf(m, a.errpart[w]);
@@ -303,19 +318,6 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
             return;
         }
         if (blockIdx.x == 0 && tid == 0) a.ctrl->err = err;
-    }
-    const int cq = tid & 7, sl = tid >> 3;
-    const int j4 = blockIdx.x * 8 + cq;
-    const bool ok = 4 * j4 < a.n;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (ok) {
-        const float4* cp = reinterpret_cast<const float4*>(a.colpart);
-        const size_t stride = (size_t)a.np / 4;
-#pragma unroll 8
-        for (int w = sl; w < W; w += 32) {
-            const float4 t = cp[(size_t)w * stride + j4];
-            acc.x += t.x; acc.y += t.y; acc.z += t.z; acc.w += t.w;
-        }
     }
     part[sl][cq] = acc;
     __syncthreads();
