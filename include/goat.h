@@ -53,6 +53,7 @@ extern "C" {
 #define GOAT_PREC_FP32    0
 #define GOAT_PREC_BF16X2  1
 #define GOAT_PREC_BF16X3  2
+#define GOAT_PREC_FP8     3
 
 /* Sinkhorn starting potentials. */
 #define GOAT_INIT_COLD  0   /* g = 0                                   */
@@ -75,7 +76,12 @@ size_t goat_workspace_size(int n, int prec, int symmetric);
  * symmetric != 0 the caller promises A = A^T and B = B^T and the library
  * evaluates G = 2 A P B (two products instead of four). prec selects the
  * arithmetic (GOAT_PREC_*). BF16X2 requires A and B exactly representable
- * in bf16 (e.g. 0/1 adjacency); it is the caller's promise.
+ * in bf16 (e.g. 0/1 adjacency); it is the caller's promise. FP8 requires A
+ * and B exactly representable in FP8 E4M3 (0/1 adjacency, small integers);
+ * P and the intermediate product enter as three E4M3 terms each (term t of
+ * x is E4M3 of the residual times 2^(s + 4t), s from max|x|), so the
+ * products run on the FP8 matrix cores with FP32 accumulation and about 12
+ * significant bits per operand element.
  */
 int goat_grad(int n, const float* A, const float* B, int ld,
               const float* P, int ldp, float* G, int ldg,

@@ -43,6 +43,14 @@ Layout make_layout(int n, int prec, int sym) {
     L.GQ = take(pl * 4);
     // packed operands
     const int rows = L.sym ? 1 : 2;
+    if (prec == GOAT_PREC_FP8) {
+        L.opA = take(pl * rows);                          // E4M3
+        L.opB = take(pl * rows);
+        L.opP = take(pl * kFp8Terms);                     // term planes of P (or Q)
+        L.opY = take(pl * rows * 4 + pl * rows * kFp8Terms);   // fp32 Y^T, then its terms
+        L.total = o;
+        return L;
+    }
     const size_t op_elt = prec == GOAT_PREC_FP32 ? 4 : 2;
     const int op_planes = prec == GOAT_PREC_BF16X3 ? 2 : 1;
     L.opA = take(pl * rows * op_elt * op_planes);
@@ -60,7 +68,53 @@ size_t small_bytes(const Layout& L) { return L.P; }
 // Symmetric: Y^T = B P^T (= (P B)^T) then G = 2 A Y. General: the stacked
 // [B; B^T] P^T gives (P B^T)^T and (P B)^T, then
 // G = A (P B^T) + A^T (P B) as one product over two k-segments.
+// FP8 (0/1 A, B exact in E4M3): the P-side operand and Y^T enter as three
+// E4M3 terms each, k-concatenated segments scaled back on the matrix cores.
+static int grad_packed_fp8(const Layout& L, const GradOps& o, float* G, int ldg, int m_valid, hipStream_t s) {
+    const int np = L.np;
+    const size_t pl = (size_t)np * np;
+    const int rows = L.sym ? 1 : 2;
+    const uint8_t* P8 = static_cast<const uint8_t*>(o.P_hi);
+    GemmSegs s1{};
+    for (int t = 0; t < kFp8Terms; ++t) {
+        s1.X[t] = o.B_hi;
+        s1.Z[t] = P8 + t * pl;
+        s1.zterm[t] = t;
+    }
+    s1.nseg = kFp8Terms;
+    s1.zmax = o.P_max;
+    float* Y = static_cast<float*>(o.Y_hi);
+    uint8_t* Y8 = static_cast<uint8_t*>(o.Y_lo);
+    int rc = launch_gemm_nt(GEMM_FP8, rows * np, np, np, np, np, s1, 1.0f, OUT_F32, Y, np, rows * np, np, nullptr,
+                            nullptr, 0, s);
+    if (!rc) rc = launch_absmax_rect(rows * np, np, Y, np, o.max_partial, o.Y_max, s);
+    if (!rc) rc = launch_split_fp8(rows * np, np, rows * np, np, Y, np, o.Y_max, Y8, pl * rows, s);
+    if (rc) return rc;
+    GemmSegs s2{};
+    int k = 0;
+    for (int h = 0; h < rows; ++h)
+        for (int t = 0; t < kFp8Terms; ++t) {
+            s2.X[k] = static_cast<const uint8_t*>(o.A_hi) + h * pl;     // A (h=0) or A^T (h=1)
+            s2.Z[k] = Y8 + t * pl * rows + h * pl;                     // term t of (P B^T)^T or (P B)^T
+            s2.zterm[k] = t;
+            ++k;
+        }
+    s2.nseg = k;
+    s2.zmax = o.Y_max;
+    return launch_gemm_nt(GEMM_FP8, np, np, np, np, np, s2, L.sym ? 2.0f : 1.0f, OUT_F32, G, ldg, m_valid, m_valid,
+                          nullptr, nullptr, 0, s);
+}
+
+int prep_fp8_operand(const Layout& L, const GradOps& o, const float* src, int ld, hipStream_t s) {
+    float* pmax = const_cast<float*>(o.P_max);
+    int rc = launch_absmax_rect(L.n, L.n, src, ld, o.max_partial, pmax, s);
+    if (rc) return rc;
+    return launch_split_fp8(L.n, L.n, L.np, L.np, src, ld, pmax,
+                            static_cast<uint8_t*>(const_cast<void*>(o.P_hi)), (size_t)L.np * L.np, s);
+}
+
 int grad_packed(const Layout& L, const GradOps& o, float* G, int ldg, int m_valid, hipStream_t s) {
+    if (L.prec == GOAT_PREC_FP8) return grad_packed_fp8(L, o, G, ldg, m_valid, s);
     const int np = L.np;
     const size_t pl = (size_t)np * np;
     const int rows = L.sym ? 1 : 2;
@@ -80,7 +134,7 @@ int grad_packed(const Layout& L, const GradOps& o, float* G, int ldg, int m_vali
         s1.X[1] = o.B_hi; s1.Z[1] = o.P_lo;
         s1.X[2] = o.B_lo; s1.Z[2] = o.P_hi; s1.nseg = 3;
     }
-    int rc = launch_gemm_nt(bf, rows * np, np, np, np, np, s1, 1.0f, bf ? OUT_BF16_SPLIT : OUT_F32,
+    int rc = launch_gemm_nt(bf ? GEMM_BF16 : GEMM_F32, rows * np, np, np, np, np, s1, 1.0f, bf ? OUT_BF16_SPLIT : OUT_F32,
                             static_cast<float*>(o.Y_hi), np, rows * np, np,
                             static_cast<uint16_t*>(o.Y_hi), static_cast<uint16_t*>(o.Y_lo), np, s);
     if (rc) return rc;
@@ -101,7 +155,7 @@ int grad_packed(const Layout& L, const GradOps& o, float* G, int ldg, int m_vali
         }
     }
     s2.nseg = k;
-    return launch_gemm_nt(bf, np, np, np, np, np, s2, L.sym ? 2.0f : 1.0f, OUT_F32, G, ldg, m_valid,
+    return launch_gemm_nt(bf ? GEMM_BF16 : GEMM_F32, np, np, np, np, np, s2, L.sym ? 2.0f : 1.0f, OUT_F32, G, ldg, m_valid,
                           m_valid, nullptr, nullptr, 0, s);
 }
 
@@ -115,15 +169,26 @@ Ptrs make_ptrs(const Layout& L, void* ws) {
     p.Q = reinterpret_cast<float*>(b + L.Q);
     p.GP = reinterpret_cast<float*>(b + L.GP);
     p.GQ = reinterpret_cast<float*>(b + L.GQ);
-    const size_t op_elt = L.prec == GOAT_PREC_FP32 ? 4 : 2;
-    p.A_hi = b + L.opA;
-    p.A_lo = b + L.opA + pl * rows * op_elt;
-    p.B_hi = b + L.opB;
-    p.B_lo = b + L.opB + pl * rows * op_elt;
-    p.P_hi = b + L.opP;
-    p.P_lo = b + L.opP + pl * 2;
-    p.Y_hi = b + L.opY;
-    p.Y_lo = b + L.opY + pl * rows * 2;
+    if (L.prec == GOAT_PREC_FP8) {
+        p.A_hi = b + L.opA;
+        p.A_lo = nullptr;
+        p.B_hi = b + L.opB;
+        p.B_lo = nullptr;
+        p.P_hi = b + L.opP;
+        p.P_lo = nullptr;
+        p.Y_hi = b + L.opY;
+        p.Y_lo = b + L.opY + pl * rows * 4;
+    } else {
+        const size_t op_elt = L.prec == GOAT_PREC_FP32 ? 4 : 2;
+        p.A_hi = b + L.opA;
+        p.A_lo = b + L.opA + pl * rows * op_elt;
+        p.B_hi = b + L.opB;
+        p.B_lo = b + L.opB + pl * rows * op_elt;
+        p.P_hi = b + L.opP;
+        p.P_lo = b + L.opP + pl * 2;
+        p.Y_hi = b + L.opY;
+        p.Y_lo = b + L.opY + pl * rows * 2;
+    }
     p.sk.ctrl = reinterpret_cast<SkCtrl*>(b + L.ctrl);
     float* pot = reinterpret_cast<float*>(b + L.pot);
     p.sk.ug = pot;
@@ -145,8 +210,10 @@ Ptrs make_ptrs(const Layout& L, void* ws) {
 }
 
 int pack_graph(const Layout& L, const float* X, int ld, void* hi, void* lo, hipStream_t s) {
-    const int mode = L.prec == GOAT_PREC_FP32 ? PACK_F32 : (L.prec == GOAT_PREC_BF16X2 ? PACK_BF16 : PACK_BF16_SPLIT);
-    const size_t es = L.prec == GOAT_PREC_FP32 ? 4 : 2;
+    const int mode = L.prec == GOAT_PREC_FP32 ? PACK_F32
+                     : L.prec == GOAT_PREC_FP8 ? PACK_FP8
+                     : (L.prec == GOAT_PREC_BF16X2 ? PACK_BF16 : PACK_BF16_SPLIT);
+    const size_t es = L.prec == GOAT_PREC_FP32 ? 4 : (L.prec == GOAT_PREC_FP8 ? 1 : 2);
     const size_t pl = (size_t)L.np * L.np;
     int rc = launch_pack(X, ld, L.n, L.np, 0, mode, hi, lo, s);
     if (rc || L.sym) return rc;
@@ -158,6 +225,10 @@ GradOps grad_ops(const Ptrs& p) {
     GradOps o;
     o.A_hi = p.A_hi; o.A_lo = p.A_lo; o.B_hi = p.B_hi; o.B_lo = p.B_lo;
     o.P_hi = p.P_hi; o.P_lo = p.P_lo; o.Y_hi = p.Y_hi; o.Y_lo = p.Y_lo;
+    // FP8 maxima: fscal[1] (P-side operand), fscal[2] (Y^T); partials at fscal + 16
+    o.P_max = p.fscal + 1;
+    o.Y_max = p.fscal + 2;
+    o.max_partial = p.fscal + 16;
     return o;
 }
 
@@ -174,7 +245,7 @@ int goat_version(void) { return 100; }
 const char* goat_last_error(void) { return g_last_error.c_str(); }
 
 size_t goat_workspace_size(int n, int prec, int symmetric) {
-    if (n < 1 || prec < GOAT_PREC_FP32 || prec > GOAT_PREC_BF16X3) return 0;
+    if (n < 1 || prec < GOAT_PREC_FP32 || prec > GOAT_PREC_FP8) return 0;
     return make_layout(n, prec, symmetric).total;
 }
 
@@ -200,7 +271,7 @@ int goat_grad(int n, const float* A, const float* B, int ld, const float* P, int
     GOAT_CHECK_ARG(n >= 1, "n < 1");
     GOAT_CHECK_ARG(A && B && P && G && ws, "null pointer");
     GOAT_CHECK_ARG(ld >= n && ldp >= n && ldg >= n, "leading dimension < n");
-    GOAT_CHECK_ARG(prec >= GOAT_PREC_FP32 && prec <= GOAT_PREC_BF16X3, "unknown precision");
+    GOAT_CHECK_ARG(prec >= GOAT_PREC_FP32 && prec <= GOAT_PREC_FP8, "unknown precision");
     const Layout L = make_layout(n, prec, symmetric);
     if (ws_bytes < L.total) { set_error("goat_grad: workspace too small"); return GOAT_ENOMEM; }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -208,7 +279,8 @@ int goat_grad(int n, const float* A, const float* B, int ld, const float* P, int
     int rc = pack_graph(L, A, ld, p.A_hi, p.A_lo, s);
     if (!rc) rc = pack_graph(L, B, ld, p.B_hi, p.B_lo, s);
     if (rc) return rc;
-    if (prec == GOAT_PREC_FP32) rc = launch_copy_pad(n, P, ldp, static_cast<float*>(p.P_hi), L.np, L.np, s);
+    if (prec == GOAT_PREC_FP8) rc = prep_fp8_operand(L, grad_ops(p), P, ldp, s);
+    else if (prec == GOAT_PREC_FP32) rc = launch_copy_pad(n, P, ldp, static_cast<float*>(p.P_hi), L.np, L.np, s);
     else rc = launch_split_bf16(n, L.np, P, ldp, static_cast<uint16_t*>(p.P_hi), static_cast<uint16_t*>(p.P_lo), s);
     if (rc) return rc;
     return grad_packed(L, grad_ops(p), G, ldg, n, s);

@@ -86,22 +86,77 @@ __host__ __device__ inline float bf16_to_f32(uint16_t h) {
     return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
 
+// OCP FP8 E4M3 (sign, 4 exponent bits with bias 7, 3 mantissa bits; no
+// infinities; largest finite 448; subnormals m * 2^-9). Encoding rounds to
+// nearest, ties to even, and saturates at +-448; NaN is not produced for
+// finite input.
+__host__ __device__ inline uint8_t f32_to_e4m3_rne(float x) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    const uint8_t sign = (uint8_t)((u >> 31) << 7);
+    const float a = __builtin_fabsf(x);
+    if (!(a > 0.0f)) return sign;                       // zero (or NaN: encoded as zero)
+    if (a >= 448.0f) return (uint8_t)(sign | 0x7E);     // saturate
+    const int E = (int)((u >> 23) & 0xFF) - 127;
+    if (E < -6) {                                       // subnormal: m * 2^-9, m = 0..8
+        const int m = (int)__builtin_rintf(a * 512.0f);
+        return (uint8_t)(sign | (m >= 8 ? 0x08 : m));
+    }
+    uint32_t q = ((u & 0x7FFFFFu) | 0x800000u) >> 20;   // 1.mmm (4 bits)
+    const uint32_t rem = u & 0xFFFFFu, half = 0x80000u;
+    if (rem > half || (rem == half && (q & 1u))) ++q;
+    int e = E;
+    if (q == 16u) { q = 8u; ++e; }
+    if (e > 8 || (e == 8 && q > 14u)) return (uint8_t)(sign | 0x7E);
+    return (uint8_t)(sign | ((e + 7) << 3) | (q & 7u));
+}
+__host__ __device__ inline float e4m3_to_f32(uint8_t c) {
+    const int e = (c >> 3) & 15, m = c & 7;
+    const float v = e == 0 ? (float)m * 0.001953125f : __builtin_ldexpf((float)(8 + m), e - 10);
+    return (c & 0x80) ? -v : v;
+}
+// Power-of-two exponent s with max|x| * 2^s <= 448 (the first FP8 term of a
+// split); 0 for an all-zero matrix.
+__host__ __device__ inline int fp8_split_exponent(float absmax) {
+    if (!(absmax > 0.0f)) return 0;
+    int e = 0;
+    __builtin_frexpf(448.0f / absmax, &e);              // 448 / absmax in [2^(e-1), 2^e)
+    int s = e - 1;
+    if (__builtin_ldexpf(absmax, s) > 448.0f) --s;
+    return s < -100 ? -100 : (s > 100 ? 100 : s);
+}
+constexpr int kFp8Terms = 3;       // FP8 terms of a split operand
+constexpr int kFp8TermShift = 4;   // term t is scaled by 2^(s + 4 t)
+
 // ---------------------------------------------------------------- launchers
 
 // Operand packing into padded internal planes (pack.hip).
-enum PackMode { PACK_F32 = 0, PACK_BF16 = 1, PACK_BF16_SPLIT = 2 };
+enum PackMode { PACK_F32 = 0, PACK_BF16 = 1, PACK_BF16_SPLIT = 2, PACK_FP8 = 3 };
 int launch_pack(const float* src, int ld, int n, int np, int transpose, int mode,
                 void* dst_hi, void* dst_lo, hipStream_t s);
+// rows x cols block of src (row stride ld) -> max |x| into *out (pack.hip)
+int launch_absmax_rect(int rows, int cols, const float* src, int ld, float* partial, float* out,
+                       hipStream_t s);
+// rows x cols block of src -> kFp8Terms zero-padded E4M3 planes (np columns,
+// plane stride plane_bytes): term t = e4m3(r_t 2^(s + 4t)) with r_0 = x,
+// r_{t+1} = r_t - term_t 2^-(s + 4t), s = fp8_split_exponent(*absmax)
+// (pack.hip). Rows past `rows` up to prow are written as zeros.
+int launch_split_fp8(int rows, int cols, int prow, int np, const float* src, int ld, const float* absmax,
+                     uint8_t* planes, size_t plane_bytes, hipStream_t s);
 
 // C[i][j] = alpha * sum_s sum_k X_s[i][k] Z_s[j][k]  (gemm.hip)
 enum OutMode { OUT_F32 = 0, OUT_BF16_SPLIT = 1 };
+enum GemmKind { GEMM_F32 = 0, GEMM_BF16 = 1, GEMM_FP8 = 2 };
 constexpr int kMaxSeg = 6;
 struct GemmSegs {
     const void* X[kMaxSeg];
     const void* Z[kMaxSeg];
     int nseg;
+    // FP8 only: Z_s holds term (zterm[s]) of a split whose exponent follows
+    // from *zmax; the product is scaled back by 2^-(s + 4 zterm[s])
+    int zterm[kMaxSeg];
+    const float* zmax;
 };
-int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz,
+int launch_gemm_nt(int kind, int M, int N, int K, int ldx, int ldz,
                    const GemmSegs& segs, float alpha,
                    int out_mode, float* C, int ldc, int m_valid, int n_valid,
                    uint16_t* C_hi, uint16_t* C_lo, int ld_split,
@@ -111,9 +166,16 @@ int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz,
 struct GradOps {
     const void* A_hi; const void* A_lo;     // [A; A^T] when general
     const void* B_hi; const void* B_lo;     // [B; B^T] when general
-    const void* P_hi; const void* P_lo;     // P-side operand (fp32 in P_hi for FP32)
-    void* Y_hi; void* Y_lo;                 // intermediate
+    const void* P_hi; const void* P_lo;     // P-side operand (fp32 in P_hi for FP32;
+                                            // FP8: the term planes in P_hi)
+    void* Y_hi; void* Y_lo;                 // intermediate (FP8: fp32 in Y_hi, terms in Y_lo)
+    const float* P_max;                     // FP8: max |P-side operand| of its split
+    float* Y_max;                           // FP8: max |intermediate|
+    float* max_partial;                     // FP8: kRedWG floats for the maxima
 };
+// FP8 form: split an n x n fp32 operand (leading dimension ld) into the
+// E4M3 term planes of P_hi, its maximum into P_max (api.cpp).
+int prep_fp8_operand(const Layout& L, const GradOps& o, const float* src, int ld, hipStream_t s);
 int grad_packed(const Layout& L, const GradOps& ops, float* G, int ldg, int m_valid,
                 hipStream_t s);
 

@@ -18,12 +18,15 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 128, BN = 128;
 
 struct GemmParams {
     const void* X[kMaxSeg];
     const void* Z[kMaxSeg];
+    int zterm[kMaxSeg];
+    const float* zmax;
     int nseg, K, ldx, ldz;
     float alpha;
     float* C;
@@ -163,6 +166,104 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmParams p) {
     }
 #undef GOAT_GLOAD16
 #undef GOAT_SSTORE16
+    store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
+}
+
+// ------------------------------------------------------------------ fp8
+
+// FP8 E4M3 operands (one byte per element), same block and wave tiles as
+// the bf16 kernel; a k-tile is 128 bytes = 128 elements, so a stage moves the
+// same bytes as a bf16 stage but covers twice the contraction. Each wave
+// step is v_mfma_scale_f32_32x32x64_f8f6f4: lane l supplies 32 consecutive k
+// of row l % 32 (lane halves take k and k + 32) for both operands, and the
+// E8M0 scale of the Z operand undoes segment s's split factor
+// 2^(e + 4 zterm[s]) exactly (X operands are exact, scale 2^0).
+constexpr int BK8 = 128;                 // k-tile (bytes = elements)
+constexpr int LD8 = BK8 + 16;            // LDS row stride (bytes), 16 B pad
+
+template <int OUT>
+__global__ __launch_bounds__(256) void gemm_nt_fp8_kernel(GemmParams p) {
+    __shared__ __attribute__((aligned(16))) uint8_t sA[2][BM * LD8];
+    __shared__ __attribute__((aligned(16))) uint8_t sB[2][BN * LD8];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_of(p, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    const int ktiles = p.K / BK8;
+    const int total = ktiles * p.nseg;
+    const int zexp = fp8_split_exponent(*p.zmax);
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
+
+    // global -> register staging of one k-tile: 128 rows x 128 bytes per
+    // operand, four 16-byte chunks per thread (row = c / 8, chunk = c % 8)
+    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+    const int lrow = tid >> 3, lkc = (tid & 7) * 16;
+#define GOAT_GLOAD8(T)                                                                            \
+    do {                                                                                          \
+        const int seg_ = (T) / ktiles, kt_ = (T) - seg_ * ktiles;                                 \
+        const uint8_t* X_ = static_cast<const uint8_t*>(p.X[seg_]) +                              \
+                            (size_t)(m0 + lrow) * p.ldx + kt_ * BK8 + lkc;                       \
+        const uint8_t* Z_ = static_cast<const uint8_t*>(p.Z[seg_]) +                              \
+                            (size_t)(n0 + lrow) * p.ldz + kt_ * BK8 + lkc;                       \
+        const size_t sx_ = (size_t)32 * p.ldx, sz_ = (size_t)32 * p.ldz;                          \
+        ra0 = *reinterpret_cast<const uint4*>(X_);                                                \
+        ra1 = *reinterpret_cast<const uint4*>(X_ + sx_);                                          \
+        ra2 = *reinterpret_cast<const uint4*>(X_ + 2 * sx_);                                      \
+        ra3 = *reinterpret_cast<const uint4*>(X_ + 3 * sx_);                                      \
+        rb0 = *reinterpret_cast<const uint4*>(Z_);                                                \
+        rb1 = *reinterpret_cast<const uint4*>(Z_ + sz_);                                          \
+        rb2 = *reinterpret_cast<const uint4*>(Z_ + 2 * sz_);                                      \
+        rb3 = *reinterpret_cast<const uint4*>(Z_ + 3 * sz_);                                      \
+    } while (0)
+#define GOAT_SSTORE8(BUF)                                                                         \
+    do {                                                                                          \
+        uint8_t* a_ = &sA[BUF][lrow * LD8 + lkc];                                                 \
+        uint8_t* b_ = &sB[BUF][lrow * LD8 + lkc];                                                 \
+        *reinterpret_cast<uint4*>(a_) = ra0;                                                      \
+        *reinterpret_cast<uint4*>(a_ + 32 * LD8) = ra1;                                           \
+        *reinterpret_cast<uint4*>(a_ + 64 * LD8) = ra2;                                           \
+        *reinterpret_cast<uint4*>(a_ + 96 * LD8) = ra3;                                           \
+        *reinterpret_cast<uint4*>(b_) = rb0;                                                      \
+        *reinterpret_cast<uint4*>(b_ + 32 * LD8) = rb1;                                           \
+        *reinterpret_cast<uint4*>(b_ + 64 * LD8) = rb2;                                           \
+        *reinterpret_cast<uint4*>(b_ + 96 * LD8) = rb3;                                           \
+    } while (0)
+
+    GOAT_GLOAD8(0);
+    GOAT_SSTORE8(0);
+    __syncthreads();
+    const int arow = (wm * 64 + (lane & 31)) * LD8 + (lane >> 5) * 32;
+    const int brow = (wn * 64 + (lane & 31)) * LD8 + (lane >> 5) * 32;
+    for (int t = 0; t < total; ++t) {
+        const int buf = t & 1;
+        const int zscale = 127 - zexp - kFp8TermShift * p.zterm[t / ktiles];
+        if (t + 1 < total) GOAT_GLOAD8(t + 1);
+        const uint8_t* sa = sA[buf];
+        const uint8_t* sb = sB[buf];
+#pragma unroll
+        for (int ks = 0; ks < BK8 / 64; ++ks) {
+            const i32x8 a0 = *reinterpret_cast<const i32x8*>(sa + arow + ks * 64);
+            const i32x8 a1 = *reinterpret_cast<const i32x8*>(sa + arow + 32 * LD8 + ks * 64);
+            const i32x8 b0 = *reinterpret_cast<const i32x8*>(sb + brow + ks * 64);
+            const i32x8 b1 = *reinterpret_cast<const i32x8*>(sb + brow + 32 * LD8 + ks * 64);
+            acc[0][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a0, b0, acc[0][0], 0, 0, 0, 127, 0, zscale);
+            acc[0][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a0, b1, acc[0][1], 0, 0, 0, 127, 0, zscale);
+            acc[1][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a1, b0, acc[1][0], 0, 0, 0, 127, 0, zscale);
+            acc[1][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a1, b1, acc[1][1], 0, 0, 0, 127, 0, zscale);
+        }
+        if (t + 1 < total) GOAT_SSTORE8(buf ^ 1);
+        __syncthreads();
+    }
+#undef GOAT_GLOAD8
+#undef GOAT_SSTORE8
     store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
@@ -410,10 +511,16 @@ bool use_tile256(int M, int N, int K) {
 
 }  // namespace
 
-int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz, const GemmSegs& segs,
+int launch_gemm_nt(int kind, int M, int N, int K, int ldx, int ldz, const GemmSegs& segs,
                    float alpha, int out_mode, float* C, int ldc, int m_valid, int n_valid,
                    uint16_t* C_hi, uint16_t* C_lo, int ld_split, hipStream_t s) {
-    if (M % BM || N % BN || K % (is_bf16 ? BK16 : BK32) || segs.nseg < 1 || segs.nseg > kMaxSeg) {
+    const bool is_bf16 = kind == GEMM_BF16, is_fp8 = kind == GEMM_FP8;
+    const int bk = is_fp8 ? BK8 : (is_bf16 ? BK16 : BK32);
+    if (is_fp8 && (!segs.zmax || out_mode != OUT_F32)) {
+        set_error("launch_gemm_nt: fp8 products need the split maximum and fp32 output");
+        return GOAT_EINVAL;
+    }
+    if (M % BM || N % BN || K % bk || segs.nseg < 1 || segs.nseg > kMaxSeg) {
         set_error("launch_gemm_nt: shape not a multiple of the tile or bad segment count");
         return GOAT_EINVAL;
     }
@@ -421,7 +528,9 @@ int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz, const Gem
     for (int i = 0; i < segs.nseg; ++i) {
         p.X[i] = segs.X[i];
         p.Z[i] = segs.Z[i];
+        p.zterm[i] = segs.zterm[i];
     }
+    p.zmax = segs.zmax;
     p.nseg = segs.nseg;
     p.K = K;
     p.ldx = ldx;
@@ -439,7 +548,9 @@ int launch_gemm_nt(int is_bf16, int M, int N, int K, int ldx, int ldz, const Gem
     p.tiles_n = N / (big ? BN2 : BN);
     dim3 grid(p.tiles_m * p.tiles_n), block(256);
     prof_begin(1, s);
-    if (big) {
+    if (is_fp8) {
+        hipLaunchKernelGGL(gemm_nt_fp8_kernel<OUT_F32>, grid, block, 0, s, p);
+    } else if (big) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_256_kernel<OUT_F32>, grid, block, kLds256, s, p);
         else hipLaunchKernelGGL(gemm_nt_bf16_256_kernel<OUT_BF16_SPLIT>, grid, block, kLds256, s, p);
     } else if (is_bf16) {

@@ -80,7 +80,7 @@ static int run_sinkhorn_polled(Run& r) {
 
 static int run_sinkhorn(Run& r) {
     const int n = r.L.n, np = r.L.np;
-    const bool bf = r.opt.prec != GOAT_PREC_FP32;
+    const bool bf = r.opt.prec == GOAT_PREC_BF16X2 || r.opt.prec == GOAT_PREC_BF16X3;
     Ptrs& p = r.p;
     // warm: 1 previous iteration's column potentials; 2 the network every
     // iteration; 3 the network on the first iteration, then as 1
@@ -107,12 +107,13 @@ static int run_sinkhorn(Run& r) {
 
 static int run_step(Run& r, goat_iter_record* rec) {
     const int n = r.L.n, np = r.L.np;
-    const bool bf = r.opt.prec != GOAT_PREC_FP32;
+    const bool bf = r.opt.prec == GOAT_PREC_BF16X2 || r.opt.prec == GOAT_PREC_BF16X3;
     Ptrs& p = r.p;
     int rc = run_sinkhorn(r);
     if (rc) return rc;
-    if (!bf) r.ops.P_hi = p.Q;
-    rc = grad_packed(r.L, r.ops, p.GQ, np, np, r.s);
+    if (r.opt.prec == GOAT_PREC_FP32) r.ops.P_hi = p.Q;
+    if (r.opt.prec == GOAT_PREC_FP8) rc = prep_fp8_operand(r.L, r.ops, p.Q, np, r.s);
+    if (!rc) rc = grad_packed(r.L, r.ops, p.GQ, np, np, r.s);
     if (rc) return rc;
     rc = launch_traces(n, p.P, p.Q, p.GP, p.GQ, np, p.red, p.scal, r.s);
     if (!rc) rc = launch_fw_update(n, p.P, p.Q, p.GP, p.GQ, np, p.scal, p.fscal + 16, p.fscal, r.s);
@@ -162,7 +163,7 @@ int goat_run_begin(int n, const float* A, const float* B, int ld, const float* P
     GOAT_CHECK_ARG(n >= 1, "n < 1");
     GOAT_CHECK_ARG(A && B && ws, "null pointer");
     GOAT_CHECK_ARG(ld >= n, "leading dimension < n");
-    GOAT_CHECK_ARG(opt.prec >= GOAT_PREC_FP32 && opt.prec <= GOAT_PREC_BF16X3, "unknown precision");
+    GOAT_CHECK_ARG(opt.prec >= GOAT_PREC_FP32 && opt.prec <= GOAT_PREC_FP8, "unknown precision");
     GOAT_CHECK_ARG(std::isfinite(opt.eps_rel) && opt.eps_rel > 0.0f, "eps_rel must be > 0");
     GOAT_CHECK_ARG(std::isfinite(opt.sk_tol) && opt.sk_tol >= 0.0f, "bad sk_tol");
     GOAT_CHECK_ARG(opt.sk_max >= 1 && opt.fw_max >= 1, "sk_max and fw_max must be >= 1");
@@ -202,7 +203,10 @@ int goat_run_begin(int n, const float* A, const float* B, int ld, const float* P
     if (!rc) rc = P0 ? launch_copy_pad(n, P0, ld, p.P, np, np, r.s) : launch_fill_barycenter(n, np, p.P, r.s);
     if (rc) return fail(rc);
     r.ops = grad_ops(p);
-    if (opt.prec != GOAT_PREC_FP32) {
+    if (opt.prec == GOAT_PREC_FP8) {
+        rc = prep_fp8_operand(L, r.ops, p.P, np, r.s);
+        if (rc) return fail(rc);
+    } else if (opt.prec != GOAT_PREC_FP32) {
         rc = launch_split_bf16(n, np, p.P, np, static_cast<uint16_t*>(p.P_hi), static_cast<uint16_t*>(p.P_lo), r.s);
         if (rc) return fail(rc);
     } else {

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgoat.so")
 
 GOAT_OK, GOAT_EINVAL, GOAT_EHIP, GOAT_ENOMEM, GOAT_ENOTSUP = 0, -1, -2, -3, -4
-PREC = {"fp32": 0, "bf16x2": 1, "bf16x3": 2}
+PREC = {"fp32": 0, "bf16x2": 1, "bf16x3": 2, "fp8": 3}
 INIT_COLD, INIT_G = 0, 1
 
 

@@ -57,6 +57,27 @@ def test_gradient_sampled_entries_full_size(G, pair, prec):
     assert err <= 1e-4 and err_c <= 1e-4
 
 
+def test_gradient_fp8_sampled_entries_er5000(G):
+    """FP8 form on the 0/1 correlated ER pair at n = 5000 (p = 0.02,
+    rho = 0.7): sampled rows and columns of G against FP64."""
+    g = I.workload_er_5000()
+    n = g.A.shape[0]
+    P = I.uniform_matrix(n, 4343) / np.float32(n)
+    Gd = G.grad(torch.as_tensor(g.A, device="cuda"), torch.as_tensor(g.B, device="cuda"),
+                torch.as_tensor(P, device="cuda"), prec="fp8")
+    got = Gd.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(8)
+    rows = rng.choice(n, size=4, replace=False)
+    cols = rng.choice(n, size=6, replace=False)
+    Ad, Bd, Pd = g.A.astype(np.float64), g.B.astype(np.float64), P.astype(np.float64)
+    ref_rows = 2.0 * (Ad[rows] @ Pd) @ Bd
+    ref_cols = 2.0 * Ad @ (Pd @ Bd[:, cols])
+    err = np.max(np.abs(got[rows] - ref_rows)) / np.max(np.abs(ref_rows))
+    err_c = np.max(np.abs(got[:, cols] - ref_cols)) / np.max(np.abs(ref_cols))
+    print(f"grad n={n} fp8: sampled rows rel {err:.2e}, sampled cols rel {err_c:.2e}")
+    assert err <= 1e-4 and err_c <= 1e-4
+
+
 def test_sinkhorn_first_iteration_full_size(G):
     """After one iteration from g = 0: f_i = -eps LSE_j(G_ij/eps) and
     g_j = -eps LSE_i((G_ij + f_i)/eps), all n of each, in FP64."""

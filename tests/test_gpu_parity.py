@@ -48,6 +48,12 @@ def _pair(kind, n, seed):
         bp = np.full((k, k), 0.05); np.fill_diagonal(bp, 0.2)
         g = I.weighted_sbm_pair(sizes, bp, 0.1, seed)
         return g.A, g.B
+    if kind == "dir01":       # directed 0/1 pair (general, exact in bf16 and FP8)
+        A = (I.random_matrix(n, n, seed, 0, 1) > 0.9).astype(np.float32)
+        B = (I.random_matrix(n, n, seed + 1, 0, 1) > 0.9).astype(np.float32)
+        np.fill_diagonal(A, 0.0)
+        np.fill_diagonal(B, 0.0)
+        return A, B
     A = I.random_matrix(n, n, seed, -1, 1)
     B = I.random_matrix(n, n, seed + 1, -1, 1)
     return A, B
@@ -56,6 +62,7 @@ def _pair(kind, n, seed):
 GRAD_CASES = [
     ("fp32", True, "er"), ("fp32", True, "wsbm"), ("fp32", False, "gen"),
     ("bf16x2", True, "er"), ("bf16x3", True, "wsbm"), ("bf16x3", False, "gen"),
+    ("fp8", True, "er"), ("fp8", False, "dir01"),
 ]
 
 
@@ -89,6 +96,8 @@ def test_grad_barycenter_and_permutation(G):
     got = host(G.grad(A, B, dev(Pi), prec="bf16x2"))
     ref = O.gradient(g.A.astype(float), g.B.astype(float), Pi)
     assert np.max(np.abs(got - ref)) == 0.0       # integer-valued: exact in bf16 with fp32 accumulation
+    got = host(G.grad(A, B, dev(Pi), prec="fp8"))
+    assert np.max(np.abs(got - ref)) == 0.0       # and in E4M3 (one term carries every 0/1 entry)
 
 
 def _sk_problem(n, seed):
@@ -194,7 +203,7 @@ def test_bitwise_deterministic(G):
     assert np.array_equal(host(q1.Q), host(q2.Q))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2", "fp8"])
 def test_solve_parity_er64(G, prec):
     g = I.workload_er_small()
     print(f"solve n=64 prec={prec}", flush=True)
