@@ -324,3 +324,155 @@ def goat_restarts(A, B, inits, opt: GoatOptions | None = None) -> GoatResult:
 def match_ratio(perm, truth) -> float:
     """Fraction of nodes aligned as planted (Results section)."""
     return float(np.mean(np.asarray(perm) == np.asarray(truth)))
+
+
+# ---------------------------------------------------------------- seeds, unequal sizes
+
+# READING (seeded / unequal-size GOAT): the paper applies Fishkind et al.'s
+# modification of FAQ without printing it. Restated here from that method:
+# seeded vertices come first in both graphs (seed i of A is matched to seed
+# i of B), the other vertices follow in increasing order, and the smaller
+# graph is padded with isolated dummy vertices ("naive" padding) or, for 0/1
+# graphs, both graphs are first recentred to 2X - J ("adopted" padding, so
+# that an edge to a dummy vertex is neither rewarded nor penalised). With
+# blocks X11 (seeds), X12, X21, X22 and a doubly stochastic P on the
+# non-seed block, Pi = diag(I, P) gives
+#     tr(A^T Pi B Pi^T) = tr(A11^T B11) + <C, P> + tr(A22^T P B22 P^T),
+#     C = A21 B21^T + A12^T B12,
+# so the gradient is C + A22 P B22^T + A22^T P B22 and the exact step gains
+# the linear term's share below.
+
+@dataclass
+class SeededProblem:
+    A: np.ndarray          # n x n, seeds first, padded
+    B: np.ndarray
+    m: int                 # number of seeds
+    order_A: np.ndarray    # position -> original A vertex (-1: dummy)
+    order_B: np.ndarray
+
+
+def seeded_problem(A, B, seeds_A=(), seeds_B=(), pad: str = "naive") -> SeededProblem:
+    A = np.asarray(A, np.float64); B = np.asarray(B, np.float64)
+    seeds_A = [int(v) for v in seeds_A]; seeds_B = [int(v) for v in seeds_B]
+    if len(seeds_A) != len(seeds_B) or len(set(seeds_A)) != len(seeds_A) or len(set(seeds_B)) != len(seeds_B):
+        raise ValueError("seeds must be two equally long lists of distinct vertices")
+    if pad == "adopted":
+        A = 2.0 * A - 1.0
+        B = 2.0 * B - 1.0
+    elif pad != "naive":
+        raise ValueError("pad must be 'naive' or 'adopted'")
+    nA, nB = A.shape[0], B.shape[0]
+    n = max(nA, nB)
+
+    def order(nx, seeds):
+        sset = set(seeds)
+        rest = [v for v in range(nx) if v not in sset]
+        return np.array(seeds + rest + [-1] * (n - nx), dtype=np.int64)
+
+    oA, oB = order(nA, seeds_A), order(nB, seeds_B)
+
+    def arrange(X, o):
+        Y = np.zeros((n, n))
+        real = np.nonzero(o >= 0)[0]
+        Y[np.ix_(real, real)] = X[np.ix_(o[real], o[real])]
+        return Y
+
+    return SeededProblem(arrange(A, oA), arrange(B, oB), len(seeds_A), oA, oB)
+
+
+def seeded_linear_term(sp: SeededProblem) -> np.ndarray:
+    m = sp.m
+    A, B = sp.A, sp.B
+    return A[m:, :m] @ B[m:, :m].T + A[:m, m:].T @ B[:m, m:]
+
+
+def seeded_gradient(sp: SeededProblem, P) -> np.ndarray:
+    m = sp.m
+    A22, B22 = sp.A[m:, m:], sp.B[m:, m:]
+    return seeded_linear_term(sp) + A22 @ P @ B22.T + A22.T @ P @ B22
+
+
+def seeded_objective(sp: SeededProblem, P) -> float:
+    """<C, P> + tr(A22^T P B22 P^T) (the seeded objective without its
+    constant tr(A11^T B11))."""
+    m = sp.m
+    return float(np.sum(seeded_linear_term(sp) * P)) + relaxed_objective(sp.A[m:, m:], sp.B[m:, m:], P)
+
+
+def seeded_linesearch(P, Q, GP, GQ, C) -> LineSearch:
+    """Exact step for f(X) = <C, X> + q(X), q quadratic with gradient
+    grad q(X) = G_X - C. With D = Q - P:
+        f(P + tD) = f(P) + t <D, G_P> + t^2 q(D),
+        q(D) = q(Q) - <Q, grad q(P)> + q(P)
+             = <Q,G_Q>/2 - <Q,G_P> + <P,G_P>/2 + <Q - P, C>/2.
+    fP and fQ are f(P) and f(Q) themselves."""
+    P = np.asarray(P, np.float64); Q = np.asarray(Q, np.float64)
+    qp, qq = float(np.sum(Q * GP)), float(np.sum(P * GP))
+    a = 0.5 * float(np.sum(Q * GQ)) - qp + 0.5 * qq + 0.5 * float(np.sum((Q - P) * C))
+    b = qp - qq
+    if a < 0.0:
+        t = min(max(-b / (2.0 * a), 0.0), 1.0)
+    else:
+        t = 1.0 if a + b > 0.0 else 0.0
+    fP = 0.5 * qq + 0.5 * float(np.sum(P * C))
+    fQ = 0.5 * float(np.sum(Q * GQ)) + 0.5 * float(np.sum(Q * C))
+    return LineSearch(fP, fQ, qp, a, b, t, float(np.sum((Q - P) ** 2)))
+
+
+@dataclass
+class SeededResult:
+    perm: np.ndarray       # A vertex -> B vertex, -1 if matched to a dummy
+    score: float           # tr(A'^T Pi B'^T Pi^T) on the arranged (padded) graphs
+    P: np.ndarray          # final P on the non-seed block
+    fw_iters: int
+    history: list = field(default_factory=list)
+
+
+def goat_seeded(A, B, seeds_A=(), seeds_B=(), P0=None, opt: GoatOptions | None = None,
+                pad: str = "naive", record: bool = False) -> SeededResult:
+    """GOAT on the non-seed block of the seeded (and padded) problem: the
+    loop of Alg. 3 with the seeded gradient and step; the final assignment
+    maps the non-seed block, seeds map to each other."""
+    opt = opt or GoatOptions()
+    sp = seeded_problem(A, B, seeds_A, seeds_B, pad)
+    n, m = sp.A.shape[0], sp.m
+    k = n - m
+    C = seeded_linear_term(sp)
+    if k == 0:
+        P = np.zeros((0, 0))
+    else:
+        P = barycenter(k) if P0 is None else np.asarray(P0, np.float64).copy()
+    hist = []
+    it = 0
+    if k > 0:
+        for it in range(1, opt.fw_max + 1):
+            G = seeded_gradient(sp, P)
+            gmax = float(np.max(np.abs(G)))
+            eps = opt.eps_rel * gmax
+            if eps == 0.0:
+                Q = barycenter(k); sk_it = 0; sk_err = 0.0
+            else:
+                sk = log_sinkhorn_max(G, eps, opt.sk_tol, opt.sk_max)
+                Q, sk_it, sk_err = sk.Q, sk.iters, sk.err
+            GQ = seeded_gradient(sp, Q)
+            ls = seeded_linesearch(P, Q, G, GQ, C)
+            P = P + ls.t * (Q - P)
+            delta = ls.t * math.sqrt(ls.dist2) / math.sqrt(k)
+            if record:
+                hist.append(dict(it=it, eps=eps, sk_iters=sk_it, sk_err=sk_err, t=ls.t, a=ls.a, b=ls.b,
+                                 fP=ls.fP, fQ=ls.fQ, c=ls.c))
+            if ls.t == 0.0 or (opt.fw_tol > 0.0 and delta < opt.fw_tol):
+                break
+        M = P if opt.proj == "P" else seeded_gradient(sp, P)
+        inner = hungarian_max(M)
+    else:
+        inner = np.zeros(0, dtype=np.int64)
+    pos = np.concatenate([np.arange(m), m + inner]).astype(np.int64)
+    nA = int(np.sum(sp.order_A >= 0))
+    perm = np.full(nA, -1, dtype=np.int64)
+    for i in range(n):
+        a = sp.order_A[i]
+        if a >= 0:
+            perm[a] = sp.order_B[pos[i]]
+    score = float(np.sum(sp.A * sp.B[np.ix_(pos, pos)]))
+    return SeededResult(perm, score, P, it, hist)
