@@ -288,6 +288,39 @@ int goat_score(int n, const float* A, const float* B, int ld,
                void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Seeds and graphs of different sizes
+ * ---------------------------------------------------------------------- */
+
+/*
+ * goat_solve_seeded - GOAT with seeds and unequal sizes: Fishkind et al.'s
+ * modification of FAQ (cited by the paper for seeded graph matching and
+ * applied there to GOAT) on Alg. 3. Seed i of A is matched to seed i of B;
+ * the remaining vertices follow in increasing order; the smaller graph is
+ * padded with isolated dummy vertices to n = max(nA, nB), after recentring
+ * both graphs to 2X - J when pad = 1 ("adopted" padding, for 0/1 graphs;
+ * pad = 0: "naive"). With Pi = diag(I_m, P) the objective is
+ * tr(A11^T B11) + <C, P> + tr(A22^T P B22 P^T), C = A21 B21^T + A12^T B12, so
+ * Alg. 3 runs on the non-seed block with C added to every gradient (C on the
+ * fp32 matrix cores) and the exact step extended by the linear term.
+ *  A: nA x nA (lda), B: nB x nB (ldb), device.
+ *  seeds_A, seeds_B: host int32[m], distinct vertices of A and of B.
+ *  perm_host: host int32[nA]: the B vertex matched to each A vertex, -1 when
+ *           it is matched to a dummy (nA > nB).
+ *  stats_host: as goat_solve for the non-seed block (f_final excludes the
+ *           constant tr(A11^T B11)); score = tr(A'^T Pi B' Pi^T) of the
+ *           arranged (recentred, padded) graphs. hist_host: as goat_solve.
+ *  ws: goat_seeded_workspace_size(nA, nB, m, opt->prec, opt->symmetric) bytes.
+ * Status: GOAT_EINVAL for bad sizes, seeds (repeated or out of range), pad
+ * or options; GOAT_ENOMEM; GOAT_EHIP. Host-synchronous, like goat_solve.
+ */
+size_t goat_seeded_workspace_size(int nA, int nB, int m, int prec, int symmetric);
+int goat_solve_seeded(int nA, const float* A, int lda, int nB, const float* B, int ldb, int m,
+                      const int32_t* seeds_A, const int32_t* seeds_B, int pad,
+                      const goat_options* opt, int32_t* perm_host, goat_stats* stats_host,
+                      goat_iter_record* hist_host, int hist_cap,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Random starts (GOAT section, random initialisations)
  * ---------------------------------------------------------------------- */
 

@@ -32,7 +32,7 @@ Layout make_layout(int n, int prec, int sym) {
     L.pot = take(np * 4 * 6);
     L.errpart = take(kSkWG * 4);
     L.colpart = take((size_t)kSkWG * np * 4);
-    L.red = take((size_t)kRedWG * 4 * 8);
+    L.red = take((size_t)kRedWG * kTraceSlots * 8);
     L.scal = take(64 * 8 + np * 4 * 2);   // scalars, then g_prev[np], perm_dev[np]
     L.fscal = take((16 + kRedWG) * 4);
     L.mlp = take(np * 5 * 4);

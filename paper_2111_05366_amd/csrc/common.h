@@ -206,8 +206,17 @@ int sk_finalize(int n, int np, const float* G, int ldg, SkState st,
 
 // Elementwise / reductions (fw.hip)
 int launch_absmax(int n, const float* G, int ldg, float* partial, float* out, hipStream_t s);
+// Float64 partials per block of the trace pass (kRedWG blocks at most).
+constexpr int kTraceSlots = 6;
 int launch_traces(int n, const float* P, const float* Q, const float* GP, const float* GQ,
-                  int ld, double* red, double* out8, hipStream_t s);
+                  int ld, double* red, double* out8, hipStream_t s, const float* C = nullptr);
+// Seeded problems (fw.hip): arrangement of a graph by a vertex order (o < 0:
+// dummy), rectangular zero-padded packing, and G += C.
+int launch_arrange(int n, const float* X, int ldx, const int* order_dev, int adopted, float* Y, int ldy,
+                   hipStream_t s);
+int launch_pack_rect(const float* src, int ld, int rows, int cols, int transpose, float* dst, int ldd, int prows,
+                     int pcols, hipStream_t s);
+int launch_add_mat(int n, float* G, const float* C, int ld, hipStream_t s);
 int launch_fw_update(int n, float* P, const float* Q, float* GP, const float* GQ, int ld,
                      const double* ls8, float* absmax_partial, float* absmax_out,
                      hipStream_t s);

@@ -65,13 +65,16 @@ __global__ __launch_bounds__(RT) void max_final_kernel(int nb, const float* part
 
 // ------------------------------------------------------------------ traces
 
+// Partial traces per block: <P,GP>, <Q,GQ>, <Q,GP>, ||Q-P||^2 and, with a
+// linear term C (seeded problems), <P,C> and <Q,C>.
 __global__ __launch_bounds__(RT) void traces_partial_kernel(int n, const float* __restrict__ P,
                                                             const float* __restrict__ Q,
                                                             const float* __restrict__ GP,
-                                                            const float* __restrict__ GQ, int ld,
+                                                            const float* __restrict__ GQ,
+                                                            const float* __restrict__ C, int ld,
                                                             double* partial) {
     __shared__ double sh[4];
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0, s5 = 0.0;
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const size_t o = (size_t)i * ld;
         for (int j = threadIdx.x; j < n; j += RT) {
@@ -81,31 +84,41 @@ __global__ __launch_bounds__(RT) void traces_partial_kernel(int n, const float* 
             s2 += q * gp;
             const double d = q - p;
             s3 += d * d;
+            if (C) {
+                const double c = C[o + j];
+                s4 += p * c;
+                s5 += q * c;
+            }
         }
     }
     s0 = block_sum_d(s0, sh);
     s1 = block_sum_d(s1, sh);
     s2 = block_sum_d(s2, sh);
     s3 = block_sum_d(s3, sh);
+    s4 = block_sum_d(s4, sh);
+    s5 = block_sum_d(s5, sh);
     if (threadIdx.x == 0) {
-        double* o = partial + 4 * (size_t)blockIdx.x;
-        o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3;
+        double* o = partial + kTraceSlots * (size_t)blockIdx.x;
+        o[0] = s0; o[1] = s1; o[2] = s2; o[3] = s3; o[4] = s4; o[5] = s5;
     }
 }
 
 // Exact step: with fP = <P,GP>/2, fQ = <Q,GQ>/2, c = <Q,GP>,
 // f(P + t(Q-P)) = fP + b t + a t^2, a = fP + fQ - c, b = c - 2 fP.
+// With a linear term C (f(X) = <C,X> + q(X), q quadratic) the curvature
+// gains <Q - P, C>/2, and f(P) = fP + <P,C>/2, f(Q) = fQ + <Q,C>/2 are
+// reported.
 __global__ __launch_bounds__(RT) void linesearch_final_kernel(int nb, const double* partial, double* out8) {
     __shared__ double sh[4];
-    double s[4];
-    for (int k = 0; k < 4; ++k) {
+    double s[kTraceSlots];
+    for (int k = 0; k < kTraceSlots; ++k) {
         double x = 0.0;
-        for (int b = threadIdx.x; b < nb; b += RT) x += partial[4 * (size_t)b + k];
+        for (int b = threadIdx.x; b < nb; b += RT) x += partial[kTraceSlots * (size_t)b + k];
         s[k] = block_sum_d(x, sh);
     }
     if (threadIdx.x == 0) {
         const double fP = 0.5 * s[0], fQ = 0.5 * s[1], c = s[2];
-        const double a = fP + fQ - c, b = c - 2.0 * fP;
+        const double a = fP + fQ - c + 0.5 * (s[5] - s[4]), b = c - 2.0 * fP;
         double t;
         if (a < 0.0) {
             t = -b / (2.0 * a);
@@ -113,7 +126,7 @@ __global__ __launch_bounds__(RT) void linesearch_final_kernel(int nb, const doub
         } else {
             t = (a + b > 0.0) ? 1.0 : 0.0;
         }
-        out8[0] = fP; out8[1] = fQ; out8[2] = c; out8[3] = a;
+        out8[0] = fP + 0.5 * s[4]; out8[1] = fQ + 0.5 * s[5]; out8[2] = c; out8[3] = a;
         out8[4] = b;  out8[5] = t;  out8[6] = s[3]; out8[7] = 0.0;
     }
 }
@@ -195,6 +208,41 @@ __global__ __launch_bounds__(RT) void sum_final_kernel(int nb, const double* par
     if (threadIdx.x == 0) *out = x;
 }
 
+// Seeded problems: Y[i][j] = X'[o[i]][o[j]] with X' = X (naive) or 2X - 1
+// (adopted); rows and columns with o < 0 (dummy vertices) are zero.
+__global__ __launch_bounds__(RT) void arrange_kernel(int n, const float* __restrict__ X, int ldx,
+                                                     const int* __restrict__ order, int adopted, float* Y,
+                                                     int ldy) {
+    const int i = blockIdx.x;
+    const int oi = order[i];
+    for (int j = threadIdx.x; j < n; j += RT) {
+        const int oj = order[j];
+        float v = 0.0f;
+        if (oi >= 0 && oj >= 0) {
+            v = X[(size_t)oi * ldx + oj];
+            if (adopted) v = 2.0f * v - 1.0f;
+        }
+        Y[(size_t)i * ldy + j] = v;
+    }
+}
+
+// dst (prows x pcols, ldd) = the rows x cols block of src (or its
+// transpose), zero elsewhere.
+__global__ __launch_bounds__(RT) void pack_rect_kernel(const float* __restrict__ src, int ld, int rows, int cols,
+                                                       int transpose, float* dst, int ldd, int pcols) {
+    const int i = blockIdx.x;
+    for (int j = threadIdx.x; j < pcols; j += RT) {
+        float v = 0.0f;
+        if (i < rows && j < cols) v = transpose ? src[(size_t)j * ld + i] : src[(size_t)i * ld + j];
+        dst[(size_t)i * ldd + j] = v;
+    }
+}
+
+__global__ __launch_bounds__(RT) void add_mat_kernel(int n, float* G, const float* __restrict__ C, int ld) {
+    const int i = blockIdx.x;
+    for (int j = threadIdx.x; j < n; j += RT) G[(size_t)i * ld + j] += C[(size_t)i * ld + j];
+}
+
 }  // namespace
 
 int launch_absmax(int n, const float* G, int ldg, float* partial, float* out, hipStream_t s) {
@@ -206,9 +254,9 @@ int launch_absmax(int n, const float* G, int ldg, float* partial, float* out, hi
 }
 
 int launch_traces(int n, const float* P, const float* Q, const float* GP, const float* GQ, int ld,
-                  double* red, double* out8, hipStream_t s) {
+                  double* red, double* out8, hipStream_t s, const float* C) {
     const int nb = nblocks_rows(n);
-    hipLaunchKernelGGL(traces_partial_kernel, dim3(nb), dim3(RT), 0, s, n, P, Q, GP, GQ, ld, red);
+    hipLaunchKernelGGL(traces_partial_kernel, dim3(nb), dim3(RT), 0, s, n, P, Q, GP, GQ, C, ld, red);
     hipLaunchKernelGGL(linesearch_final_kernel, dim3(1), dim3(RT), 0, s, nb, (const double*)red, out8);
     GOAT_HIP(hipGetLastError());
     return GOAT_OK;
@@ -247,6 +295,34 @@ int launch_score(int n, const float* A, const float* B, int ld, const int32_t* p
     const int nb = nblocks_rows(n);
     hipLaunchKernelGGL(score_partial_kernel, dim3(nb), dim3(RT), 0, s, n, A, B, ld, perm, red);
     hipLaunchKernelGGL(sum_final_kernel, dim3(1), dim3(RT), 0, s, nb, (const double*)red, out);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+}  // namespace goat
+
+namespace goat {
+
+int launch_arrange(int n, const float* X, int ldx, const int* order_dev, int adopted, float* Y, int ldy,
+                   hipStream_t s) {
+    if (n < 1) return GOAT_OK;
+    hipLaunchKernelGGL(arrange_kernel, dim3(n), dim3(RT), 0, s, n, X, ldx, order_dev, adopted, Y, ldy);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+int launch_pack_rect(const float* src, int ld, int rows, int cols, int transpose, float* dst, int ldd, int prows,
+                     int pcols, hipStream_t s) {
+    if (prows < 1) return GOAT_OK;
+    hipLaunchKernelGGL(pack_rect_kernel, dim3(prows), dim3(RT), 0, s, src, ld, rows, cols, transpose, dst, ldd,
+                       pcols);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+int launch_add_mat(int n, float* G, const float* C, int ld, hipStream_t s) {
+    if (n < 1) return GOAT_OK;
+    hipLaunchKernelGGL(add_mat_kernel, dim3(n), dim3(RT), 0, s, n, G, C, ld);
     GOAT_HIP(hipGetLastError());
     return GOAT_OK;
 }

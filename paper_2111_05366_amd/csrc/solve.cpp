@@ -11,6 +11,7 @@
 //   4. float64 traces -> exact step t (Alg. 3 step 3)
 //   5. P <- P + t(Q - P), G_P <- G_P + t(G_Q - G_P), next max|G_P|
 // The only host synchronisation per iteration reads back the step scalars.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -29,6 +30,7 @@ struct Run {
     const float* A = nullptr;
     const float* B = nullptr;
     int ld = 0;
+    const float* lin = nullptr;  // seeded problems: linear term C (np x np), added to every gradient
     int fw = 0;                 // iterations done
     bool stalled = false;
     double last_ls[8] = {0};
@@ -114,8 +116,9 @@ static int run_step(Run& r, goat_iter_record* rec) {
     if (r.opt.prec == GOAT_PREC_FP32) r.ops.P_hi = p.Q;
     if (r.opt.prec == GOAT_PREC_FP8) rc = prep_fp8_operand(r.L, r.ops, p.Q, np, r.s);
     if (!rc) rc = grad_packed(r.L, r.ops, p.GQ, np, np, r.s);
+    if (!rc && r.lin) rc = launch_add_mat(n, p.GQ, r.lin, np, r.s);
     if (rc) return rc;
-    rc = launch_traces(n, p.P, p.Q, p.GP, p.GQ, np, p.red, p.scal, r.s);
+    rc = launch_traces(n, p.P, p.Q, p.GP, p.GQ, np, p.red, p.scal, r.s, r.lin);
     if (!rc) rc = launch_fw_update(n, p.P, p.Q, p.GP, p.GQ, np, p.scal, p.fscal + 16, p.fscal, r.s);
     if (rc) return rc;
     GOAT_HIP(hipMemcpyAsync(r.hbuf, p.scal, 80, hipMemcpyDeviceToHost, r.s));
@@ -153,8 +156,21 @@ struct goat_run {
 
 extern "C" {
 
+static int run_begin_impl(int n, const float* A, const float* B, int ld, const float* P0,
+                          const goat_options* opt_in, void* ws, size_t ws_bytes, void* stream, const float* lin,
+                          goat_run** run_out);
+
 int goat_run_begin(int n, const float* A, const float* B, int ld, const float* P0, const goat_options* opt_in,
                    void* ws, size_t ws_bytes, void* stream, goat_run** run_out) {
+    return run_begin_impl(n, A, B, ld, P0, opt_in, ws, ws_bytes, stream, nullptr, run_out);
+}
+
+}  // extern "C"
+
+// lin: optional linear term (np x np, zero padded) of a seeded problem
+static int run_begin_impl(int n, const float* A, const float* B, int ld, const float* P0,
+                          const goat_options* opt_in, void* ws, size_t ws_bytes, void* stream, const float* lin,
+                          goat_run** run_out) {
     clear_error();
     GOAT_CHECK_ARG(run_out, "null run pointer");
     *run_out = nullptr;
@@ -184,6 +200,7 @@ int goat_run_begin(int n, const float* A, const float* B, int ld, const float* P
     r.A = A;
     r.B = B;
     r.ld = ld;
+    r.lin = lin;
     auto fail = [&](int rc) { delete h; return rc; };
 #define RUN_HIP(call)                                                                    \
     do {                                                                                 \
@@ -213,6 +230,7 @@ int goat_run_begin(int n, const float* A, const float* B, int ld, const float* P
         r.ops.P_hi = p.P;
     }
     rc = grad_packed(L, r.ops, p.GP, np, np, r.s);
+    if (!rc && lin) rc = launch_add_mat(n, p.GP, lin, np, r.s);
     if (!rc) rc = launch_absmax(n, p.GP, np, p.fscal + 16, p.fscal, r.s);
     if (rc) return fail(rc);
     RUN_HIP(hipStreamSynchronize(r.s));
@@ -220,6 +238,8 @@ int goat_run_begin(int n, const float* A, const float* B, int ld, const float* P
     *run_out = h;
     return GOAT_OK;
 }
+
+extern "C" {
 
 int goat_run_steps(goat_run* h, int k, goat_iter_record* hist_host, int hist_cap, int* done_out) {
     clear_error();
@@ -298,6 +318,151 @@ int goat_run_gradient(goat_run* h, float* G_out, int ldg) {
 }
 
 void goat_run_free(goat_run* h) { delete h; }
+
+// ---------------------------------------------------------------- seeded, unequal sizes
+
+// Workspace of a seeded problem: the inner (non-seed) solver's layout, then
+// the arranged graphs (n x n), the linear term C (kp x kp), the four packed
+// seed blocks (kp x mp), the vertex orders and the full assignment.
+struct SeededPlan {
+    int n, m, k, kp, mp;
+    size_t inner, arrA, arrB, lin, x1, z1, x2, z2, ordA, ordB, pos, total;
+};
+
+static SeededPlan seeded_plan(int nA, int nB, int m, int prec, int symmetric) {
+    SeededPlan sp{};
+    sp.n = std::max(nA, nB);
+    sp.m = m;
+    sp.k = sp.n - m;
+    const int kk = std::max(sp.k, 1);
+    sp.kp = pad_n(kk);
+    sp.mp = std::max(16, (m + 15) / 16 * 16);
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    size_t o = al(make_layout(kk, prec, symmetric).total);
+    sp.inner = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o = al(o + bytes); return at; };
+    const size_t nn = (size_t)sp.n * sp.n * 4;
+    sp.arrA = take(nn);
+    sp.arrB = take(nn);
+    sp.lin = take((size_t)sp.kp * sp.kp * 4);
+    const size_t rect = (size_t)sp.kp * sp.mp * 4;
+    sp.x1 = take(rect);
+    sp.z1 = take(rect);
+    sp.x2 = take(rect);
+    sp.z2 = take(rect);
+    sp.ordA = take((size_t)sp.n * 4);
+    sp.ordB = take((size_t)sp.n * 4);
+    sp.pos = take((size_t)sp.n * 4);
+    sp.total = o;
+    return sp;
+}
+
+size_t goat_seeded_workspace_size(int nA, int nB, int m, int prec, int symmetric) {
+    if (nA < 1 || nB < 1 || m < 0 || m > std::min(nA, nB) || prec < GOAT_PREC_FP32 || prec > GOAT_PREC_FP8)
+        return 0;
+    return seeded_plan(nA, nB, m, prec, symmetric).total;
+}
+
+int goat_solve_seeded(int nA, const float* A, int lda, int nB, const float* B, int ldb, int m,
+                      const int32_t* seeds_A, const int32_t* seeds_B, int pad, const goat_options* opt,
+                      int32_t* perm_host, goat_stats* stats_host, goat_iter_record* hist_host, int hist_cap,
+                      void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(nA >= 1 && nB >= 1, "graph size < 1");
+    GOAT_CHECK_ARG(A && B && ws && perm_host, "null pointer");
+    GOAT_CHECK_ARG(lda >= nA && ldb >= nB, "leading dimension < n");
+    GOAT_CHECK_ARG(m >= 0 && m <= std::min(nA, nB) && (m == 0 || (seeds_A && seeds_B)), "bad seed count");
+    GOAT_CHECK_ARG(pad == 0 || pad == 1, "pad must be 0 (naive) or 1 (adopted)");
+    GOAT_CHECK_ARG(hist_cap >= 0 && (hist_cap == 0 || hist_host), "bad history buffer");
+    goat_options o;
+    if (opt) o = *opt; else goat_default_options(&o);
+    const SeededPlan sp = seeded_plan(nA, nB, m, o.prec, o.symmetric);
+    if (ws_bytes < sp.total) { set_error("goat_solve_seeded: workspace too small"); return GOAT_ENOMEM; }
+    // vertex orders: seeds, then the other vertices ascending, then dummies
+    const int n = sp.n, k = sp.k;
+    std::vector<int> ordA, ordB;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int nx = pass ? nB : nA;
+        const int32_t* seeds = pass ? seeds_B : seeds_A;
+        std::vector<char> used(nx, 0);
+        std::vector<int>& ord = pass ? ordB : ordA;
+        for (int i = 0; i < m; ++i) {
+            const int v = seeds[i];
+            if (v < 0 || v >= nx || used[v]) {
+                set_error("goat_solve_seeded: seeds must be distinct vertices of their graph");
+                return GOAT_EINVAL;
+            }
+            used[v] = 1;
+            ord.push_back(v);
+        }
+        for (int v = 0; v < nx; ++v)
+            if (!used[v]) ord.push_back(v);
+        while ((int)ord.size() < n) ord.push_back(-1);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* b = static_cast<char*>(ws);
+    float* arrA = reinterpret_cast<float*>(b + sp.arrA);
+    float* arrB = reinterpret_cast<float*>(b + sp.arrB);
+    float* lin = reinterpret_cast<float*>(b + sp.lin);
+    int* dA = reinterpret_cast<int*>(b + sp.ordA);
+    int* dB = reinterpret_cast<int*>(b + sp.ordB);
+    GOAT_HIP(hipMemcpyAsync(dA, ordA.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    GOAT_HIP(hipMemcpyAsync(dB, ordB.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    int rc = launch_arrange(n, A, lda, dA, pad, arrA, n, s);
+    if (!rc) rc = launch_arrange(n, B, ldb, dB, pad, arrB, n, s);
+    if (rc) return rc;
+    std::vector<int> pos(n);
+    for (int i = 0; i < m; ++i) pos[i] = i;
+    goat_stats st{};
+    if (k > 0) {
+        // C = A21 B21^T + A12^T B12 on the fp32 matrix cores (zero without seeds)
+        GOAT_HIP(hipMemsetAsync(lin, 0, (size_t)sp.kp * sp.kp * 4, s));
+        if (m > 0) {
+            float* x1 = reinterpret_cast<float*>(b + sp.x1);
+            float* z1 = reinterpret_cast<float*>(b + sp.z1);
+            float* x2 = reinterpret_cast<float*>(b + sp.x2);
+            float* z2 = reinterpret_cast<float*>(b + sp.z2);
+            rc = launch_pack_rect(arrA + (size_t)m * n, n, k, m, 0, x1, sp.mp, sp.kp, sp.mp, s);   // A21
+            if (!rc) rc = launch_pack_rect(arrB + (size_t)m * n, n, k, m, 0, z1, sp.mp, sp.kp, sp.mp, s);   // B21
+            if (!rc) rc = launch_pack_rect(arrA + m, n, k, m, 1, x2, sp.mp, sp.kp, sp.mp, s);   // A12^T
+            if (!rc) rc = launch_pack_rect(arrB + m, n, k, m, 1, z2, sp.mp, sp.kp, sp.mp, s);   // B12^T
+            if (rc) return rc;
+            GemmSegs sg{};
+            sg.X[0] = x1; sg.Z[0] = z1;
+            sg.X[1] = x2; sg.Z[1] = z2;
+            sg.nseg = 2;
+            rc = launch_gemm_nt(GEMM_F32, sp.kp, sp.kp, sp.mp, sp.mp, sp.mp, sg, 1.0f, OUT_F32, lin, sp.kp, k, k,
+                                nullptr, nullptr, 0, s);
+            if (rc) return rc;
+        }
+        // GOAT on the non-seed block, with C added to every gradient
+        goat_run* h = nullptr;
+        rc = run_begin_impl(k, arrA + (size_t)m * n + m, arrB + (size_t)m * n + m, n, nullptr, &o, ws,
+                            sp.arrA, stream, lin, &h);
+        if (rc) return rc;
+        rc = goat_run_steps(h, o.fw_max, hist_host, hist_cap, nullptr);
+        std::vector<int32_t> inner(k);
+        if (!rc) rc = goat_run_finish(h, inner.data(), &st, nullptr, 0);
+        goat_run_free(h);
+        if (rc) return rc;
+        for (int i = 0; i < k; ++i) pos[m + i] = m + inner[i];
+    }
+    // full assignment in original labels, and its score on the arranged graphs
+    for (int i = 0; i < nA; ++i) perm_host[i] = -1;
+    for (int i = 0; i < n; ++i)
+        if (ordA[i] >= 0) perm_host[ordA[i]] = ordB[pos[i]];
+    int* dpos = reinterpret_cast<int*>(b + sp.pos);
+    GOAT_HIP(hipMemcpyAsync(dpos, pos.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    Ptrs p = make_ptrs(make_layout(std::max(k, 1), o.prec, o.symmetric), ws);
+    rc = launch_score(n, arrA, arrB, n, dpos, p.red, p.scal + 10, s);
+    if (rc) return rc;
+    double score = 0.0;
+    GOAT_HIP(hipMemcpyAsync(&score, p.scal + 10, 8, hipMemcpyDeviceToHost, s));
+    GOAT_HIP(hipStreamSynchronize(s));
+    st.score = score;
+    if (stats_host) *stats_host = st;
+    return GOAT_OK;
+}
 
 int goat_solve(int n, const float* A, const float* B, int ld, const float* P0, const goat_options* opt,
                int32_t* perm_host, goat_stats* stats_host, goat_iter_record* hist_host, int hist_cap,

@@ -119,6 +119,11 @@ def lib():
     L.goat_profile_enable.argtypes = [_I, _I]
     L.goat_profile_read.restype = _I
     L.goat_profile_read.argtypes = [_I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+    L.goat_seeded_workspace_size.restype = _SZ
+    L.goat_seeded_workspace_size.argtypes = [_I, _I, _I, _I, _I]
+    L.goat_solve_seeded.restype = _I
+    L.goat_solve_seeded.argtypes = [_I, _VP, _I, _I, _VP, _I, _I, _VP, _VP, _I, ctypes.POINTER(Options), _VP,
+                                    ctypes.POINTER(Stats), ctypes.POINTER(IterRecord), _I, _VP, _SZ, _VP]
     L.goat_random_init.restype = _I
     L.goat_random_init.argtypes = [_I, _VP, _I, _VP, _I, _F, _I, _VP, _VP, _VP]
     L.goat_batch_workspace_size.restype = _I
@@ -580,3 +585,32 @@ def tune_get(n: int):
     w = ctypes.c_int(0)
     _check(lib().goat_tune_get(int(n), ctypes.byref(L), ctypes.byref(w)))
     return L.value, w.value
+
+
+def solve_seeded(A, B, seeds_A=(), seeds_B=(), pad: str = "naive", **opts) -> SolveResult:
+    """Seeded / unequal-size GOAT (goat_solve_seeded). perm[i] is the B
+    vertex matched to A vertex i, -1 for a dummy."""
+    torch = _torch()
+    _mat(A, "A"); _mat(B, "B")
+    nA, nB = A.shape[0], B.shape[0]
+    sA = np.ascontiguousarray(np.asarray(seeds_A, dtype=np.int32))
+    sB = np.ascontiguousarray(np.asarray(seeds_B, dtype=np.int32))
+    if sA.shape != sB.shape:
+        raise ValueError("seeds_A and seeds_B must have the same length")
+    m = int(sA.shape[0])
+    o = default_options(**opts)
+    need = int(lib().goat_seeded_workspace_size(nA, nB, m, o.prec, o.symmetric))
+    if need == 0:
+        raise ValueError("bad sizes, seed count or precision")
+    ws = torch.empty(need, dtype=torch.uint8, device=A.device)
+    perm = np.empty(nA, dtype=np.int32)
+    st = Stats()
+    cap = max(o.fw_max, 1)
+    hist = (IterRecord * cap)()
+    _check(lib().goat_solve_seeded(nA, _ptr(A), A.stride(0), nB, _ptr(B), B.stride(0), m,
+                                   sA.ctypes.data_as(ctypes.c_void_p) if m else None,
+                                   sB.ctypes.data_as(ctypes.c_void_p) if m else None,
+                                   {"naive": 0, "adopted": 1}[pad], ctypes.byref(o),
+                                   perm.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st), hist, cap,
+                                   _ptr(ws), ws.numel(), _stream()))
+    return SolveResult(perm.astype(np.int64), st, _records(hist, st.fw_iters), None)
