@@ -124,6 +124,13 @@ def uniform_matrix(n: int, seed: int) -> np.ndarray:
     return rng.random((n, n)).astype(np.float32)
 
 
+def cost_matrix(n: int, seed: int, lo: float = 100.0, hi: float = 150.0) -> np.ndarray:
+    """n x n costs drawn from Uniform(lo, hi) (float32): the cost matrices of
+    the LOT-versus-LAP comparison (Uniform(100, 150))."""
+    rng = np.random.default_rng(SEED_BASE + 700 + seed)
+    return (lo + (hi - lo) * rng.random((n, n))).astype(np.float32)
+
+
 def random_matrix(m: int, n: int, seed: int, lo: float = -1.0, hi: float = 1.0,
                   dtype=np.float32) -> np.ndarray:
     rng = np.random.default_rng(seed)
