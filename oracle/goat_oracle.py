@@ -476,3 +476,51 @@ def goat_seeded(A, B, seeds_A=(), seeds_B=(), P0=None, opt: GoatOptions | None =
             perm[a] = sp.order_B[pos[i]]
     score = float(np.sum(sp.A * sp.B[np.ix_(pos, pos)]))
     return SeededResult(perm, score, P, it, hist)
+
+
+# ---------------------------------------------------------------- FAQ, nomination
+
+def faq(A, B, P0=None, opt: GoatOptions | None = None, record: bool = False) -> GoatResult:
+    """Alg. 1 (FAQ), the comparison system: the Frank-Wolfe loop of Alg. 3
+    with the direction taken by an exact linear assignment on the gradient
+    (a permutation matrix maximising <Q, grad f(P)>; SciPy's solver is the
+    library step), the same exact step, and the final assignment on P.
+    Oracle only: the device library implements GOAT."""
+    from scipy.optimize import linear_sum_assignment
+    opt = opt or GoatOptions()
+    A = np.asarray(A, np.float64); B = np.asarray(B, np.float64)
+    n = A.shape[0]
+    P = barycenter(n) if P0 is None else np.asarray(P0, np.float64).copy()
+    hist = []
+    it = 0
+    for it in range(1, opt.fw_max + 1):
+        G = gradient(A, B, P)
+        rows, cols = linear_sum_assignment(G, maximize=True)
+        Q = np.zeros((n, n))
+        Q[rows, cols] = 1.0
+        GQ = gradient(A, B, Q)
+        ls = linesearch(P, Q, G, GQ)
+        P = P + ls.t * (Q - P)
+        if record:
+            hist.append(dict(it=it, t=ls.t, fP=ls.fP, fQ=ls.fQ, c=ls.c, direction=cols.copy()))
+        delta = ls.t * math.sqrt(ls.dist2) / math.sqrt(n)
+        if ls.t == 0.0 or (opt.fw_tol > 0.0 and delta < opt.fw_tol):
+            break
+    rows, cols = linear_sum_assignment(P if opt.proj == "P" else gradient(A, B, P), maximize=True)
+    perm = np.empty(n, dtype=np.int64)
+    perm[rows] = cols
+    return GoatResult(perm, qap_value(A, B, perm), P, it, hist)
+
+
+def nominate(P, k: int) -> np.ndarray:
+    """Soft matching (vertex nomination, Discussion): for each vertex i of A
+    the k vertices of B with the largest P[i, j], best first; equal values
+    in increasing column order."""
+    P = np.asarray(P, np.float64)
+    n = P.shape[1]
+    k = min(k, n)
+    out = np.empty((P.shape[0], k), dtype=np.int64)
+    for i in range(P.shape[0]):
+        order = sorted(range(n), key=lambda j: (-P[i, j], j))
+        out[i] = order[:k]
+    return out
