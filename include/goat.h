@@ -287,6 +287,24 @@ int goat_score(int n, const float* A, const float* B, int ld,
                const int32_t* perm_dev, double* out_dev,
                void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * goat_nominate - soft matching (vertex nomination; the Discussion names it
+ * as a use of the relaxed solution): for each row i of the device float
+ * matrix P (rows x cols, row-major, leading dimension ldp >= cols; the
+ * final iterate of goat_run_finish / goat_batch_get_P, or a Sinkhorn
+ * direction Q) the k columns with the largest P[i, j], best first; equal
+ * scores rank by increasing column. Writes idx_dev[i*k + r] (device int32,
+ * rows*k entries) and, unless val_dev is NULL, val_dev[i*k + r] = the score
+ * (device float). NaN scores are never nominated; a row with fewer than k
+ * other scores ends in -1 entries. Reads P once; no workspace; asynchronous
+ * on `stream`.
+ * Status: GOAT_EINVAL for rows or cols < 1, k outside [1, min(cols,
+ * GOAT_NOMINATE_KMAX)], ldp < cols, null P or idx_dev.
+ */
+#define GOAT_NOMINATE_KMAX 32
+int goat_nominate(int rows, int cols, const float* P, int ldp, int k,
+                  int32_t* idx_dev, float* val_dev, void* stream);
+
 /* ------------------------------------------------------------------------
  * Seeds and graphs of different sizes
  * ---------------------------------------------------------------------- */

@@ -355,6 +355,17 @@ int goat_score(int n, const float* A, const float* B, int ld, const int32_t* per
     return launch_score(n, A, B, ld, perm_dev, p.red, out_dev, static_cast<hipStream_t>(stream));
 }
 
+int goat_nominate(int rows, int cols, const float* P, int ldp, int k, int32_t* idx_dev, float* val_dev,
+                  void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(rows >= 1 && cols >= 1, "rows < 1 or cols < 1");
+    GOAT_CHECK_ARG(k >= 1 && k <= cols, "k outside [1, cols]");
+    GOAT_CHECK_ARG(k <= GOAT_NOMINATE_KMAX, "k > GOAT_NOMINATE_KMAX");
+    GOAT_CHECK_ARG(ldp >= cols, "leading dimension < cols");
+    GOAT_CHECK_ARG(P && idx_dev, "null pointer");
+    return launch_nominate(rows, cols, P, ldp, k, idx_dev, val_dev, static_cast<hipStream_t>(stream));
+}
+
 int goat_mlp_param_count(void) { return mlp_param_count(); }
 
 size_t goat_mlp_workspace_size(int n_samples) {

@@ -224,6 +224,9 @@ int launch_fill_barycenter(int n, int np, float* P, hipStream_t s);
 int launch_copy_pad(int n, const float* src, int lds, float* dst, int ldd, int np, hipStream_t s);
 int launch_split_bf16(int n, int np, const float* src, int lds, uint16_t* hi, uint16_t* lo,
                       hipStream_t s);
+// per-row top-k columns of a score matrix, best first (assign.hip)
+int launch_nominate(int rows, int cols, const float* P, int ldp, int k, int32_t* idx, float* val,
+                    hipStream_t s);
 int launch_score(int n, const float* A, const float* B, int ld, const int32_t* perm,
                  double* red, double* out, hipStream_t s);
 

@@ -93,6 +93,8 @@ def lib():
     L.goat_lap_max.argtypes = [_I, _VP, _I, _VP]
     L.goat_score.restype = _I
     L.goat_score.argtypes = [_I, _VP, _VP, _I, _VP, _VP, _VP, _SZ, _VP]
+    L.goat_nominate.restype = _I
+    L.goat_nominate.argtypes = [_I, _I, _VP, _I, _I, _VP, _VP, _VP]
     L.goat_run_begin.restype = _I
     L.goat_run_begin.argtypes = [_I, _VP, _VP, _I, _VP, ctypes.POINTER(Options), _VP, _SZ, _VP,
                                  ctypes.POINTER(ctypes.c_void_p)]
@@ -295,6 +297,23 @@ def score(A, B, perm):
     _check(lib().goat_score(n, _ptr(A), _ptr(B), A.stride(0), _ptr(p), _ptr(out), _ptr(ws), ws.numel(),
                             _stream()))
     return out
+
+
+NOMINATE_KMAX = 32
+
+
+def nominate(P, k: int):
+    """Soft matching (goat_nominate): for each row of the device float matrix
+    P, the k columns with the largest scores, best first (ties by increasing
+    column). Returns (idx int32 [rows, k], val float32 [rows, k]) on P's
+    device."""
+    torch = _torch()
+    P = _mat(P, "P")
+    rows, cols = P.shape
+    idx = torch.empty((rows, k), dtype=torch.int32, device=P.device)
+    val = torch.empty((rows, k), dtype=torch.float32, device=P.device)
+    _check(lib().goat_nominate(rows, cols, _ptr(P), P.stride(0), k, _ptr(idx), _ptr(val), _stream()))
+    return idx, val
 
 
 def lap_max(M: np.ndarray) -> np.ndarray:

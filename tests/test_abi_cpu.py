@@ -198,3 +198,15 @@ def test_batch_arguments_rejected_before_device(G):
                               None, None, None) == G.GOAT_EINVAL
     assert L.goat_tune(0, 1, None) == G.GOAT_EINVAL
     assert L.goat_tune_get(2000, None, None) == G.GOAT_EINVAL
+
+
+def test_nominate_arguments_rejected_before_device(G):
+    L = G.lib()
+    dummy = ctypes.c_void_p(16)
+    assert L.goat_nominate(0, 5, dummy, 5, 1, dummy, None, None) == G.GOAT_EINVAL      # rows < 1
+    assert L.goat_nominate(4, 5, dummy, 5, 6, dummy, None, None) == G.GOAT_EINVAL      # k > cols
+    assert L.goat_nominate(4, 50, dummy, 50, 33, dummy, None, None) == G.GOAT_EINVAL   # k > kmax
+    assert L.goat_nominate(4, 5, dummy, 5, 0, dummy, None, None) == G.GOAT_EINVAL      # k < 1
+    assert L.goat_nominate(4, 5, dummy, 4, 2, dummy, None, None) == G.GOAT_EINVAL      # ld < cols
+    assert L.goat_nominate(4, 5, None, 5, 2, dummy, None, None) == G.GOAT_EINVAL       # null P
+    assert G.NOMINATE_KMAX == 32
