@@ -524,3 +524,35 @@ def nominate(P, k: int) -> np.ndarray:
         order = sorted(range(n), key=lambda j: (-P[i, j], j))
         out[i] = order[:k]
     return out
+
+
+# ----------------------------------------------------- quantised assignment
+
+def lap_resolution_bits(n: int) -> int:
+    """READING (device assignment): the integer scores of the final
+    assignment carry R = min(24, 38 - ceil(log2(n + 1))) bits."""
+    return min(24, 38 - int(math.ceil(math.log2(n + 1))))
+
+
+def quantised_scores(M) -> tuple[np.ndarray, int]:
+    """The integer scores the device assignment maximises: with
+    2^(e-1) <= max|M| < 2^e and s = R - 1 - e, c = rint(M 2^s) - min rint(M 2^s)
+    (round half to even). Returns (c as int64, s)."""
+    M = np.asarray(M, np.float64)
+    R = lap_resolution_bits(M.shape[0])
+    mx = float(np.max(np.abs(M)))
+    e = int(np.frexp(mx)[1]) if mx > 0 else 0
+    s = R - 1 - e
+    q = np.rint(np.ldexp(M, s)).astype(np.int64)
+    return q - q.min(), s
+
+
+def lap_quantised(M) -> tuple[np.ndarray, int]:
+    """An optimal assignment of the quantised scores (Alg. 3 return line on
+    c) and its value sum_i c[i, perm i] (exact, integer)."""
+    from scipy.optimize import linear_sum_assignment
+    c, _ = quantised_scores(M)
+    rows, cols = linear_sum_assignment(c, maximize=True)
+    perm = np.empty(c.shape[0], dtype=np.int64)
+    perm[rows] = cols
+    return perm, int(c[rows, cols].sum())

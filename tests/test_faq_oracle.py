@@ -9,6 +9,9 @@ paper's comparison on the three-block SBM of its first simulation).
 nominate: k = 1 is numpy's first arg-max; k = cols is numpy's lexsort order
 (score descending, column ascending); a permutation matrix nominates its own
 permutation first.
+Quantised assignment scores (the device assignment's integer problem): exact
+on dyadic inputs, brute-force optimum at n = 7, and within n 2^-s of the
+float optimum.
 """
 import itertools
 
@@ -107,3 +110,40 @@ def test_nominate_permutation_matrix_first():
     assert np.array_equal(top[:, 0], perm)
     # the runner-up is the smallest other column (all zeros tie)
     assert np.array_equal(top[:, 1], np.where(perm == 0, 1, 0))
+
+
+# ------------------------------------------------- quantised assignment scores
+
+def test_quantised_scores_exact_on_dyadic_input():
+    # scores that are multiples of 2^-s are mapped by the affine map exactly
+    rng = np.random.default_rng(21)
+    n = 40
+    M = rng.integers(-1000, 1000, size=(n, n)).astype(np.float64) / 1024.0
+    c, s = O.quantised_scores(M)
+    R = O.lap_resolution_bits(n)
+    assert R == min(24, 38 - 6)
+    mx = np.abs(M).max()
+    assert 2.0 ** (R - 2) <= mx * 2.0 ** s < 2.0 ** (R - 1)
+    assert np.array_equal(c, (M * 2.0 ** s - M.min() * 2.0 ** s).astype(np.int64))
+    assert c.min() == 0 and c.max() <= 2 ** R
+
+
+def test_lap_quantised_optimum_by_brute_force():
+    rng = np.random.default_rng(22)
+    M = rng.random((7, 7))
+    perm, val = O.lap_quantised(M)
+    c, _ = O.quantised_scores(M)
+    best = max(int(c[np.arange(7), list(p)].sum()) for p in itertools.permutations(range(7)))
+    assert val == best == int(c[np.arange(7), perm].sum())
+
+
+def test_quantised_assignment_near_float_optimum():
+    # on M itself the quantised optimum loses at most n 2^-s
+    rng = np.random.default_rng(23)
+    n = 60
+    M = rng.random((n, n)) ** 6
+    perm, _ = O.lap_quantised(M)
+    _, s = O.quantised_scores(M)
+    fperm = O.hungarian_max(M)
+    best = M[np.arange(n), fperm].sum()
+    assert M[np.arange(n), perm].sum() >= best - n * 2.0 ** -s
