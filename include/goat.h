@@ -150,7 +150,11 @@ typedef struct goat_options {
                              iteration; 3 the network first, then as 1            */
     int   stop_on_stall;  /* 1: stop when t == 0 (default); 0: run fw_max iterations */
     int   check_every;    /* Sinkhorn convergence flag polled every k iterations (16) */
-    int   reserved[5];
+    int   lap;            /* final assignment: 0 host Jonker-Volgenant on float64
+                             scores (default); 1 device auction on the quantised
+                             scores (goat_lap_device), host if it reports
+                             GOAT_ENOTSUP                                        */
+    int   reserved[4];
     const float* mlp_params; /* device float[goat_mlp_param_count()] (warm 2, 3) */
 } goat_options;
 
@@ -167,11 +171,11 @@ typedef struct goat_stats {
     int    fw_iters;       /* Frank-Wolfe iterations run                      */
     int    sk_iters_total; /* Sinkhorn iterations summed over FW iterations   */
     int    sk_capped;      /* FW iterations whose Sinkhorn hit sk_max         */
-    int    pad;
+    int    lap_device;     /* 1: the final assignment ran on the device       */
     double f_final;        /* f(P_final) = tr(A^T P B P^T)                    */
     double score;          /* tr(A^T Pi B Pi^T) of the returned permutation   */
     double ms_loop;        /* device time of the FW loop (HIP events)         */
-    double ms_lap;         /* host time of the final assignment               */
+    double ms_lap;         /* wall time of the final assignment               */
     double ms_total;       /* wall time of the call                           */
 } goat_stats;
 
@@ -275,6 +279,39 @@ int    goat_mlp_adam(const float* grad, float* params, float* m, float* v,
  * column index among equal path lengths). O(n^3) worst case.
  */
 int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
+
+/*
+ * goat_lap_device - the same projection on the device for a device float
+ * matrix M (n x n, leading dimension ld): Bertsekas' auction with epsilon
+ * scaling, Jacobi form, on integer scores. With 2^(e-1) <= max|M| < 2^e,
+ * R = min(24, 38 - ceil(log2(n+1))) and s = R - 1 - e, the scores are
+ * c_ij = rint(M_ij * 2^s) - min_kl rint(M_kl * 2^s) (round half to even;
+ * 0 <= c <= 2^R), and perm maximises sum_i c[i][perm i] exactly; on M
+ * itself it is within n * 2^-s of the optimum. Equal bids go to the lowest
+ * row, so the result is deterministic. All-equal c gives the identity.
+ *  perm_dev   device int32[n] (row i -> column perm_dev[i]).
+ *  ws         device workspace of goat_lap_device_workspace_size(n) bytes.
+ *  max_rounds cap on bidding rounds summed over phases (<= 0: 4,000,000).
+ *  stats      host goat_lap_stats (may be NULL).
+ * Host-synchronous on `stream` (it polls a device counter between batches
+ * of rounds).
+ * Status: GOAT_EINVAL for n < 1, n >= 2^20 - 1, ld < n, null pointers or a
+ * non-finite entry; GOAT_ENOMEM for a short workspace; GOAT_ENOTSUP when
+ * the round cap is reached or a bid would exceed 2^43 (the host solver,
+ * goat_lap_max, has neither limit).
+ */
+typedef struct goat_lap_stats {
+    long long rounds;           /* bidding rounds that ran (all phases)     */
+    long long rounds_launched;  /* rounds enqueued, including idle ones     */
+    int phases;                 /* epsilon phases                           */
+    int shift;                  /* s above                                  */
+    int resolution_bits;        /* R above                                  */
+    int pad;
+} goat_lap_stats;
+size_t goat_lap_device_workspace_size(int n);
+int goat_lap_device(int n, const float* M, int ld, int32_t* perm_dev,
+                    void* ws, size_t ws_bytes, long long max_rounds,
+                    goat_lap_stats* stats, void* stream);
 
 /*
  * goat_score - tr(A^T Pi B Pi^T) = sum_ij A_ij B_{perm i, perm j} for a

@@ -355,6 +355,18 @@ int goat_score(int n, const float* A, const float* B, int ld, const int32_t* per
     return launch_score(n, A, B, ld, perm_dev, p.red, out_dev, static_cast<hipStream_t>(stream));
 }
 
+size_t goat_lap_device_workspace_size(int n) { return auction_ws_bytes(n); }
+
+int goat_lap_device(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size_t ws_bytes,
+                    long long max_rounds, goat_lap_stats* stats, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(ld >= n, "leading dimension < n");
+    GOAT_CHECK_ARG(M && perm_dev && ws, "null pointer");
+    return auction_lap(n, M, ld, perm_dev, ws, ws_bytes, max_rounds > 0 ? max_rounds : 4000000ll, stats,
+                       static_cast<hipStream_t>(stream));
+}
+
 int goat_nominate(int rows, int cols, const float* P, int ldp, int k, int32_t* idx_dev, float* val_dev,
                   void* stream) {
     clear_error();

@@ -12,6 +12,10 @@
 // once: HBM traffic is rows * cols * 4 bytes plus the output.
 #include "common.h"
 
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
 namespace goat {
 namespace {
 
@@ -134,6 +138,335 @@ int launch_nominate(int rows, int cols, const float* P, int ldp, int k, int32_t*
     else
         launch_nom_K<32>(rows, cols, P, ldp, k, vec4, idx, val, s);
     GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+// ---------------------------------------------------------------- device assignment
+//
+// Final projection of Alg. 3 on the device: a permutation maximising
+// sum_i M[i, perm i], solved by Bertsekas' auction with epsilon scaling in
+// its Jacobi form (every unassigned row bids in the same round).
+//
+// Scores are first mapped to integers: with 2^(e-1) <= max|M| < 2^e and
+// s = R - 1 - e, q_ij = rint(M_ij 2^s) (round half to even; the scaling by
+// 2^s is exact) and c_ij = q_ij - min q, so 0 <= c_ij <= 2^R. Prices and
+// bids live in units of 1 / (n + 1) of c: a final phase with epsilon = 1
+// unit leaves the assignment within n / (n + 1) < 1 of the optimum of c,
+// hence optimal for c. R = min(24, 38 - ceil(log2(n + 1))) keeps every
+// scaled cost below 2^38; a phase raises no price by more than the cost
+// range plus epsilon, so over the ~14 phases a bid stays below 2^43 and
+// packs with its row (20 bits, lowest row wins equal bids) into one 64-bit
+// atomicMax word. A bid past 2^43 is reported, not wrapped.
+// Everything is integer once c is formed, so the result does not depend on
+// the order in which threads run.
+
+namespace {
+
+constexpr int AB = 256;             // threads per block
+constexpr int kRowBits = 20;
+constexpr unsigned long long kRowMask = (1ull << kRowBits) - 1;
+constexpr long long kBidLimit = 1ll << 43;
+
+struct AuctionArgs {
+    const float* M;
+    long ld;
+    int n, s, qmin, vec4;
+    long long np1;               // n + 1
+    long long* price;
+    unsigned long long* slot;
+    int32_t* owner;              // row holding object j, or -1
+    int32_t* assign;             // object held by row i, or -1
+    int* ctl;                    // [0] rows assigned, [1] bid overflow, [2] rounds bid
+};
+
+__device__ inline long long auc_value(const AuctionArgs& a, float m, int j) {
+    const int q = (int)rintf(ldexpf(m, a.s));
+    return (long long)(q - a.qmin) * a.np1 - a.price[j];
+}
+
+// (v, j) ranks before (w, k): larger value, or equal and smaller column
+__device__ inline bool auc_better(long long v, int j, long long w, int k) {
+    return v > w || (v == w && j < k);
+}
+
+__device__ inline void auc_push(long long& v1, int& j1, long long& v2, long long v, int j) {
+    if (auc_better(v, j, v1, j1)) {
+        v2 = v1;
+        v1 = v;
+        j1 = j;
+    } else if (v > v2) {
+        v2 = v;
+    }
+}
+
+// one workgroup per bidding row: rows b, b + grid, ... of the unassigned set
+__device__ inline void auc_merge(long long& v1, int& j1, long long& v2, long long ov1, int oj1, long long ov2) {
+    if (auc_better(ov1, oj1, v1, j1)) {
+        v2 = v1 > ov2 ? v1 : ov2;
+        v1 = ov1;
+        j1 = oj1;
+    } else {
+        v2 = v2 > ov1 ? v2 : ov1;
+    }
+}
+
+__global__ __launch_bounds__(AB) void auction_bid_kernel(AuctionArgs a, long long eps) {
+    __shared__ long long sv1[AB / 64], sv2[AB / 64];
+    __shared__ int sj1[AB / 64];
+    if (a.ctl[0] == a.n) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.ctl[2], 1);
+    const int t = threadIdx.x;
+    for (int i = blockIdx.x; i < a.n; i += gridDim.x) {
+        if (a.assign[i] >= 0) continue;
+        const float* r = a.M + (long)i * a.ld;
+        long long v1 = LLONG_MIN, v2 = LLONG_MIN;
+        int j1 = INT_MAX;
+        int j0 = 0;
+        if (a.vec4) {
+            const int c4 = a.n >> 2;
+            const float4* r4 = reinterpret_cast<const float4*>(r);
+#pragma unroll 2
+            for (int q = t; q < c4; q += AB) {
+                const float4 x = r4[q];
+                const int j = 4 * q;
+                auc_push(v1, j1, v2, auc_value(a, x.x, j), j);
+                auc_push(v1, j1, v2, auc_value(a, x.y, j + 1), j + 1);
+                auc_push(v1, j1, v2, auc_value(a, x.z, j + 2), j + 2);
+                auc_push(v1, j1, v2, auc_value(a, x.w, j + 3), j + 3);
+            }
+            j0 = c4 << 2;
+        }
+        for (int j = j0 + t; j < a.n; j += AB) auc_push(v1, j1, v2, auc_value(a, r[j], j), j);
+        // merge (best, column, second best) over the wave, then the waves
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const long long ov1 = __shfl_xor(v1, o, 64);
+            const long long ov2 = __shfl_xor(v2, o, 64);
+            const int oj1 = __shfl_xor(j1, o, 64);
+            auc_merge(v1, j1, v2, ov1, oj1, ov2);
+        }
+        if ((t & 63) == 0) {
+            sv1[t >> 6] = v1;
+            sv2[t >> 6] = v2;
+            sj1[t >> 6] = j1;
+        }
+        __syncthreads();
+        if (t == 0) {
+#pragma unroll
+            for (int w = 1; w < AB / 64; ++w) auc_merge(v1, j1, v2, sv1[w], sj1[w], sv2[w]);
+            // n >= 2, so both values are real: bid = price + (v1 - v2) + eps
+            const long long bid = a.price[j1] + (v1 - v2) + eps;
+            if (bid >= kBidLimit) {
+                atomicOr(&a.ctl[1], 1);
+            } else {
+                const unsigned long long w =
+                    ((unsigned long long)bid << kRowBits) | (kRowMask - (unsigned long long)i);
+                atomicMax(&a.slot[j1], w);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(AB) void auction_resolve_kernel(AuctionArgs a) {
+    const int j = blockIdx.x * AB + threadIdx.x;
+    if (j >= a.n) return;
+    const unsigned long long w = a.slot[j];
+    if (w == 0) return;
+    a.slot[j] = 0;
+    const int i = (int)(kRowMask - (w & kRowMask));
+    const int old = a.owner[j];
+    a.owner[j] = i;
+    a.assign[i] = j;
+    a.price[j] = (long long)(w >> kRowBits);
+    // the previous owner was assigned at the start of the round, so it made
+    // no bid and no other object writes its entry
+    if (old >= 0)
+        a.assign[old] = -1;
+    else
+        atomicAdd(&a.ctl[0], 1);
+}
+
+__global__ __launch_bounds__(AB) void auction_reset_kernel(AuctionArgs a, int first) {
+    const int j = blockIdx.x * AB + threadIdx.x;
+    if (j == 0) {
+        a.ctl[0] = 0;
+        if (first) {
+            a.ctl[1] = 0;
+            a.ctl[2] = 0;
+        }
+    }
+    if (j >= a.n) return;
+    a.owner[j] = -1;
+    a.assign[j] = -1;
+    a.slot[j] = 0;
+    if (first) a.price[j] = 0;
+}
+
+// per block: max |x|, min x, and a flag for non-finite entries
+__global__ __launch_bounds__(AB) void auction_range_kernel(int n, const float* __restrict__ M, long ld,
+                                                           float* __restrict__ part) {
+    __shared__ float sh[3][AB / 64];
+    float mx = 0.0f, mn = INFINITY, bad = 0.0f;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const float* r = M + (long)i * ld;
+        for (int j = threadIdx.x; j < n; j += AB) {
+            const float x = r[j];
+            if (!isfinite(x)) bad = 1.0f;
+            mx = fmaxf(mx, fabsf(x));
+            mn = fminf(mn, x);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        mn = fminf(mn, __shfl_xor(mn, o, 64));
+        bad = fmaxf(bad, __shfl_xor(bad, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = mx;
+        sh[1][threadIdx.x >> 6] = mn;
+        sh[2][threadIdx.x >> 6] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < AB / 64; ++w) {
+            mx = fmaxf(mx, sh[0][w]);
+            mn = fminf(mn, sh[1][w]);
+            bad = fmaxf(bad, sh[2][w]);
+        }
+        part[3 * blockIdx.x] = mx;
+        part[3 * blockIdx.x + 1] = mn;
+        part[3 * blockIdx.x + 2] = bad;
+    }
+}
+
+constexpr int kRangeWG = 512;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t auction_ws_bytes(int n) {
+    if (n < 1) return 0;
+    return align256((size_t)n * 8) * 2 + align256((size_t)n * 4) * 2 + 256 + align256(kRangeWG * 3 * 4);
+}
+
+int auction_resolution_bits(int n) {
+    int b = 0;
+    while ((1ll << b) < (long long)n + 1) ++b;   // ceil(log2(n + 1))
+    return std::min(24, 38 - b);
+}
+
+int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size_t ws_bytes, long long max_rounds,
+                AuctionStats* st, hipStream_t s) {
+    AuctionStats loc{};
+    if (n >= (1 << kRowBits) - 1) {
+        set_error("goat_lap_device: n too large");
+        return GOAT_EINVAL;
+    }
+    if (ws_bytes < auction_ws_bytes(n)) {
+        set_error("goat_lap_device: workspace too small");
+        return GOAT_ENOMEM;
+    }
+    char* base = static_cast<char*>(ws);
+    AuctionArgs a{};
+    a.M = M;
+    a.ld = ld;
+    a.n = n;
+    a.np1 = (long long)n + 1;
+    a.vec4 = (ld % 4) == 0 && (reinterpret_cast<uintptr_t>(M) % 16) == 0;
+    a.price = reinterpret_cast<long long*>(base);
+    base += align256((size_t)n * 8);
+    a.slot = reinterpret_cast<unsigned long long*>(base);
+    base += align256((size_t)n * 8);
+    a.owner = reinterpret_cast<int32_t*>(base);
+    base += align256((size_t)n * 4);
+    a.assign = reinterpret_cast<int32_t*>(base);
+    base += align256((size_t)n * 4);
+    a.ctl = reinterpret_cast<int*>(base);
+    base += 256;
+    float* part = reinterpret_cast<float*>(base);
+
+    // score range: the quantisation's shift and offset
+    const int nb = std::min(n, kRangeWG);
+    hipLaunchKernelGGL(auction_range_kernel, dim3(nb), dim3(AB), 0, s, n, M, (long)ld, part);
+    GOAT_HIP(hipGetLastError());
+    std::vector<float> hp((size_t)nb * 3);
+    GOAT_HIP(hipMemcpyAsync(hp.data(), part, hp.size() * 4, hipMemcpyDeviceToHost, s));
+    GOAT_HIP(hipStreamSynchronize(s));
+    float mx = 0.0f, mn = INFINITY;
+    for (int b = 0; b < nb; ++b) {
+        if (hp[3 * b + 2] != 0.0f) {
+            set_error("goat_lap_device: non-finite entry");
+            return GOAT_EINVAL;
+        }
+        mx = std::max(mx, hp[3 * b]);
+        mn = std::min(mn, hp[3 * b + 1]);
+    }
+    const int R = auction_resolution_bits(n);
+    int e = 0;
+    if (mx > 0.0f) std::frexp(mx, &e);
+    a.s = R - 1 - e;
+    a.qmin = (int)std::nearbyint(std::ldexp(mn, a.s));   // rint is monotone: min q = q(min M)
+    const long long cmax = (long long)std::nearbyint(std::ldexp(mx, a.s)) - a.qmin;
+    loc.shift = a.s;
+    loc.resolution_bits = R;
+
+    const int gr = (n + AB - 1) / AB;
+    hipLaunchKernelGGL(auction_reset_kernel, dim3(gr), dim3(AB), 0, s, a, 1);
+    GOAT_HIP(hipGetLastError());
+    if (n == 1 || cmax == 0) {
+        // one vertex, or all scores equal after quantisation: the identity
+        // (lowest columns first) is optimal
+        std::vector<int32_t> id(n);
+        for (int i = 0; i < n; ++i) id[i] = i;
+        GOAT_HIP(hipMemcpyAsync(perm_dev, id.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+        GOAT_HIP(hipStreamSynchronize(s));
+        if (st) *st = loc;
+        return GOAT_OK;
+    }
+    // bidding grid: one workgroup per row while many bid, a stride loop beyond
+    const int gb = std::min(n, 2048);
+    const long long cbig = cmax * a.np1;
+    long long eps = std::max(1ll, cbig / 4);
+    int ctl[3] = {0, 0, 0};
+    long long rounds = 0;
+    for (;;) {
+        ++loc.phases;
+        if (loc.phases > 1) {
+            hipLaunchKernelGGL(auction_reset_kernel, dim3(gr), dim3(AB), 0, s, a, 0);
+            GOAT_HIP(hipGetLastError());
+        }
+        int batch = 4;
+        for (;;) {
+            for (int k = 0; k < batch; ++k) {
+                hipLaunchKernelGGL(auction_bid_kernel, dim3(gb), dim3(AB), 0, s, a, eps);
+                hipLaunchKernelGGL(auction_resolve_kernel, dim3(gr), dim3(AB), 0, s, a);
+            }
+            GOAT_HIP(hipGetLastError());
+            rounds += batch;
+            GOAT_HIP(hipMemcpyAsync(ctl, a.ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
+            GOAT_HIP(hipStreamSynchronize(s));
+            if (ctl[1]) {
+                set_error("goat_lap_device: bid overflow");
+                return GOAT_ENOTSUP;
+            }
+            if (ctl[0] == n) break;
+            if (rounds >= max_rounds) {
+                set_error("goat_lap_device: round limit reached");
+                return GOAT_ENOTSUP;
+            }
+            batch = std::min(batch * 2, 64);
+        }
+        if (eps == 1) break;
+        eps = std::max(1ll, eps / 6);
+    }
+    loc.rounds = ctl[2];
+    loc.rounds_launched = rounds;
+    GOAT_HIP(hipMemcpyAsync(perm_dev, a.assign, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+    GOAT_HIP(hipStreamSynchronize(s));
+    if (st) *st = loc;
     return GOAT_OK;
 }
 

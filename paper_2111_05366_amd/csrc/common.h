@@ -224,6 +224,14 @@ int launch_fill_barycenter(int n, int np, float* P, hipStream_t s);
 int launch_copy_pad(int n, const float* src, int lds, float* dst, int ldd, int np, hipStream_t s);
 int launch_split_bf16(int n, int np, const float* src, int lds, uint16_t* hi, uint16_t* lo,
                       hipStream_t s);
+// Final assignment on the device (assign.hip): epsilon-scaling auction on
+// the integer-quantised scores; perm_dev receives the row -> column map.
+using AuctionStats = goat_lap_stats;
+size_t auction_ws_bytes(int n);
+int auction_resolution_bits(int n);
+int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size_t ws_bytes, long long max_rounds,
+                AuctionStats* st, hipStream_t s);
+
 // per-row top-k columns of a score matrix, best first (assign.hip)
 int launch_nominate(int rows, int cols, const float* P, int ldp, int k, int32_t* idx, float* val,
                     hipStream_t s);

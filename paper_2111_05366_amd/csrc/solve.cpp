@@ -185,6 +185,7 @@ static int run_begin_impl(int n, const float* A, const float* B, int ld, const f
     GOAT_CHECK_ARG(opt.sk_max >= 1 && opt.fw_max >= 1, "sk_max and fw_max must be >= 1");
     GOAT_CHECK_ARG(std::isfinite(opt.fw_tol) && opt.fw_tol >= 0.0f, "bad fw_tol");
     GOAT_CHECK_ARG(opt.warm >= 0 && opt.warm <= 3, "unknown warm-start mode");
+    GOAT_CHECK_ARG(opt.lap == 0 || opt.lap == 1, "unknown assignment mode");
     GOAT_CHECK_ARG(opt.warm < 2 || opt.mlp_params, "warm-start network requested without parameters");
     const Layout L = make_layout(n, opt.prec, opt.symmetric);
     if (ws_bytes < L.total) { set_error("goat_run_begin: workspace too small"); return GOAT_ENOMEM; }
@@ -277,24 +278,38 @@ int goat_run_finish(goat_run* h, int32_t* perm_host, goat_stats* stats_host, flo
     if (P_out)
         GOAT_HIP(hipMemcpy2DAsync(P_out, (size_t)ldp * 4, p.P, (size_t)np * 4, (size_t)n * 4, n,
                                   hipMemcpyDeviceToDevice, r.s));
-    // final projection (Alg. 3 return line) on the host
-    std::vector<float> hm((size_t)n * n);
-    GOAT_HIP(hipMemcpy2DAsync(hm.data(), (size_t)n * 4, r.opt.proj ? p.GP : p.P, (size_t)np * 4, (size_t)n * 4, n,
-                              hipMemcpyDeviceToHost, r.s));
-    GOAT_HIP(hipStreamSynchronize(r.s));
     if (r.fw == 0) {
         // no iteration ran: f(P0) = <P0, grad f(P0)>/2 is not tracked; report 0
         r.st.f_final = 0.0;
     }
+    // final projection (Alg. 3 return line)
+    const float* src = r.opt.proj ? p.GP : p.P;
     const auto lap0 = std::chrono::steady_clock::now();
-    {
+    bool on_device = false;
+    if (r.opt.lap == 1 && auction_ws_bytes(n) <= (size_t)np * np * 4) {
+        // the direction buffer Q is free once the loop has ended
+        int rc = auction_lap(n, src, np, p.perm_dev, p.Q, (size_t)np * np * 4, 4000000ll, nullptr, r.s);
+        if (rc == GOAT_OK) {
+            on_device = true;
+            GOAT_HIP(hipMemcpyAsync(perm_host, p.perm_dev, (size_t)n * 4, hipMemcpyDeviceToHost, r.s));
+        } else if (rc != GOAT_ENOTSUP) {
+            return rc;
+        }
+    }
+    if (!on_device) {
+        std::vector<float> hm((size_t)n * n);
+        GOAT_HIP(hipMemcpy2DAsync(hm.data(), (size_t)n * 4, src, (size_t)np * 4, (size_t)n * 4, n,
+                                  hipMemcpyDeviceToHost, r.s));
+        GOAT_HIP(hipStreamSynchronize(r.s));
         std::vector<double> md(hm.begin(), hm.end());
         std::vector<float>().swap(hm);
         int rc = lap_max(n, md.data(), n, perm_host);
         if (rc) return rc;
+        GOAT_HIP(hipMemcpyAsync(p.perm_dev, perm_host, (size_t)n * 4, hipMemcpyHostToDevice, r.s));
     }
+    GOAT_HIP(hipStreamSynchronize(r.s));
+    r.st.lap_device = on_device ? 1 : 0;
     r.st.ms_lap = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - lap0).count();
-    GOAT_HIP(hipMemcpyAsync(p.perm_dev, perm_host, (size_t)n * 4, hipMemcpyHostToDevice, r.s));
     int rc = launch_score(n, r.A, r.B, r.ld, p.perm_dev, p.red, p.scal + 10, r.s);
     if (rc) return rc;
     GOAT_HIP(hipMemcpyAsync(r.hbuf, p.scal + 10, 8, hipMemcpyDeviceToHost, r.s));

@@ -32,7 +32,7 @@ class Options(ctypes.Structure):
                 ("fw_max", ctypes.c_int), ("fw_tol", ctypes.c_float), ("prec", ctypes.c_int),
                 ("symmetric", ctypes.c_int), ("proj", ctypes.c_int), ("warm", ctypes.c_int),
                 ("stop_on_stall", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5), ("mlp_params", ctypes.c_void_p)]
+                ("lap", ctypes.c_int), ("reserved", ctypes.c_int * 4), ("mlp_params", ctypes.c_void_p)]
 
 
 class IterRecord(ctypes.Structure):
@@ -44,10 +44,16 @@ class IterRecord(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("fw_iters", ctypes.c_int), ("sk_iters_total", ctypes.c_int),
-                ("sk_capped", ctypes.c_int), ("pad", ctypes.c_int),
+                ("sk_capped", ctypes.c_int), ("lap_device", ctypes.c_int),
                 ("f_final", ctypes.c_double), ("score", ctypes.c_double),
                 ("ms_loop", ctypes.c_double), ("ms_lap", ctypes.c_double),
                 ("ms_total", ctypes.c_double)]
+
+
+class LapStats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_longlong), ("rounds_launched", ctypes.c_longlong),
+                ("phases", ctypes.c_int), ("shift", ctypes.c_int), ("resolution_bits", ctypes.c_int),
+                ("pad", ctypes.c_int)]
 
 
 class Pair(ctypes.Structure):
@@ -93,6 +99,10 @@ def lib():
     L.goat_lap_max.argtypes = [_I, _VP, _I, _VP]
     L.goat_score.restype = _I
     L.goat_score.argtypes = [_I, _VP, _VP, _I, _VP, _VP, _VP, _SZ, _VP]
+    L.goat_lap_device_workspace_size.restype = _SZ
+    L.goat_lap_device_workspace_size.argtypes = [_I]
+    L.goat_lap_device.restype = _I
+    L.goat_lap_device.argtypes = [_I, _VP, _I, _VP, _VP, _SZ, ctypes.c_longlong, ctypes.POINTER(LapStats), _VP]
     L.goat_nominate.restype = _I
     L.goat_nominate.argtypes = [_I, _I, _VP, _I, _I, _VP, _VP, _VP]
     L.goat_run_begin.restype = _I
@@ -297,6 +307,23 @@ def score(A, B, perm):
     _check(lib().goat_score(n, _ptr(A), _ptr(B), A.stride(0), _ptr(p), _ptr(out), _ptr(ws), ws.numel(),
                             _stream()))
     return out
+
+
+def lap_device(M, max_rounds: int = 0):
+    """Device assignment maximising sum_i M[i, perm i] on the quantised
+    scores (goat_lap_device). M: row-major float32 device matrix. Returns
+    (perm int32 device tensor, LapStats)."""
+    torch = _torch()
+    _mat(M, "M")
+    n = M.shape[0]
+    if M.shape[1] != n:
+        raise ValueError("M must be square")
+    ws = torch.empty(max(int(lib().goat_lap_device_workspace_size(n)), 1), dtype=torch.uint8, device=M.device)
+    perm = torch.empty(n, dtype=torch.int32, device=M.device)
+    st = LapStats()
+    _check(lib().goat_lap_device(n, _ptr(M), M.stride(0), _ptr(perm), _ptr(ws), ws.numel(), max_rounds,
+                                 ctypes.byref(st), _stream()))
+    return perm, st
 
 
 NOMINATE_KMAX = 32

@@ -1,0 +1,132 @@
+"""The final assignment on the device (goat_lap_device) against the oracle's
+assignment of the same quantised scores: the returned map is a permutation
+and its integer score equals the oracle's optimum exactly (several optimal
+permutations may exist, so the value is compared, not the map); the shift s
+is the oracle's. Cases: uniform, heavily tied, negative, near-permutation
+and doubly stochastic scores, aligned and unaligned leading dimensions,
+n = 2 .. 4000, the all-equal and one-vertex cases, goat_solve with the
+device assignment, a planted permutation at n = 10,000, and the round cap.
+"""
+import numpy as np
+import pytest
+
+from oracle import goat_oracle as O
+from paper_2111_05366_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_05366_amd import goat
+    goat.lib()
+    yield goat
+    goat.release_workspace()
+
+
+def _scores(kind, n, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        M = rng.random((n, n))
+    elif kind == "ties":
+        M = np.floor(rng.random((n, n)) * 4) / 4
+    elif kind == "negative":
+        M = -rng.uniform(100, 150, (n, n))
+    elif kind == "normal":
+        M = rng.standard_normal((n, n))
+    elif kind == "nearperm":
+        M = rng.random((n, n)) * 1e-3 / n
+        M[np.arange(n), rng.permutation(n)] += 0.9
+    elif kind == "ds":
+        X = rng.random((n, n)) ** 8
+        M = O.sinkhorn_knopp(X + 1e-12, tol=1e-10)
+    return M.astype(np.float32)
+
+
+def _device(M, ld=None):
+    n = M.shape[0]
+    ld = n if ld is None else ld
+    buf = torch.zeros((n, ld), dtype=torch.float32, device="cuda")
+    buf[:, :n] = torch.as_tensor(M, device="cuda")
+    return buf[:, :n]
+
+
+def _check(G, M, ld=None):
+    n = M.shape[0]
+    perm, st = G.lap_device(_device(M, ld))
+    perm = perm.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(perm), np.arange(n))
+    c, s = O.quantised_scores(M.astype(np.float64))
+    _, best = O.lap_quantised(M.astype(np.float64))
+    assert int(c[np.arange(n), perm].sum()) == best
+    if n > 1 and c.max() > 0:
+        assert st.shift == s and st.resolution_bits == O.lap_resolution_bits(n)
+    return perm, st
+
+
+@pytest.mark.parametrize("kind,n,ld", [
+    ("uniform", 2, None), ("uniform", 3, None), ("ties", 64, None), ("normal", 257, None),
+    ("uniform", 1000, None), ("negative", 1000, 1003), ("ties", 777, 780), ("ds", 1500, None),
+    ("nearperm", 2001, 2005), ("uniform", 4000, None),
+])
+def test_lap_device_parity(G, kind, n, ld):
+    print(f"lap_device {kind} n={n} ld={ld}", flush=True)
+    _, st = _check(G, _scores(kind, n, 31 * n + len(kind)), ld)
+    print(f"  rounds {st.rounds} (launched {st.rounds_launched}), phases {st.phases}", flush=True)
+
+
+def test_lap_device_degenerate(G):
+    perm, _ = G.lap_device(torch.full((1, 1), 3.0, device="cuda"))
+    assert perm.cpu().tolist() == [0]
+    perm, _ = G.lap_device(torch.full((50, 50), 0.25, device="cuda"))
+    assert np.array_equal(perm.cpu().numpy(), np.arange(50))
+    perm, _ = G.lap_device(torch.zeros((9, 9), device="cuda"))
+    assert np.array_equal(perm.cpu().numpy(), np.arange(9))
+
+
+def test_lap_device_rejects_nonfinite_and_round_cap(G):
+    M = torch.rand((40, 40), device="cuda")
+    M[3, 5] = float("nan")
+    with pytest.raises(G.GoatError) as e:
+        G.lap_device(M)
+    assert e.value.status == G.GOAT_EINVAL
+    M = torch.as_tensor(_scores("uniform", 300, 5), device="cuda")
+    with pytest.raises(G.GoatError) as e:
+        G.lap_device(M, max_rounds=4)
+    assert e.value.status == G.GOAT_ENOTSUP
+    # the library is usable after the refusal
+    _check(G, _scores("uniform", 300, 5))
+
+
+def test_solve_with_device_assignment(G):
+    g = I.rho_sbm_pair([100, 100, 100], [[0.2, 0.01, 0.01], [0.01, 0.1, 0.01], [0.01, 0.01, 0.2]], 0.9, 9300)
+    A = torch.as_tensor(g.A, device="cuda")
+    B = torch.as_tensor(g.B, device="cuda")
+    r1 = G.solve(A, B, return_P=True, lap=1)
+    r0 = G.solve(A, B, lap=0)
+    assert r1.stats.lap_device == 1 and r0.stats.lap_device == 0
+    P = r1.P.cpu().numpy().astype(np.float64)
+    c, _ = O.quantised_scores(P)
+    _, best = O.lap_quantised(P)
+    assert int(c[np.arange(300), r1.perm].sum()) == best
+    # both projections score the same on P up to the quantisation bound
+    _, s = O.quantised_scores(P)
+    v1 = P[np.arange(300), r1.perm].sum()
+    v0 = P[np.arange(300), r0.perm].sum()
+    assert abs(v1 - v0) <= 300 * 2.0 ** -s
+    print(f"match ratio device {O.match_ratio(r1.perm, g.truth):.4f}, host {O.match_ratio(r0.perm, g.truth):.4f}, "
+          f"assignment ms device {r1.stats.ms_lap:.1f}, host {r0.stats.ms_lap:.1f}")
+
+
+def test_lap_device_planted_full_size(G):
+    n = 10000
+    gen = torch.Generator(device="cuda").manual_seed(12)
+    M = torch.rand((n, n), generator=gen, device="cuda") * (1e-3 / n)
+    truth = torch.randperm(n, generator=gen, device="cuda")
+    M[torch.arange(n, device="cuda"), truth] += 0.9
+    perm, st = G.lap_device(M)
+    assert torch.equal(perm.long(), truth)
+    print(f"n=10000 planted: rounds {st.rounds}, phases {st.phases}")
