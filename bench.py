@@ -67,12 +67,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_form(goat, A, B, n, form, warmup, steps, sk_max, sk_tol, prof_stride, mlp=None):
+def run_form(goat, A, B, n, form, warmup, steps, sk_max, sk_tol, prof_stride, mlp=None, lap=1):
     import torch
     prec = "fp32" if form == "plain" else "bf16x3"
     warm = 0 if form == "plain" else 3
     run = goat.Run(A, B, prec=prec, warm=warm, stop_on_stall=0, sk_max=sk_max, sk_tol=sk_tol,
-                   mlp_params=None if form == "plain" else mlp)
+                   mlp_params=None if form == "plain" else mlp, lap=lap)
     run.steps(warmup)
     log(f"{form}: warmup {warmup} done")
     goat.profile_enable(goat.PROF_SINKHORN_ROW, prof_stride)
@@ -87,7 +87,8 @@ def run_form(goat, A, B, n, form, warmup, steps, sk_max, sk_tol, prof_stride, ml
     goat.profile_enable(goat.PROF_SINKHORN_ROW, 0)
     goat.profile_enable(goat.PROF_GEMM, 0)
     assert done == steps
-    log(f"{form}: timed {steps} steps in {t1 - t0:.2f} s; final assignment on the host ...")
+    log(f"{form}: timed {steps} steps in {t1 - t0:.2f} s; final assignment on the "
+        f"{'device' if lap else 'host'} ...")
     res = run.finish()
     run.close()
     hist = res.history[warmup:]
@@ -103,7 +104,7 @@ def run_form(goat, A, B, n, form, warmup, steps, sk_max, sk_tol, prof_stride, ml
         gemm_exec_tflops=gemm_exec_flops / (2 * gm_ms / max(gm_cnt, 1) * 1e-3) / 1e12 if gm_cnt else None,
         gemm_alg_tflops=4.0 * float(n) ** 3 / (2 * gm_ms / max(gm_cnt, 1) * 1e-3) / 1e12 if gm_cnt else None,
         perm=res.perm, t_hist=[round(h["t"], 6) for h in hist], f_final=res.stats.f_final,
-        score=res.stats.score, lap_ms=res.stats.ms_lap,
+        score=res.stats.score, lap_ms=res.stats.ms_lap, lap_device=res.stats.lap_device,
     )
     log(f"{form}: {out['fw_iters_per_s']:.3f} FW it/s, {out['ms_per_step']:.1f} ms/step, "
         f"sk iters mean {out['sk_iters_mean']:.1f}, row sweep {out['sk_row_ms']*1e3:.1f} us, "
@@ -152,6 +153,7 @@ def main():
     ap.add_argument("--prof-stride", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--json-out", default=None)
+    ap.add_argument("--host-lap", action="store_true", help="final assignment on the host instead of the device")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
@@ -183,7 +185,7 @@ def main():
     forms = {}
     for form in args.forms.split(","):
         forms[form] = run_form(goat, A, B, n, form, args.warmup, args.steps, args.sk_max, args.sk_tol,
-                               args.prof_stride, mlp)
+                               args.prof_stride, mlp, lap=0 if args.host_lap else 1)
         forms[form]["match_ratio"] = float(np.mean(forms[form]["perm"] == pair.truth))
         log(f"{form}: match ratio {forms[form]['match_ratio']:.4f}")
     main_form = forms.get("mixed") or next(iter(forms.values()))

@@ -283,7 +283,10 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
 /*
  * goat_lap_device - the same projection on the device for a device float
  * matrix M (n x n, leading dimension ld): Bertsekas' auction with epsilon
- * scaling, Jacobi form, on integer scores. With 2^(e-1) <= max|M| < 2^e,
+ * scaling on integer scores. Unassigned rows bid in parallel rounds; when
+ * few are left, or a batch of rounds assigns few rows, one workgroup takes
+ * the bids in sequence; each phase keeps the pairs that stay optimal to
+ * within the new epsilon. With 2^(e-1) <= max|M| < 2^e,
  * R = min(24, 38 - ceil(log2(n+1))) and s = R - 1 - e, the scores are
  * c_ij = rint(M_ij * 2^s) - min_kl rint(M_kl * 2^s) (round half to even;
  * 0 <= c <= 2^R), and perm maximises sum_i c[i][perm i] exactly; on M
@@ -291,7 +294,8 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
  * row, so the result is deterministic. All-equal c gives the identity.
  *  perm_dev   device int32[n] (row i -> column perm_dev[i]).
  *  ws         device workspace of goat_lap_device_workspace_size(n) bytes.
- *  max_rounds cap on bidding rounds summed over phases (<= 0: 4,000,000).
+ *  max_rounds cap on parallel rounds plus tail bids over all phases
+ *             (<= 0: 20,000,000).
  *  stats      host goat_lap_stats (may be NULL).
  * Host-synchronous on `stream` (it polls a device counter between batches
  * of rounds).
@@ -301,8 +305,9 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
  * goat_lap_max, has neither limit).
  */
 typedef struct goat_lap_stats {
-    long long rounds;           /* bidding rounds that ran (all phases)     */
-    long long rounds_launched;  /* rounds enqueued, including idle ones     */
+    long long rounds;           /* parallel bidding rounds that ran         */
+    long long rounds_launched;  /* parallel rounds enqueued + sequential budgets */
+    long long tail_bids;        /* bids taken in sequence                   */
     int phases;                 /* epsilon phases                           */
     int shift;                  /* s above                                  */
     int resolution_bits;        /* R above                                  */

@@ -363,7 +363,7 @@ int goat_lap_device(int n, const float* M, int ld, int32_t* perm_dev, void* ws, 
     GOAT_CHECK_ARG(n >= 1, "n < 1");
     GOAT_CHECK_ARG(ld >= n, "leading dimension < n");
     GOAT_CHECK_ARG(M && perm_dev && ws, "null pointer");
-    return auction_lap(n, M, ld, perm_dev, ws, ws_bytes, max_rounds > 0 ? max_rounds : 4000000ll, stats,
+    return auction_lap(n, M, ld, perm_dev, ws, ws_bytes, max_rounds > 0 ? max_rounds : 20000000ll, stats,
                        static_cast<hipStream_t>(stream));
 }
 

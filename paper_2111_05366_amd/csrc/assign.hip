@@ -13,7 +13,10 @@
 #include "common.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 namespace goat {
@@ -144,8 +147,10 @@ int launch_nominate(int rows, int cols, const float* P, int ldp, int k, int32_t*
 // ---------------------------------------------------------------- device assignment
 //
 // Final projection of Alg. 3 on the device: a permutation maximising
-// sum_i M[i, perm i], solved by Bertsekas' auction with epsilon scaling in
-// its Jacobi form (every unassigned row bids in the same round).
+// sum_i M[i, perm i], solved by Bertsekas' auction with epsilon scaling:
+// parallel (Jacobi) rounds in which every unassigned row bids, and
+// sequential (Gauss-Seidel) bids in one workgroup when rounds assign few
+// rows.
 //
 // Scores are first mapped to integers: with 2^(e-1) <= max|M| < 2^e and
 // s = R - 1 - e, q_ij = rint(M_ij 2^s) (round half to even; the scaling by
@@ -154,7 +159,7 @@ int launch_nominate(int rows, int cols, const float* P, int ldp, int k, int32_t*
 // unit leaves the assignment within n / (n + 1) < 1 of the optimum of c,
 // hence optimal for c. R = min(24, 38 - ceil(log2(n + 1))) keeps every
 // scaled cost below 2^38; a phase raises no price by more than the cost
-// range plus epsilon, so over the ~14 phases a bid stays below 2^43 and
+// range plus epsilon, so over the ~12 phases a bid stays below 2^43 and
 // packs with its row (20 bits, lowest row wins equal bids) into one 64-bit
 // atomicMax word. A bid past 2^43 is reported, not wrapped.
 // Everything is integer once c is formed, so the result does not depend on
@@ -176,7 +181,8 @@ struct AuctionArgs {
     unsigned long long* slot;
     int32_t* owner;              // row holding object j, or -1
     int32_t* assign;             // object held by row i, or -1
-    int* ctl;                    // [0] rows assigned, [1] bid overflow, [2] rounds bid
+    int* ctl;                    // [0] rows assigned, [1] bid overflow, [2] parallel rounds,
+                                 // [3] sequential bids
 };
 
 __device__ inline long long auc_value(const AuctionArgs& a, float m, int j) {
@@ -213,58 +219,75 @@ __device__ inline void auc_merge(long long& v1, int& j1, long long& v2, long lon
 __global__ __launch_bounds__(AB) void auction_bid_kernel(AuctionArgs a, long long eps) {
     __shared__ long long sv1[AB / 64], sv2[AB / 64];
     __shared__ int sj1[AB / 64];
+    __shared__ int rows[AB];
+    __shared__ int cnt;
     if (a.ctl[0] == a.n) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.ctl[2], 1);
     const int t = threadIdx.x;
-    for (int i = blockIdx.x; i < a.n; i += gridDim.x) {
-        if (a.assign[i] >= 0) continue;
-        const float* r = a.M + (long)i * a.ld;
-        long long v1 = LLONG_MIN, v2 = LLONG_MIN;
-        int j1 = INT_MAX;
-        int j0 = 0;
-        if (a.vec4) {
-            const int c4 = a.n >> 2;
-            const float4* r4 = reinterpret_cast<const float4*>(r);
+    // this block's rows are blockIdx.x + k * gridDim.x; their assignment
+    // flags are read in one parallel load, AB rows at a time (order within
+    // the list does not matter: every bid of a round sees the same prices)
+    const int per = (a.n - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
+    for (int base = 0; base < per; base += AB) {
+        if (t == 0) cnt = 0;
+        __syncthreads();
+        const int k = base + t;
+        if (k < per) {
+            const int i = (int)blockIdx.x + k * (int)gridDim.x;
+            if (a.assign[i] < 0) rows[atomicAdd(&cnt, 1)] = i;
+        }
+        __syncthreads();
+        const int m = cnt;
+        for (int u = 0; u < m; ++u) {
+            const int i = rows[u];
+            const float* r = a.M + (long)i * a.ld;
+            long long v1 = LLONG_MIN, v2 = LLONG_MIN;
+            int j1 = INT_MAX;
+            int j0 = 0;
+            if (a.vec4) {
+                const int c4 = a.n >> 2;
+                const float4* r4 = reinterpret_cast<const float4*>(r);
 #pragma unroll 2
-            for (int q = t; q < c4; q += AB) {
-                const float4 x = r4[q];
-                const int j = 4 * q;
-                auc_push(v1, j1, v2, auc_value(a, x.x, j), j);
-                auc_push(v1, j1, v2, auc_value(a, x.y, j + 1), j + 1);
-                auc_push(v1, j1, v2, auc_value(a, x.z, j + 2), j + 2);
-                auc_push(v1, j1, v2, auc_value(a, x.w, j + 3), j + 3);
+                for (int q = t; q < c4; q += AB) {
+                    const float4 x = r4[q];
+                    const int j = 4 * q;
+                    auc_push(v1, j1, v2, auc_value(a, x.x, j), j);
+                    auc_push(v1, j1, v2, auc_value(a, x.y, j + 1), j + 1);
+                    auc_push(v1, j1, v2, auc_value(a, x.z, j + 2), j + 2);
+                    auc_push(v1, j1, v2, auc_value(a, x.w, j + 3), j + 3);
+                }
+                j0 = c4 << 2;
             }
-            j0 = c4 << 2;
-        }
-        for (int j = j0 + t; j < a.n; j += AB) auc_push(v1, j1, v2, auc_value(a, r[j], j), j);
-        // merge (best, column, second best) over the wave, then the waves
+            for (int j = j0 + t; j < a.n; j += AB) auc_push(v1, j1, v2, auc_value(a, r[j], j), j);
+            // merge (best, column, second best) over the wave, then the waves
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const long long ov1 = __shfl_xor(v1, o, 64);
-            const long long ov2 = __shfl_xor(v2, o, 64);
-            const int oj1 = __shfl_xor(j1, o, 64);
-            auc_merge(v1, j1, v2, ov1, oj1, ov2);
-        }
-        if ((t & 63) == 0) {
-            sv1[t >> 6] = v1;
-            sv2[t >> 6] = v2;
-            sj1[t >> 6] = j1;
-        }
-        __syncthreads();
-        if (t == 0) {
-#pragma unroll
-            for (int w = 1; w < AB / 64; ++w) auc_merge(v1, j1, v2, sv1[w], sj1[w], sv2[w]);
-            // n >= 2, so both values are real: bid = price + (v1 - v2) + eps
-            const long long bid = a.price[j1] + (v1 - v2) + eps;
-            if (bid >= kBidLimit) {
-                atomicOr(&a.ctl[1], 1);
-            } else {
-                const unsigned long long w =
-                    ((unsigned long long)bid << kRowBits) | (kRowMask - (unsigned long long)i);
-                atomicMax(&a.slot[j1], w);
+            for (int o = 32; o > 0; o >>= 1) {
+                const long long ov1 = __shfl_xor(v1, o, 64);
+                const long long ov2 = __shfl_xor(v2, o, 64);
+                const int oj1 = __shfl_xor(j1, o, 64);
+                auc_merge(v1, j1, v2, ov1, oj1, ov2);
             }
+            if ((t & 63) == 0) {
+                sv1[t >> 6] = v1;
+                sv2[t >> 6] = v2;
+                sj1[t >> 6] = j1;
+            }
+            __syncthreads();
+            if (t == 0) {
+#pragma unroll
+                for (int w = 1; w < AB / 64; ++w) auc_merge(v1, j1, v2, sv1[w], sj1[w], sv2[w]);
+                // n >= 2, so both values are real: bid = price + (v1 - v2) + eps
+                const long long bid = a.price[j1] + (v1 - v2) + eps;
+                if (bid >= kBidLimit) {
+                    atomicOr(&a.ctl[1], 1);
+                } else {
+                    const unsigned long long w =
+                        ((unsigned long long)bid << kRowBits) | (kRowMask - (unsigned long long)i);
+                    atomicMax(&a.slot[j1], w);
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -287,20 +310,168 @@ __global__ __launch_bounds__(AB) void auction_resolve_kernel(AuctionArgs a) {
         atomicAdd(&a.ctl[0], 1);
 }
 
-__global__ __launch_bounds__(AB) void auction_reset_kernel(AuctionArgs a, int first) {
+// Phase start without a full restart: a row keeps its object when the pair
+// still satisfies eps-complementary slackness for the new, smaller eps
+// (its value is within eps of the row's best); later price rises only make
+// other objects worse, so kept pairs stay valid. Other rows are released.
+// ctl[0] counts the kept rows (the reset before this kernel zeroed it).
+__global__ __launch_bounds__(AB) void auction_keep_kernel(AuctionArgs a, long long eps) {
+    __shared__ long long sv[AB / 64];
+    const int t = threadIdx.x;
+    for (int i = blockIdx.x; i < a.n; i += gridDim.x) {
+        const int ja = a.assign[i];
+        if (ja < 0) continue;
+        const float* r = a.M + (long)i * a.ld;
+        long long v1 = LLONG_MIN;
+        for (int j = t; j < a.n; j += AB) {
+            const long long v = auc_value(a, r[j], j);
+            v1 = v > v1 ? v : v1;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const long long ov = __shfl_xor(v1, o, 64);
+            v1 = ov > v1 ? ov : v1;
+        }
+        if ((t & 63) == 0) sv[t >> 6] = v1;
+        __syncthreads();
+        if (t == 0) {
+            for (int w = 1; w < AB / 64; ++w) v1 = sv[w] > v1 ? sv[w] : v1;
+            const long long va = auc_value(a, r[ja], ja);
+            if (v1 - va > eps) {
+                a.assign[i] = -1;
+                a.owner[ja] = -1;
+            } else {
+                atomicAdd(&a.ctl[0], 1);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// mode 0: everything (prices to zero); 1: assignments released, prices
+// kept; 2: only the assigned-row count (before auction_keep_kernel)
+__global__ __launch_bounds__(AB) void auction_reset_kernel(AuctionArgs a, int mode) {
     const int j = blockIdx.x * AB + threadIdx.x;
     if (j == 0) {
         a.ctl[0] = 0;
-        if (first) {
+        if (mode == 0) {
             a.ctl[1] = 0;
             a.ctl[2] = 0;
+            a.ctl[3] = 0;
         }
     }
-    if (j >= a.n) return;
+    if (j >= a.n || mode == 2) return;
     a.owner[j] = -1;
     a.assign[j] = -1;
     a.slot[j] = 0;
-    if (first) a.price[j] = 0;
+    if (mode == 0) a.price[j] = 0;
+}
+
+// Sequential bidding: when parallel rounds assign few rows each (the tail
+// of a phase, or rows that all want the same objects), one 1024-thread
+// workgroup takes the bids one after the other (the Gauss-Seidel auction)
+// inside one launch instead of two launches per round. The unassigned rows
+// form a queue in global memory (capacity n), built in increasing row
+// order; an evicted row takes its evictor's place at the head. At most
+// `budget` bids per launch, so every launch ends.
+constexpr int TB = 1024;
+
+__global__ __launch_bounds__(TB) void auction_tail_kernel(AuctionArgs a, int* __restrict__ q, long long eps,
+                                                         long long budget) {
+    __shared__ int qn;
+    __shared__ int wcnt[TB / 64];
+    __shared__ long long sv1[TB / 64], sv2[TB / 64];
+    __shared__ int sj1[TB / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) qn = 0;
+    __syncthreads();
+    for (int base = 0; base < a.n; base += TB) {
+        const int i = base + t;
+        const bool un = i < a.n && a.assign[i] < 0;
+        const unsigned long long m = __ballot(un);
+        if (lane == 0) wcnt[w] = __popcll(m);
+        __syncthreads();
+        int off = qn;
+        for (int u = 0; u < w; ++u) off += wcnt[u];
+        off += __popcll(m & ((1ull << lane) - 1ull));
+        if (un) q[off] = i;
+        __syncthreads();
+        if (t == 0) {
+            int tot = 0;
+            for (int u = 0; u < TB / 64; ++u) tot += wcnt[u];
+            qn += tot;
+        }
+        __syncthreads();
+    }
+    __shared__ int cur;
+    if (t == 0 && qn > 0) cur = q[0];
+    __syncthreads();
+    long long done = 0;
+    while (qn > 0 && done < budget) {
+        const int i = cur;
+        const float* r = a.M + (long)i * a.ld;
+        long long v1 = LLONG_MIN, v2 = LLONG_MIN;
+        int j1 = INT_MAX;
+        int j0 = 0;
+        if (a.vec4) {
+            const int c4 = a.n >> 2;
+            const float4* r4 = reinterpret_cast<const float4*>(r);
+            for (int k = t; k < c4; k += TB) {
+                const float4 x = r4[k];
+                const int j = 4 * k;
+                auc_push(v1, j1, v2, auc_value(a, x.x, j), j);
+                auc_push(v1, j1, v2, auc_value(a, x.y, j + 1), j + 1);
+                auc_push(v1, j1, v2, auc_value(a, x.z, j + 2), j + 2);
+                auc_push(v1, j1, v2, auc_value(a, x.w, j + 3), j + 3);
+            }
+            j0 = c4 << 2;
+        }
+        for (int j = j0 + t; j < a.n; j += TB) auc_push(v1, j1, v2, auc_value(a, r[j], j), j);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const long long ov1 = __shfl_xor(v1, o, 64);
+            const long long ov2 = __shfl_xor(v2, o, 64);
+            const int oj1 = __shfl_xor(j1, o, 64);
+            auc_merge(v1, j1, v2, ov1, oj1, ov2);
+        }
+        if (lane == 0) {
+            sv1[w] = v1;
+            sv2[w] = v2;
+            sj1[w] = j1;
+        }
+        __syncthreads();
+        if (t == 0) {
+            for (int u = 1; u < TB / 64; ++u) auc_merge(v1, j1, v2, sv1[u], sj1[u], sv2[u]);
+            // both loads issue before either is used
+            const long long pj = a.price[j1];
+            const int old = a.owner[j1];
+            const long long bid = pj + (v1 - v2) + eps;
+            if (bid >= kBidLimit) {
+                atomicOr(&a.ctl[1], 1);
+                qn = 0;
+            } else {
+                a.owner[j1] = i;
+                a.assign[i] = j1;
+                a.price[j1] = bid;
+                if (old >= 0) {
+                    a.assign[old] = -1;
+                    q[0] = old;
+                    cur = old;
+                } else {
+                    a.ctl[0] += 1;
+                    const int last = q[qn - 1];
+                    q[0] = last;
+                    cur = last;
+                    qn -= 1;
+                }
+            }
+        }
+        ++done;
+        // thread 0's stores to price, owner and assign are seen by the whole
+        // workgroup after the barrier
+        __syncthreads();
+    }
+    if (t == 0) a.ctl[3] += (int)done;
 }
 
 // per block: max |x|, min x, and a flag for non-finite entries
@@ -342,6 +513,29 @@ __global__ __launch_bounds__(AB) void auction_range_kernel(int n, const float* _
 }
 
 constexpr int kRangeWG = 512;
+constexpr long long kTailBudget = 262144;     // bids per tail launch
+
+// Tuning: GOAT_LAP_TAIL (unassigned rows that switch a phase to sequential
+// bids, default 32), GOAT_LAP_RATE (a batch of parallel rounds that assigns
+// fewer rows than this per round also switches, default 2), GOAT_LAP_THETA
+// (epsilon divisor between phases, default 10), GOAT_LAP_KEEP (0: every
+// phase restarts from no assignment; default 1 keeps the pairs that stay
+// eps-optimal), GOAT_LAP_TRACE=1 (per-phase counts on stderr).
+struct LapKnobs {
+    int tail = 32, theta = 10, trace = 0, keep = 1, rate = 2;
+};
+const LapKnobs& lap_knobs() {
+    static const LapKnobs k = [] {
+        LapKnobs r;
+        if (const char* e = std::getenv("GOAT_LAP_TAIL")) r.tail = std::max(0, std::atoi(e));
+        if (const char* e = std::getenv("GOAT_LAP_RATE")) r.rate = std::max(0, std::atoi(e));
+        if (const char* e = std::getenv("GOAT_LAP_THETA")) r.theta = std::max(2, std::atoi(e));
+        if (const char* e = std::getenv("GOAT_LAP_TRACE")) r.trace = std::atoi(e);
+        if (const char* e = std::getenv("GOAT_LAP_KEEP")) r.keep = std::atoi(e) != 0;
+        return r;
+    }();
+    return k;
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -349,7 +543,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t auction_ws_bytes(int n) {
     if (n < 1) return 0;
-    return align256((size_t)n * 8) * 2 + align256((size_t)n * 4) * 2 + 256 + align256(kRangeWG * 3 * 4);
+    return align256((size_t)n * 8) * 2 + align256((size_t)n * 4) * 3 + 256 + align256(kRangeWG * 3 * 4);
 }
 
 int auction_resolution_bits(int n) {
@@ -384,6 +578,8 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     base += align256((size_t)n * 4);
     a.assign = reinterpret_cast<int32_t*>(base);
     base += align256((size_t)n * 4);
+    int* queue = reinterpret_cast<int*>(base);
+    base += align256((size_t)n * 4);
     a.ctl = reinterpret_cast<int*>(base);
     base += 256;
     float* part = reinterpret_cast<float*>(base);
@@ -414,7 +610,7 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     loc.resolution_bits = R;
 
     const int gr = (n + AB - 1) / AB;
-    hipLaunchKernelGGL(auction_reset_kernel, dim3(gr), dim3(AB), 0, s, a, 1);
+    hipLaunchKernelGGL(auction_reset_kernel, dim3(gr), dim3(AB), 0, s, a, 0);
     GOAT_HIP(hipGetLastError());
     if (n == 1 || cmax == 0) {
         // one vertex, or all scores equal after quantisation: the identity
@@ -430,40 +626,76 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     const int gb = std::min(n, 2048);
     const long long cbig = cmax * a.np1;
     long long eps = std::max(1ll, cbig / 4);
-    int ctl[3] = {0, 0, 0};
-    long long rounds = 0;
+    int ctl[4] = {0, 0, 0, 0};
+    long long work = 0;          // parallel rounds launched + tail bids allowed
+    const LapKnobs& kn = lap_knobs();
+    const int kTailRows = kn.tail;
+    int prev_rounds = 0, prev_tail = 0;
+    auto tp = std::chrono::steady_clock::now();
     for (;;) {
         ++loc.phases;
+        int left = n;
         if (loc.phases > 1) {
-            hipLaunchKernelGGL(auction_reset_kernel, dim3(gr), dim3(AB), 0, s, a, 0);
+            hipLaunchKernelGGL(auction_reset_kernel, dim3(gr), dim3(AB), 0, s, a, kn.keep ? 2 : 1);
+            if (kn.keep) hipLaunchKernelGGL(auction_keep_kernel, dim3(gb), dim3(AB), 0, s, a, eps);
             GOAT_HIP(hipGetLastError());
+            if (kn.keep) {
+                GOAT_HIP(hipMemcpyAsync(ctl, a.ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
+                GOAT_HIP(hipStreamSynchronize(s));
+                left = n - ctl[0];
+            }
         }
         int batch = 4;
-        for (;;) {
-            for (int k = 0; k < batch; ++k) {
-                hipLaunchKernelGGL(auction_bid_kernel, dim3(gb), dim3(AB), 0, s, a, eps);
-                hipLaunchKernelGGL(auction_resolve_kernel, dim3(gr), dim3(AB), 0, s, a);
+        bool seq = false;
+        while (left > 0) {
+            const bool sequential = seq || left <= kTailRows;
+            if (sequential) {
+                const long long budget = std::min(kTailBudget, std::max(1ll, max_rounds - work));
+                hipLaunchKernelGGL(auction_tail_kernel, dim3(1), dim3(TB), 0, s, a, queue, eps, budget);
+                work += budget;
+            } else {
+                for (int k = 0; k < batch; ++k) {
+                    hipLaunchKernelGGL(auction_bid_kernel, dim3(gb), dim3(AB), 0, s, a, eps);
+                    hipLaunchKernelGGL(auction_resolve_kernel, dim3(gr), dim3(AB), 0, s, a);
+                }
+                work += batch;
             }
             GOAT_HIP(hipGetLastError());
-            rounds += batch;
             GOAT_HIP(hipMemcpyAsync(ctl, a.ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
             GOAT_HIP(hipStreamSynchronize(s));
             if (ctl[1]) {
                 set_error("goat_lap_device: bid overflow");
                 return GOAT_ENOTSUP;
             }
-            if (ctl[0] == n) break;
-            if (rounds >= max_rounds) {
+            const int now_left = n - ctl[0];
+            if (!sequential) {
+                // rows that collide on the same objects: bid one by one
+                if ((long long)(left - now_left) < (long long)kn.rate * batch) seq = true;
+                batch = std::min(batch * 2, 64);
+                if (now_left <= 4 * kTailRows) batch = 4;
+            }
+            left = now_left;
+            if (left == 0) break;
+            if (work >= max_rounds) {
                 set_error("goat_lap_device: round limit reached");
                 return GOAT_ENOTSUP;
             }
-            batch = std::min(batch * 2, 64);
+        }
+        if (kn.trace) {
+            const auto now = std::chrono::steady_clock::now();
+            std::fprintf(stderr, "[lap] phase %d eps %lld: rounds %d, tail bids %d, %.2f ms\n", loc.phases, eps,
+                         ctl[2] - prev_rounds, ctl[3] - prev_tail,
+                         std::chrono::duration<double, std::milli>(now - tp).count());
+            tp = now;
+            prev_rounds = ctl[2];
+            prev_tail = ctl[3];
         }
         if (eps == 1) break;
-        eps = std::max(1ll, eps / 6);
+        eps = std::max(1ll, eps / kn.theta);
     }
     loc.rounds = ctl[2];
-    loc.rounds_launched = rounds;
+    loc.tail_bids = ctl[3];
+    loc.rounds_launched = work;
     GOAT_HIP(hipMemcpyAsync(perm_dev, a.assign, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
     GOAT_HIP(hipStreamSynchronize(s));
     if (st) *st = loc;

@@ -288,7 +288,7 @@ int goat_run_finish(goat_run* h, int32_t* perm_host, goat_stats* stats_host, flo
     bool on_device = false;
     if (r.opt.lap == 1 && auction_ws_bytes(n) <= (size_t)np * np * 4) {
         // the direction buffer Q is free once the loop has ended
-        int rc = auction_lap(n, src, np, p.perm_dev, p.Q, (size_t)np * np * 4, 4000000ll, nullptr, r.s);
+        int rc = auction_lap(n, src, np, p.perm_dev, p.Q, (size_t)np * np * 4, 20000000ll, nullptr, r.s);
         if (rc == GOAT_OK) {
             on_device = true;
             GOAT_HIP(hipMemcpyAsync(perm_host, p.perm_dev, (size_t)n * 4, hipMemcpyDeviceToHost, r.s));

@@ -75,7 +75,7 @@ def _check(G, M, ld=None):
 def test_lap_device_parity(G, kind, n, ld):
     print(f"lap_device {kind} n={n} ld={ld}", flush=True)
     _, st = _check(G, _scores(kind, n, 31 * n + len(kind)), ld)
-    print(f"  rounds {st.rounds} (launched {st.rounds_launched}), phases {st.phases}", flush=True)
+    print(f"  rounds {st.rounds}, tail bids {st.tail_bids}, phases {st.phases}", flush=True)
 
 
 def test_lap_device_degenerate(G):
@@ -129,4 +129,4 @@ def test_lap_device_planted_full_size(G):
     M[torch.arange(n, device="cuda"), truth] += 0.9
     perm, st = G.lap_device(M)
     assert torch.equal(perm.long(), truth)
-    print(f"n=10000 planted: rounds {st.rounds}, phases {st.phases}")
+    print(f"n=10000 planted: rounds {st.rounds}, tail bids {st.tail_bids}, phases {st.phases}")
