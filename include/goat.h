@@ -287,7 +287,7 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
  * few are left, or a batch of rounds assigns few rows, one workgroup takes
  * the bids in sequence; each phase keeps the pairs that stay optimal to
  * within the new epsilon. With 2^(e-1) <= max|M| < 2^e,
- * R = min(24, 38 - ceil(log2(n+1))) and s = R - 1 - e, the scores are
+ * R = min(40, 55 - ceil(log2(n+1))) and s = R - 1 - e, the scores are
  * c_ij = rint(M_ij * 2^s) - min_kl rint(M_kl * 2^s) (round half to even;
  * 0 <= c <= 2^R), and perm maximises sum_i c[i][perm i] exactly; on M
  * itself it is within n * 2^-s of the optimum. Equal bids go to the lowest
@@ -301,7 +301,7 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
  * of rounds).
  * Status: GOAT_EINVAL for n < 1, n >= 2^20 - 1, ld < n, null pointers or a
  * non-finite entry; GOAT_ENOMEM for a short workspace; GOAT_ENOTSUP when
- * the round cap is reached or a bid would exceed 2^43 (the host solver,
+ * the round cap is reached or a bid would exceed 2^62 (the host solver,
  * goat_lap_max, has neither limit).
  */
 typedef struct goat_lap_stats {

@@ -530,8 +530,8 @@ def nominate(P, k: int) -> np.ndarray:
 
 def lap_resolution_bits(n: int) -> int:
     """READING (device assignment): the integer scores of the final
-    assignment carry R = min(24, 38 - ceil(log2(n + 1))) bits."""
-    return min(24, 38 - int(math.ceil(math.log2(n + 1))))
+    assignment carry R = min(40, 55 - ceil(log2(n + 1))) bits."""
+    return min(40, 55 - int(math.ceil(math.log2(n + 1))))
 
 
 def quantised_scores(M) -> tuple[np.ndarray, int]:

@@ -154,31 +154,38 @@ int launch_nominate(int rows, int cols, const float* P, int ldp, int k, int32_t*
 //
 // Scores are first mapped to integers: with 2^(e-1) <= max|M| < 2^e and
 // s = R - 1 - e, q_ij = rint(M_ij 2^s) (round half to even; the scaling by
-// 2^s is exact) and c_ij = q_ij - min q, so 0 <= c_ij <= 2^R. Prices and
-// bids live in units of 1 / (n + 1) of c: a final phase with epsilon = 1
-// unit leaves the assignment within n / (n + 1) < 1 of the optimum of c,
-// hence optimal for c. R = min(24, 38 - ceil(log2(n + 1))) keeps every
-// scaled cost below 2^38; a phase raises no price by more than the cost
-// range plus epsilon, so over the ~12 phases a bid stays below 2^43 and
-// packs with its row (20 bits, lowest row wins equal bids) into one 64-bit
-// atomicMax word. A bid past 2^43 is reported, not wrapped.
-// Everything is integer once c is formed, so the result does not depend on
-// the order in which threads run.
+// 2^s is exact, and so is the conversion: a float of magnitude >= 2^24 is an
+// integer) and c_ij = q_ij - min q, so 0 <= c_ij <= 2^R. Prices and bids are
+// int64 in units of 1 / (n + 1) of c: a final phase with epsilon = 1 unit
+// leaves the assignment within n / (n + 1) < 1 of the optimum of c, hence
+// optimal for c. R = min(40, 55 - ceil(log2(n + 1))) keeps every scaled cost
+// below 2^55; a phase raises no price by more than the cost range plus
+// epsilon, so over the ~33 phases (epsilon divided by 3 each time) prices
+// stay below the 2^62 guard (a bid past it is reported, not wrapped).
+//
+// A parallel round: each bidding row records (bid, object) and takes the
+// object's atomicMax; a claim pass lets the lowest row among those whose bid
+// equals the maximum take the object (atomicMin); the resolve pass hands
+// each claimed object over. Everything is integer once c is formed, so the
+// result does not depend on the order in which threads run.
 
 namespace {
 
 constexpr int AB = 256;             // threads per block
-constexpr int kRowBits = 20;
-constexpr unsigned long long kRowMask = (1ull << kRowBits) - 1;
-constexpr long long kBidLimit = 1ll << 43;
+constexpr long long kBidLimit = 1ll << 62;
+constexpr int kNoRow = 0x7fffffff;
 
 struct AuctionArgs {
     const float* M;
     long ld;
-    int n, s, qmin, vec4;
+    int n, s, vec4, pad;
+    long long qmin;              // min_ij rint(M_ij 2^s)
     long long np1;               // n + 1
-    long long* price;
-    unsigned long long* slot;
+    long long* price;            // per object
+    long long* best;             // per object: highest bid of the round (0: none)
+    int32_t* win;                // per object: lowest row with that bid
+    long long* mybid;            // per row: its bid of the round
+    int32_t* tgt;                // per row: the object it bid for, or -1
     int32_t* owner;              // row holding object j, or -1
     int32_t* assign;             // object held by row i, or -1
     int* ctl;                    // [0] rows assigned, [1] bid overflow, [2] parallel rounds,
@@ -186,8 +193,8 @@ struct AuctionArgs {
 };
 
 __device__ inline long long auc_value(const AuctionArgs& a, float m, int j) {
-    const int q = (int)rintf(ldexpf(m, a.s));
-    return (long long)(q - a.qmin) * a.np1 - a.price[j];
+    const long long q = (long long)rintf(ldexpf(m, a.s));
+    return (q - a.qmin) * a.np1 - a.price[j];
 }
 
 // (v, j) ranks before (w, k): larger value, or equal and smaller column
@@ -205,7 +212,6 @@ __device__ inline void auc_push(long long& v1, int& j1, long long& v2, long long
     }
 }
 
-// one workgroup per bidding row: rows b, b + grid, ... of the unassigned set
 __device__ inline void auc_merge(long long& v1, int& j1, long long& v2, long long ov1, int oj1, long long ov2) {
     if (auc_better(ov1, oj1, v1, j1)) {
         v2 = v1 > ov2 ? v1 : ov2;
@@ -216,6 +222,55 @@ __device__ inline void auc_merge(long long& v1, int& j1, long long& v2, long lon
     }
 }
 
+// Best and second-best value of row i over all columns, reduced over the
+// block (NT threads); the result is valid in thread 0.
+template <int NT>
+__device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, int& j1, long long& v2,
+                                    long long* sv1, long long* sv2, int* sj1) {
+    const int t = threadIdx.x;
+    const float* r = a.M + (long)i * a.ld;
+    v1 = LLONG_MIN;
+    v2 = LLONG_MIN;
+    j1 = INT_MAX;
+    int j0 = 0;
+    if (a.vec4) {
+        const int c4 = a.n >> 2;
+        const float4* r4 = reinterpret_cast<const float4*>(r);
+#pragma unroll 2
+        for (int q = t; q < c4; q += NT) {
+            const float4 x = r4[q];
+            const int j = 4 * q;
+            auc_push(v1, j1, v2, auc_value(a, x.x, j), j);
+            auc_push(v1, j1, v2, auc_value(a, x.y, j + 1), j + 1);
+            auc_push(v1, j1, v2, auc_value(a, x.z, j + 2), j + 2);
+            auc_push(v1, j1, v2, auc_value(a, x.w, j + 3), j + 3);
+        }
+        j0 = c4 << 2;
+    }
+    for (int j = j0 + t; j < a.n; j += NT) auc_push(v1, j1, v2, auc_value(a, r[j], j), j);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long ov1 = __shfl_xor(v1, o, 64);
+        const long long ov2 = __shfl_xor(v2, o, 64);
+        const int oj1 = __shfl_xor(j1, o, 64);
+        auc_merge(v1, j1, v2, ov1, oj1, ov2);
+    }
+    if ((t & 63) == 0) {
+        sv1[t >> 6] = v1;
+        sv2[t >> 6] = v2;
+        sj1[t >> 6] = j1;
+    }
+    __syncthreads();
+    if (t == 0) {
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) auc_merge(v1, j1, v2, sv1[w], sj1[w], sv2[w]);
+    }
+}
+
+// Parallel bids: one workgroup per bidding row; this block's rows are
+// blockIdx.x + k * gridDim.x, their assignment flags read in one parallel
+// load, AB rows at a time (order within the list does not matter: every bid
+// of a round sees the same prices).
 __global__ __launch_bounds__(AB) void auction_bid_kernel(AuctionArgs a, long long eps) {
     __shared__ long long sv1[AB / 64], sv2[AB / 64];
     __shared__ int sj1[AB / 64];
@@ -224,9 +279,6 @@ __global__ __launch_bounds__(AB) void auction_bid_kernel(AuctionArgs a, long lon
     if (a.ctl[0] == a.n) return;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.ctl[2], 1);
     const int t = threadIdx.x;
-    // this block's rows are blockIdx.x + k * gridDim.x; their assignment
-    // flags are read in one parallel load, AB rows at a time (order within
-    // the list does not matter: every bid of a round sees the same prices)
     const int per = (a.n - (int)blockIdx.x + (int)gridDim.x - 1) / (int)gridDim.x;
     for (int base = 0; base < per; base += AB) {
         if (t == 0) cnt = 0;
@@ -240,50 +292,18 @@ __global__ __launch_bounds__(AB) void auction_bid_kernel(AuctionArgs a, long lon
         const int m = cnt;
         for (int u = 0; u < m; ++u) {
             const int i = rows[u];
-            const float* r = a.M + (long)i * a.ld;
-            long long v1 = LLONG_MIN, v2 = LLONG_MIN;
-            int j1 = INT_MAX;
-            int j0 = 0;
-            if (a.vec4) {
-                const int c4 = a.n >> 2;
-                const float4* r4 = reinterpret_cast<const float4*>(r);
-#pragma unroll 2
-                for (int q = t; q < c4; q += AB) {
-                    const float4 x = r4[q];
-                    const int j = 4 * q;
-                    auc_push(v1, j1, v2, auc_value(a, x.x, j), j);
-                    auc_push(v1, j1, v2, auc_value(a, x.y, j + 1), j + 1);
-                    auc_push(v1, j1, v2, auc_value(a, x.z, j + 2), j + 2);
-                    auc_push(v1, j1, v2, auc_value(a, x.w, j + 3), j + 3);
-                }
-                j0 = c4 << 2;
-            }
-            for (int j = j0 + t; j < a.n; j += AB) auc_push(v1, j1, v2, auc_value(a, r[j], j), j);
-            // merge (best, column, second best) over the wave, then the waves
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const long long ov1 = __shfl_xor(v1, o, 64);
-                const long long ov2 = __shfl_xor(v2, o, 64);
-                const int oj1 = __shfl_xor(j1, o, 64);
-                auc_merge(v1, j1, v2, ov1, oj1, ov2);
-            }
-            if ((t & 63) == 0) {
-                sv1[t >> 6] = v1;
-                sv2[t >> 6] = v2;
-                sj1[t >> 6] = j1;
-            }
-            __syncthreads();
+            long long v1, v2;
+            int j1;
+            auc_scan_row<AB>(a, i, v1, j1, v2, sv1, sv2, sj1);
             if (t == 0) {
-#pragma unroll
-                for (int w = 1; w < AB / 64; ++w) auc_merge(v1, j1, v2, sv1[w], sj1[w], sv2[w]);
                 // n >= 2, so both values are real: bid = price + (v1 - v2) + eps
                 const long long bid = a.price[j1] + (v1 - v2) + eps;
                 if (bid >= kBidLimit) {
                     atomicOr(&a.ctl[1], 1);
                 } else {
-                    const unsigned long long w =
-                        ((unsigned long long)bid << kRowBits) | (kRowMask - (unsigned long long)i);
-                    atomicMax(&a.slot[j1], w);
+                    a.mybid[i] = bid;
+                    a.tgt[i] = j1;
+                    atomicMax(&a.best[j1], bid);
                 }
             }
             __syncthreads();
@@ -291,17 +311,27 @@ __global__ __launch_bounds__(AB) void auction_bid_kernel(AuctionArgs a, long lon
     }
 }
 
+// Among the rows whose bid equals their object's maximum, the lowest wins.
+__global__ __launch_bounds__(AB) void auction_claim_kernel(AuctionArgs a) {
+    const int i = blockIdx.x * AB + threadIdx.x;
+    if (i >= a.n) return;
+    const int j = a.tgt[i];
+    if (j < 0) return;
+    a.tgt[i] = -1;
+    if (a.mybid[i] == a.best[j]) atomicMin(&a.win[j], i);
+}
+
 __global__ __launch_bounds__(AB) void auction_resolve_kernel(AuctionArgs a) {
     const int j = blockIdx.x * AB + threadIdx.x;
     if (j >= a.n) return;
-    const unsigned long long w = a.slot[j];
-    if (w == 0) return;
-    a.slot[j] = 0;
-    const int i = (int)(kRowMask - (w & kRowMask));
+    const int i = a.win[j];
+    if (i == kNoRow) return;
+    a.win[j] = kNoRow;
+    a.price[j] = a.best[j];
+    a.best[j] = 0;
     const int old = a.owner[j];
     a.owner[j] = i;
     a.assign[i] = j;
-    a.price[j] = (long long)(w >> kRowBits);
     // the previous owner was assigned at the start of the round, so it made
     // no bid and no other object writes its entry
     if (old >= 0)
@@ -360,25 +390,30 @@ __global__ __launch_bounds__(AB) void auction_reset_kernel(AuctionArgs a, int mo
             a.ctl[3] = 0;
         }
     }
-    if (j >= a.n || mode == 2) return;
+    if (j >= a.n) return;
+    if (mode == 0) {
+        a.price[j] = 0;
+        a.best[j] = 0;
+        a.win[j] = kNoRow;
+        a.tgt[j] = -1;
+    }
+    if (mode == 2) return;
     a.owner[j] = -1;
     a.assign[j] = -1;
-    a.slot[j] = 0;
-    if (mode == 0) a.price[j] = 0;
 }
 
 // Sequential bidding: when parallel rounds assign few rows each (the tail
 // of a phase, or rows that all want the same objects), one 1024-thread
 // workgroup takes the bids one after the other (the Gauss-Seidel auction)
-// inside one launch instead of two launches per round. The unassigned rows
-// form a queue in global memory (capacity n), built in increasing row
+// inside one launch instead of three launches per round. The unassigned
+// rows form a queue in global memory (capacity n), built in increasing row
 // order; an evicted row takes its evictor's place at the head. At most
 // `budget` bids per launch, so every launch ends.
 constexpr int TB = 1024;
 
-__global__ __launch_bounds__(TB) void auction_tail_kernel(AuctionArgs a, int* __restrict__ q, long long eps,
-                                                         long long budget) {
-    __shared__ int qn;
+__global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs a, int* __restrict__ q, long long eps,
+                                                        long long budget) {
+    __shared__ int qn, cur;
     __shared__ int wcnt[TB / 64];
     __shared__ long long sv1[TB / 64], sv2[TB / 64];
     __shared__ int sj1[TB / 64];
@@ -403,45 +438,15 @@ __global__ __launch_bounds__(TB) void auction_tail_kernel(AuctionArgs a, int* __
         }
         __syncthreads();
     }
-    __shared__ int cur;
     if (t == 0 && qn > 0) cur = q[0];
     __syncthreads();
     long long done = 0;
     while (qn > 0 && done < budget) {
         const int i = cur;
-        const float* r = a.M + (long)i * a.ld;
-        long long v1 = LLONG_MIN, v2 = LLONG_MIN;
-        int j1 = INT_MAX;
-        int j0 = 0;
-        if (a.vec4) {
-            const int c4 = a.n >> 2;
-            const float4* r4 = reinterpret_cast<const float4*>(r);
-            for (int k = t; k < c4; k += TB) {
-                const float4 x = r4[k];
-                const int j = 4 * k;
-                auc_push(v1, j1, v2, auc_value(a, x.x, j), j);
-                auc_push(v1, j1, v2, auc_value(a, x.y, j + 1), j + 1);
-                auc_push(v1, j1, v2, auc_value(a, x.z, j + 2), j + 2);
-                auc_push(v1, j1, v2, auc_value(a, x.w, j + 3), j + 3);
-            }
-            j0 = c4 << 2;
-        }
-        for (int j = j0 + t; j < a.n; j += TB) auc_push(v1, j1, v2, auc_value(a, r[j], j), j);
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const long long ov1 = __shfl_xor(v1, o, 64);
-            const long long ov2 = __shfl_xor(v2, o, 64);
-            const int oj1 = __shfl_xor(j1, o, 64);
-            auc_merge(v1, j1, v2, ov1, oj1, ov2);
-        }
-        if (lane == 0) {
-            sv1[w] = v1;
-            sv2[w] = v2;
-            sj1[w] = j1;
-        }
-        __syncthreads();
+        long long v1, v2;
+        int j1;
+        auc_scan_row<TB>(a, i, v1, j1, v2, sv1, sv2, sj1);
         if (t == 0) {
-            for (int u = 1; u < TB / 64; ++u) auc_merge(v1, j1, v2, sv1[u], sj1[u], sv2[u]);
             // both loads issue before either is used
             const long long pj = a.price[j1];
             const int old = a.owner[j1];
@@ -513,16 +518,19 @@ __global__ __launch_bounds__(AB) void auction_range_kernel(int n, const float* _
 }
 
 constexpr int kRangeWG = 512;
-constexpr long long kTailBudget = 262144;     // bids per tail launch
+constexpr long long kSeqBudget = 262144;      // bids per sequential launch
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Tuning: GOAT_LAP_TAIL (unassigned rows that switch a phase to sequential
 // bids, default 32), GOAT_LAP_RATE (a batch of parallel rounds that assigns
 // fewer rows than this per round also switches, default 2), GOAT_LAP_THETA
-// (epsilon divisor between phases, default 10), GOAT_LAP_KEEP (0: every
+// (epsilon divisor between phases, default 3), GOAT_LAP_KEEP (0: every
 // phase restarts from no assignment; default 1 keeps the pairs that stay
-// eps-optimal), GOAT_LAP_TRACE=1 (per-phase counts on stderr).
+// eps-optimal), GOAT_LAP_BITS (score resolution R, default and maximum 40),
+// GOAT_LAP_TRACE=1 (per-phase counts on stderr).
 struct LapKnobs {
-    int tail = 32, theta = 10, trace = 0, keep = 1, rate = 2;
+    int tail = 32, theta = 3, trace = 0, keep = 1, rate = 2;
 };
 const LapKnobs& lap_knobs() {
     static const LapKnobs k = [] {
@@ -537,25 +545,25 @@ const LapKnobs& lap_knobs() {
     return k;
 }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
 }  // namespace
 
 size_t auction_ws_bytes(int n) {
     if (n < 1) return 0;
-    return align256((size_t)n * 8) * 2 + align256((size_t)n * 4) * 3 + 256 + align256(kRangeWG * 3 * 4);
+    return align256((size_t)n * 8) * 3 + align256((size_t)n * 4) * 5 + 256 + align256(kRangeWG * 3 * 4);
 }
 
 int auction_resolution_bits(int n) {
     int b = 0;
     while ((1ll << b) < (long long)n + 1) ++b;   // ceil(log2(n + 1))
-    return std::min(24, 38 - b);
+    int r = 40;
+    if (const char* e = std::getenv("GOAT_LAP_BITS")) r = std::max(8, std::min(40, std::atoi(e)));
+    return std::min(r, 55 - b);
 }
 
 int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size_t ws_bytes, long long max_rounds,
                 AuctionStats* st, hipStream_t s) {
     AuctionStats loc{};
-    if (n >= (1 << kRowBits) - 1) {
+    if (n >= (1 << 20) - 1) {
         set_error("goat_lap_device: n too large");
         return GOAT_EINVAL;
     }
@@ -564,25 +572,27 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
         return GOAT_ENOMEM;
     }
     char* base = static_cast<char*>(ws);
+    auto take = [&](size_t bytes) {
+        char* p = base;
+        base += align256(bytes);
+        return p;
+    };
     AuctionArgs a{};
     a.M = M;
     a.ld = ld;
     a.n = n;
     a.np1 = (long long)n + 1;
     a.vec4 = (ld % 4) == 0 && (reinterpret_cast<uintptr_t>(M) % 16) == 0;
-    a.price = reinterpret_cast<long long*>(base);
-    base += align256((size_t)n * 8);
-    a.slot = reinterpret_cast<unsigned long long*>(base);
-    base += align256((size_t)n * 8);
-    a.owner = reinterpret_cast<int32_t*>(base);
-    base += align256((size_t)n * 4);
-    a.assign = reinterpret_cast<int32_t*>(base);
-    base += align256((size_t)n * 4);
-    int* queue = reinterpret_cast<int*>(base);
-    base += align256((size_t)n * 4);
-    a.ctl = reinterpret_cast<int*>(base);
-    base += 256;
-    float* part = reinterpret_cast<float*>(base);
+    a.price = reinterpret_cast<long long*>(take((size_t)n * 8));
+    a.best = reinterpret_cast<long long*>(take((size_t)n * 8));
+    a.mybid = reinterpret_cast<long long*>(take((size_t)n * 8));
+    a.win = reinterpret_cast<int32_t*>(take((size_t)n * 4));
+    a.tgt = reinterpret_cast<int32_t*>(take((size_t)n * 4));
+    a.owner = reinterpret_cast<int32_t*>(take((size_t)n * 4));
+    a.assign = reinterpret_cast<int32_t*>(take((size_t)n * 4));
+    int* queue = reinterpret_cast<int*>(take((size_t)n * 4));
+    a.ctl = reinterpret_cast<int*>(take(256));
+    float* part = reinterpret_cast<float*>(take(kRangeWG * 3 * 4));
 
     // score range: the quantisation's shift and offset
     const int nb = std::min(n, kRangeWG);
@@ -604,8 +614,9 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     int e = 0;
     if (mx > 0.0f) std::frexp(mx, &e);
     a.s = R - 1 - e;
-    a.qmin = (int)std::nearbyint(std::ldexp(mn, a.s));   // rint is monotone: min q = q(min M)
-    const long long cmax = (long long)std::nearbyint(std::ldexp(mx, a.s)) - a.qmin;
+    // rint is monotone, so min q = q(min M); both are exact in double
+    a.qmin = (long long)std::nearbyint(std::ldexp((double)mn, a.s));
+    const long long cmax = (long long)std::nearbyint(std::ldexp((double)mx, a.s)) - a.qmin;
     loc.shift = a.s;
     loc.resolution_bits = R;
 
@@ -627,10 +638,9 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     const long long cbig = cmax * a.np1;
     long long eps = std::max(1ll, cbig / 4);
     int ctl[4] = {0, 0, 0, 0};
-    long long work = 0;          // parallel rounds launched + tail bids allowed
+    long long work = 0;          // parallel rounds launched + sequential budgets
     const LapKnobs& kn = lap_knobs();
-    const int kTailRows = kn.tail;
-    int prev_rounds = 0, prev_tail = 0;
+    int prev_rounds = 0, prev_seq = 0;
     auto tp = std::chrono::steady_clock::now();
     for (;;) {
         ++loc.phases;
@@ -648,14 +658,15 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
         int batch = 4;
         bool seq = false;
         while (left > 0) {
-            const bool sequential = seq || left <= kTailRows;
+            const bool sequential = seq || left <= kn.tail;
             if (sequential) {
-                const long long budget = std::min(kTailBudget, std::max(1ll, max_rounds - work));
-                hipLaunchKernelGGL(auction_tail_kernel, dim3(1), dim3(TB), 0, s, a, queue, eps, budget);
+                const long long budget = std::min(kSeqBudget, std::max(1ll, max_rounds - work));
+                hipLaunchKernelGGL(auction_seq_kernel, dim3(1), dim3(TB), 0, s, a, queue, eps, budget);
                 work += budget;
             } else {
                 for (int k = 0; k < batch; ++k) {
                     hipLaunchKernelGGL(auction_bid_kernel, dim3(gb), dim3(AB), 0, s, a, eps);
+                    hipLaunchKernelGGL(auction_claim_kernel, dim3(gr), dim3(AB), 0, s, a);
                     hipLaunchKernelGGL(auction_resolve_kernel, dim3(gr), dim3(AB), 0, s, a);
                 }
                 work += batch;
@@ -672,7 +683,7 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
                 // rows that collide on the same objects: bid one by one
                 if ((long long)(left - now_left) < (long long)kn.rate * batch) seq = true;
                 batch = std::min(batch * 2, 64);
-                if (now_left <= 4 * kTailRows) batch = 4;
+                if (now_left <= 4 * kn.tail) batch = 4;
             }
             left = now_left;
             if (left == 0) break;
@@ -683,12 +694,12 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
         }
         if (kn.trace) {
             const auto now = std::chrono::steady_clock::now();
-            std::fprintf(stderr, "[lap] phase %d eps %lld: rounds %d, tail bids %d, %.2f ms\n", loc.phases, eps,
-                         ctl[2] - prev_rounds, ctl[3] - prev_tail,
+            std::fprintf(stderr, "[lap] phase %d eps %lld: rounds %d, sequential bids %d, %.2f ms\n", loc.phases, eps,
+                         ctl[2] - prev_rounds, ctl[3] - prev_seq,
                          std::chrono::duration<double, std::milli>(now - tp).count());
             tp = now;
             prev_rounds = ctl[2];
-            prev_tail = ctl[3];
+            prev_seq = ctl[3];
         }
         if (eps == 1) break;
         eps = std::max(1ll, eps / kn.theta);

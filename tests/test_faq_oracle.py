@@ -121,7 +121,7 @@ def test_quantised_scores_exact_on_dyadic_input():
     M = rng.integers(-1000, 1000, size=(n, n)).astype(np.float64) / 1024.0
     c, s = O.quantised_scores(M)
     R = O.lap_resolution_bits(n)
-    assert R == min(24, 38 - 6)
+    assert R == min(40, 55 - 6)
     mx = np.abs(M).max()
     assert 2.0 ** (R - 2) <= mx * 2.0 ** s < 2.0 ** (R - 1)
     assert np.array_equal(c, (M * 2.0 ** s - M.min() * 2.0 ** s).astype(np.int64))
