@@ -192,9 +192,13 @@ struct AuctionArgs {
                                  // [3] sequential bids
 };
 
-__device__ inline long long auc_value(const AuctionArgs& a, float m, int j) {
+__device__ inline long long auc_cost(const AuctionArgs& a, float m) {
     const long long q = (long long)rintf(ldexpf(m, a.s));
-    return (q - a.qmin) * a.np1 - a.price[j];
+    return (q - a.qmin) * a.np1;
+}
+
+__device__ inline long long auc_value(const AuctionArgs& a, float m, int j) {
+    return auc_cost(a, m) - a.price[j];
 }
 
 // (v, j) ranks before (w, k): larger value, or equal and smaller column
@@ -202,14 +206,14 @@ __device__ inline bool auc_better(long long v, int j, long long w, int k) {
     return v > w || (v == w && j < k);
 }
 
+// Columns reach a thread in increasing order, so a value equal to the
+// current best never displaces it; selects, no branches.
 __device__ inline void auc_push(long long& v1, int& j1, long long& v2, long long v, int j) {
-    if (auc_better(v, j, v1, j1)) {
-        v2 = v1;
-        v1 = v;
-        j1 = j;
-    } else if (v > v2) {
-        v2 = v;
-    }
+    const bool top = v > v1;
+    const long long lo = top ? v1 : v;
+    v2 = lo > v2 ? lo : v2;
+    v1 = top ? v : v1;
+    j1 = top ? j : j1;
 }
 
 __device__ inline void auc_merge(long long& v1, int& j1, long long& v2, long long ov1, int oj1, long long ov2) {
@@ -223,10 +227,13 @@ __device__ inline void auc_merge(long long& v1, int& j1, long long& v2, long lon
 }
 
 // Best and second-best value of row i over all columns, reduced over the
-// block (NT threads); the result is valid in thread 0.
+// block (NT threads); the result is valid in thread 0. On the aligned path
+// a thread issues the loads of up to four float4 chunks of the row and of
+// their prices before it uses any of them.
 template <int NT>
 __device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, int& j1, long long& v2,
                                     long long* sv1, long long* sv2, int* sj1) {
+    constexpr int U = 4;
     const int t = threadIdx.x;
     const float* r = a.M + (long)i * a.ld;
     v1 = LLONG_MIN;
@@ -236,14 +243,30 @@ __device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, 
     if (a.vec4) {
         const int c4 = a.n >> 2;
         const float4* r4 = reinterpret_cast<const float4*>(r);
-#pragma unroll 2
-        for (int q = t; q < c4; q += NT) {
-            const float4 x = r4[q];
-            const int j = 4 * q;
-            auc_push(v1, j1, v2, auc_value(a, x.x, j), j);
-            auc_push(v1, j1, v2, auc_value(a, x.y, j + 1), j + 1);
-            auc_push(v1, j1, v2, auc_value(a, x.z, j + 2), j + 2);
-            auc_push(v1, j1, v2, auc_value(a, x.w, j + 3), j + 3);
+        const longlong2* p2 = reinterpret_cast<const longlong2*>(a.price);
+        for (int q0 = t; q0 < c4; q0 += NT * U) {
+            float4 x[U];
+            longlong2 pa[U], pb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * NT;
+                if (q < c4) {
+                    x[u] = r4[q];
+                    pa[u] = p2[2 * q];
+                    pb[u] = p2[2 * q + 1];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * NT;
+                if (q < c4) {
+                    const int j = 4 * q;
+                    auc_push(v1, j1, v2, auc_cost(a, x[u].x) - pa[u].x, j);
+                    auc_push(v1, j1, v2, auc_cost(a, x[u].y) - pa[u].y, j + 1);
+                    auc_push(v1, j1, v2, auc_cost(a, x[u].z) - pb[u].x, j + 2);
+                    auc_push(v1, j1, v2, auc_cost(a, x[u].w) - pb[u].y, j + 3);
+                }
+            }
         }
         j0 = c4 << 2;
     }
