@@ -232,6 +232,9 @@ int auction_resolution_bits(int n);
 int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size_t ws_bytes, long long max_rounds,
                 AuctionStats* st, hipStream_t s);
 
+// compute units of the current device, cached per device (sinkhorn.hip)
+int cu_count();
+
 // per-row top-k columns of a score matrix, best first (assign.hip)
 int launch_nominate(int rows, int cols, const float* P, int ldp, int k, int32_t* idx, float* val,
                     hipStream_t s);

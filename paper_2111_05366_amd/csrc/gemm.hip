@@ -7,9 +7,12 @@
 // multiple of the k-tile, so the main loop has no bounds checks.
 //
 // Block tile 128 x 128, four waves in a 2 x 2 arrangement, each wave a
-// 64 x 64 sub-tile made of 2 x 2 MFMA 32x32 blocks. Double-buffered LDS
-// stages with register-staged global loads (one barrier per k-tile).
+// 64 x 64 sub-tile made of 2 x 2 MFMA 32x32 blocks (fp32 and fp8 products;
+// bf16 products use the 256 x 256 eight-wave tile below when the shape is a
+// multiple of it). Double-buffered LDS stages with register-staged global
+// loads (one barrier per k-tile).
 #include <cstdlib>
+#include <cstring>
 
 #include "common.h"
 
@@ -35,6 +38,7 @@ struct GemmParams {
     uint16_t* Clo;
     int ld_split;
     int tiles_m, tiles_n;
+    int m_off;                   // first output row of this launch
 };
 
 // Block -> tile map. Consecutive block ids go to different XCDs (round
@@ -93,7 +97,7 @@ __global__ __launch_bounds__(256) void gemm_nt_bf16_kernel(GemmParams p) {
     const int wm = wave >> 1, wn = wave & 1;
     int tm, tn;
     tile_of(p, tm, tn);
-    const int m0 = tm * BM, n0 = tn * BN;
+    const int m0 = p.m_off + tm * BM, n0 = tn * BN;
     const int ktiles = p.K / BK16;
     const int total = ktiles * p.nseg;
 
@@ -189,7 +193,7 @@ __global__ __launch_bounds__(256) void gemm_nt_fp8_kernel(GemmParams p) {
     const int wm = wave >> 1, wn = wave & 1;
     int tm, tn;
     tile_of(p, tm, tn);
-    const int m0 = tm * BM, n0 = tn * BN;
+    const int m0 = p.m_off + tm * BM, n0 = tn * BN;
     const int ktiles = p.K / BK8;
     const int total = ktiles * p.nseg;
     const int zexp = fp8_split_exponent(*p.zmax);
@@ -313,7 +317,7 @@ void gemm_nt_bf16_256_kernel(GemmParams p) {
     const int wm = wave >> 1, wn = wave & 1;
     int tm, tn;
     tile_of(p, tm, tn);
-    const int m0 = tm * BM2, n0 = tn * BN2;
+    const int m0 = p.m_off + tm * BM2, n0 = tn * BN2;
     const int ktiles = p.K / BK2;
     const int total = ktiles * p.nseg;
 
@@ -395,6 +399,118 @@ void gemm_nt_bf16_256_kernel(GemmParams p) {
     store_tile_256<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
+// 256 x 256 tile on eight waves (2 x 4), 128 x 64 per wave: per 16-wide
+// k-step a wave reads six 16-byte fragments for eight MFMAs (43.7 flops per
+// LDS byte against 32.8 for the 64 x 64 wave tile), and 128 accumulator
+// registers leave room for two waves per SIMD. k-tile 64, two LDS stages of
+// 72 KB; each thread stages four 16-byte chunks per operand.
+constexpr int BM3 = 256, BN3 = 256, BK3 = 64, LD3 = BK3 + 8;
+constexpr size_t kLdsW8 = (size_t)2 * 2 * BM3 * LD3 * sizeof(uint16_t);
+
+template <int OUT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void gemm_nt_bf16_w8_kernel(GemmParams p) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t smem16w[];
+    uint16_t* sA = smem16w;                      // [2][BM3 * LD3]
+    uint16_t* sB = smem16w + 2 * BM3 * LD3;      // [2][BN3 * LD3]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;
+    int tm, tn;
+    tile_of(p, tm, tn);
+    const int m0 = p.m_off + tm * BM3, n0 = tn * BN3;
+    const int ktiles = p.K / BK3;
+    const int total = ktiles * p.nseg;
+
+    f32x16 acc[4][2];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
+
+    // chunk q of a thread: row tid / 8 + 64 q, bf16 columns (tid % 8) * 8 .. + 7
+    uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
+    const int lrow = tid >> 3, lkc = (tid & 7) * 8;
+#define GOAT_GLOADW8(T)                                                                           \
+    do {                                                                                          \
+        const int seg_ = (T) / ktiles, kt_ = (T) - seg_ * ktiles;                                 \
+        const uint16_t* X_ = static_cast<const uint16_t*>(p.X[seg_]) +                            \
+                             (size_t)(m0 + lrow) * p.ldx + kt_ * BK3 + lkc;                      \
+        const uint16_t* Z_ = static_cast<const uint16_t*>(p.Z[seg_]) +                            \
+                             (size_t)(n0 + lrow) * p.ldz + kt_ * BK3 + lkc;                      \
+        const size_t sx_ = (size_t)64 * p.ldx, sz_ = (size_t)64 * p.ldz;                          \
+        ra0 = *reinterpret_cast<const uint4*>(X_);                                                \
+        ra1 = *reinterpret_cast<const uint4*>(X_ + sx_);                                          \
+        ra2 = *reinterpret_cast<const uint4*>(X_ + 2 * sx_);                                      \
+        ra3 = *reinterpret_cast<const uint4*>(X_ + 3 * sx_);                                      \
+        rb0 = *reinterpret_cast<const uint4*>(Z_);                                                \
+        rb1 = *reinterpret_cast<const uint4*>(Z_ + sz_);                                          \
+        rb2 = *reinterpret_cast<const uint4*>(Z_ + 2 * sz_);                                      \
+        rb3 = *reinterpret_cast<const uint4*>(Z_ + 3 * sz_);                                      \
+    } while (0)
+#define GOAT_SSTOREW8(BUF)                                                                        \
+    do {                                                                                          \
+        uint16_t* a_ = sA + (BUF) * BM3 * LD3 + lrow * LD3 + lkc;                                 \
+        uint16_t* b_ = sB + (BUF) * BN3 * LD3 + lrow * LD3 + lkc;                                 \
+        *reinterpret_cast<uint4*>(a_) = ra0;                                                      \
+        *reinterpret_cast<uint4*>(a_ + 64 * LD3) = ra1;                                           \
+        *reinterpret_cast<uint4*>(a_ + 128 * LD3) = ra2;                                          \
+        *reinterpret_cast<uint4*>(a_ + 192 * LD3) = ra3;                                          \
+        *reinterpret_cast<uint4*>(b_) = rb0;                                                      \
+        *reinterpret_cast<uint4*>(b_ + 64 * LD3) = rb1;                                           \
+        *reinterpret_cast<uint4*>(b_ + 128 * LD3) = rb2;                                          \
+        *reinterpret_cast<uint4*>(b_ + 192 * LD3) = rb3;                                          \
+    } while (0)
+
+    GOAT_GLOADW8(0);
+    GOAT_SSTOREW8(0);
+    __syncthreads();
+    const int arow = (wm * 128 + (lane & 31)) * LD3 + (lane >> 5) * 8;
+    const int brow = (wn * 64 + (lane & 31)) * LD3 + (lane >> 5) * 8;
+    for (int t = 0; t < total; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < total) GOAT_GLOADW8(t + 1);
+        const uint16_t* sa = sA + buf * BM3 * LD3;
+        const uint16_t* sb = sB + buf * BN3 * LD3;
+#pragma unroll
+        for (int ks = 0; ks < BK3 / 16; ++ks) {
+            bf16x8 a[4], b[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(sa + arow + i * 32 * LD3 + ks * 16);
+#pragma unroll
+            for (int i = 0; i < 2; ++i) b[i] = *reinterpret_cast<const bf16x8*>(sb + brow + i * 32 * LD3 + ks * 16);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
+        }
+        if (t + 1 < total) GOAT_SSTOREW8(buf ^ 1);
+        __syncthreads();
+    }
+#undef GOAT_GLOADW8
+#undef GOAT_SSTOREW8
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * 128 + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn * 64 + ni * 32 + (lane & 31);
+                const float x = p.alpha * acc[mi][ni][r];
+                if (OUT == OUT_F32) {
+                    if (row < p.m_valid && col < p.n_valid) p.C[(size_t)row * p.ldc + col] = x;
+                } else {
+                    const uint16_t h = f32_to_bf16_rne(x);
+                    const size_t idx = (size_t)row * p.ld_split + col;
+                    p.Chi[idx] = h;
+                    p.Clo[idx] = f32_to_bf16_rne(x - bf16_to_f32(h));
+                }
+            }
+}
+
 // ------------------------------------------------------------------ fp32
 
 constexpr int BK32 = 16;                 // k-tile (float elements)
@@ -411,7 +527,7 @@ __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmParams p) {
     const int wm = wave >> 1, wn = wave & 1;
     int tm, tn;
     tile_of(p, tm, tn);
-    const int m0 = tm * BM, n0 = tn * BN;
+    const int m0 = p.m_off + tm * BM, n0 = tn * BN;
     const int ktiles = p.K / BK32;
     const int total = ktiles * p.nseg;
 
@@ -492,21 +608,30 @@ __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmParams p) {
     store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
-// bf16 products use the 128 x 128 tile: the 256 x 256 tile measured slower
-// at n = 10,000 (782 against 957 TFLOP/s executed; one wave per SIMD leaves
-// its LDS and global latencies exposed). GOAT_GEMM_TILE=256 selects it (a
-// measurement knob).
-bool use_tile256(int M, int N, int K) {
-    static const bool want256 = [] {
+// bf16 products use the 256 x 256 tile on eight waves when the shape allows
+// (1034 against 951 TFLOP/s executed for the 128 x 128 tile at n = 10,000;
+// the 256 x 256 tile on four waves: 782, one wave per SIMD leaves its LDS and
+// global latencies exposed). GOAT_GEMM_TILE = 128 or 256 selects the others
+// (a measurement knob).
+int tile_choice(int M, int N, int K) {
+    // 0: 128 x 128, 1: 256 x 256 on four waves, 2: 256 x 256 on eight waves
+    static const int want = [] {
         const char* e = getenv("GOAT_GEMM_TILE");
-        return e && e[0] == '2' && e[1] == '5' && e[2] == '6';
+        if (e && std::strcmp(e, "128") == 0) return 0;
+        if (e && std::strcmp(e, "256") == 0) return 1;
+        return 2;
     }();
+    if (want == 0 || M % 256 || N % 256 || K % 64) return 0;
     static const bool lds_ok =
         hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_256_kernel<OUT_F32>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds256) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_256_kernel<OUT_BF16_SPLIT>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds256) == hipSuccess;
-    return want256 && lds_ok && M % BM2 == 0 && N % BN2 == 0 && K % BK2 == 0;
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLds256) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_w8_kernel<OUT_F32>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsW8) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_w8_kernel<OUT_BF16_SPLIT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsW8) == hipSuccess;
+    return lds_ok ? want : 0;
 }
 
 }  // namespace
@@ -543,16 +668,45 @@ int launch_gemm_nt(int kind, int M, int N, int K, int ldx, int ldz, const GemmSe
     p.Chi = C_hi;
     p.Clo = C_lo;
     p.ld_split = ld_split;
-    const bool big = is_bf16 && use_tile256(M, N, K);
-    p.tiles_m = M / (big ? BM2 : BM);
-    p.tiles_n = N / (big ? BN2 : BN);
-    dim3 grid(p.tiles_m * p.tiles_n), block(256);
+    int tile = is_bf16 ? tile_choice(M, N, K) : 0;
+    // Eight-wave tiles run one block per compute unit. Whole tile-rows that
+    // fill complete rounds go to them; the rows of a last, partial round go
+    // to a second launch of the 128 x 128 kernel (four times as many
+    // blocks); a product with fewer 256-tiles than compute units runs on
+    // 128 x 128 tiles only.
+    int rows_big = M;
+    if (tile == 2) {
+        const int tm2 = M / BM3, tn2 = N / BN3, cus = cu_count();
+        const int nb = tm2 * tn2;
+        if (nb < cus) {
+            tile = 0;
+        } else if (nb % cus != 0) {
+            rows_big = (nb / cus * cus) / tn2 * BM3;
+            if (rows_big == 0) tile = 0;
+        }
+    }
+    p.m_off = 0;
+    p.tiles_m = (tile ? rows_big : M) / (tile ? BM2 : BM);
+    p.tiles_n = N / (tile ? BN2 : BN);
+    dim3 grid(p.tiles_m * p.tiles_n), block(tile == 2 ? 512 : 256);
     prof_begin(1, s);
+    if (tile == 2 && rows_big < M) {
+        GemmParams q = p;
+        q.m_off = rows_big;
+        q.tiles_m = (M - rows_big) / BM;
+        q.tiles_n = N / BN;
+        const dim3 g2(q.tiles_m * q.tiles_n), b2(256);
+        if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_F32>, g2, b2, 0, s, q);
+        else hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_BF16_SPLIT>, g2, b2, 0, s, q);
+    }
     if (is_fp8) {
         hipLaunchKernelGGL(gemm_nt_fp8_kernel<OUT_F32>, grid, block, 0, s, p);
-    } else if (big) {
+    } else if (tile == 1) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_256_kernel<OUT_F32>, grid, block, kLds256, s, p);
         else hipLaunchKernelGGL(gemm_nt_bf16_256_kernel<OUT_BF16_SPLIT>, grid, block, kLds256, s, p);
+    } else if (tile == 2) {
+        if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_w8_kernel<OUT_F32>, grid, block, kLdsW8, s, p);
+        else hipLaunchKernelGGL(gemm_nt_bf16_w8_kernel<OUT_BF16_SPLIT>, grid, block, kLdsW8, s, p);
     } else if (is_bf16) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_F32>, grid, block, 0, s, p);
         else hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_BF16_SPLIT>, grid, block, 0, s, p);

@@ -39,6 +39,21 @@
 #include "common.h"
 
 namespace goat {
+
+// Compute units of the current device (cached per device).
+int cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
 namespace {
 
 constexpr float kLog2e = 1.4426950408889634f;
@@ -486,18 +501,6 @@ struct Geometry {
 // both (a measurement knob).
 constexpr int kSkSmallWG = 512;
 
-int cu_count() {
-    static int cached[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (cached[dev] == 0) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            cus = 256;
-        cached[dev] = cus;
-    }
-    return cached[dev];
-}
 
 Geometry geometry(int n) {
     int env_T = 0, env_W = 0;
