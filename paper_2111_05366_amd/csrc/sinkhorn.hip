@@ -299,12 +299,16 @@ void sk_row_kernel(SkArgs a) {
 // block, n/32 blocks. With check, the largest row-marginal error of the
 // sweep decides convergence first (no update then).
 __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int check) {
-    if (a.ctrl->done) return;
     __shared__ float4 part[32][8];
     __shared__ float red[4];
     const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
-    // the partial loads are issued before the convergence check so that the
-    // two memory round trips overlap
+    // Every load of the kernel is issued before the first one is used: the
+    // stop flag, the control scalars, the column partials, the strips'
+    // error partials and (threads that write columns) the potentials, so
+    // the kernel waits for one memory round trip instead of four. Loads made
+    // after convergence are read and discarded.
+    const int done = a.ctrl->done;
+    const float tol = a.ctrl->tol, h = a.ctrl->h;
     const int cq = tid & 7, sl = tid >> 3;
     const int j4 = blockIdx.x * 8 + cq;
     const bool ok = 4 * j4 < a.n;
@@ -318,14 +322,25 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
             acc.x += t.x; acc.y += t.y; acc.z += t.z; acc.w += t.w;
         }
     }
-    if (check) {
-        float m = 0.0f;
+    float m = 0.0f;
+    if (check)
         for (int w = tid; w < W; w += 256) m = fmaxf(m, a.errpart[w]);
+    // potentials of this thread's four columns (np-sized arrays, so the
+    // vector loads stay in bounds past n)
+    float4 vg4 = make_float4(0.f, 0.f, 0.f, 0.f), vs4 = vg4, ung4 = vg4, uns4 = vg4;
+    if (sl == 0 && ok) {
+        vg4 = reinterpret_cast<const float4*>(a.vg)[j4];
+        vs4 = reinterpret_cast<const float4*>(a.vs)[j4];
+        ung4 = reinterpret_cast<const float4*>(a.ung)[j4];
+        uns4 = reinterpret_cast<const float4*>(a.uns)[j4];
+    }
+    if (done) return;
+    if (check) {
         m = wave_max(m);
         if (lane == 0) red[q] = m;
         __syncthreads();
         const float err = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-        if (err <= a.ctrl->tol) {
+        if (err <= tol) {
             if (blockIdx.x == 0 && tid == 0) {
                 a.ctrl->err = err;
                 a.ctrl->done = 1;
@@ -344,17 +359,21 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
             c.x += t.x; c.y += t.y; c.z += t.z; c.w += t.w;
         }
         const float cc[4] = {c.x, c.y, c.z, c.w};
-        const float h = a.ctrl->h, inv_h = 1.0f / h;
+        const float vgv[4] = {vg4.x, vg4.y, vg4.z, vg4.w};
+        const float vsv[4] = {vs4.x, vs4.y, vs4.z, vs4.w};
+        const float ungv[4] = {ung4.x, ung4.y, ung4.z, ung4.w};
+        const float unsv[4] = {uns4.x, uns4.y, uns4.z, uns4.w};
+        const float inv_h = 1.0f / h;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int j = 4 * j4 + e;
             if (j < a.n) {
-                float g = a.vg[j], r = a.vs[j] - log2f(fmaxf(cc[e], 1.17549435e-38f));
+                float g = vgv[e], r = vsv[e] - log2f(fmaxf(cc[e], 1.17549435e-38f));
                 renorm(g, r, h, inv_h);
                 a.vg[j] = g;
                 a.vs[j] = r;
-                a.ug[j] = a.ung[j];
-                a.us[j] = a.uns[j];
+                a.ug[j] = ungv[e];
+                a.us[j] = unsv[e];
             }
         }
     }
