@@ -292,7 +292,9 @@ int goat_run_finish(goat_run* h, int32_t* perm_host, goat_stats* stats_host, flo
         if (rc == GOAT_OK) {
             on_device = true;
             GOAT_HIP(hipMemcpyAsync(perm_host, p.perm_dev, (size_t)n * 4, hipMemcpyDeviceToHost, r.s));
-        } else if (rc != GOAT_ENOTSUP) {
+        } else if (rc == GOAT_ENOTSUP) {
+            clear_error();      // round cap or bid range: the host solver takes over
+        } else {
             return rc;
         }
     }

@@ -210,3 +210,18 @@ def test_nominate_arguments_rejected_before_device(G):
     assert L.goat_nominate(4, 5, dummy, 4, 2, dummy, None, None) == G.GOAT_EINVAL      # ld < cols
     assert L.goat_nominate(4, 5, None, 5, 2, dummy, None, None) == G.GOAT_EINVAL       # null P
     assert G.NOMINATE_KMAX == 32
+
+
+def test_lap_device_arguments_rejected_before_device(G):
+    L = G.lib()
+    dummy = ctypes.c_void_p(16)
+    assert L.goat_lap_device_workspace_size(0) == 0
+    assert L.goat_lap_device_workspace_size(1000) >= 1000 * (3 * 8 + 5 * 4)
+    assert L.goat_lap_device(0, dummy, 1, dummy, dummy, 1 << 20, 0, None, None) == G.GOAT_EINVAL      # n < 1
+    assert L.goat_lap_device(8, dummy, 7, dummy, dummy, 1 << 20, 0, None, None) == G.GOAT_EINVAL      # ld < n
+    assert L.goat_lap_device(8, None, 8, dummy, dummy, 1 << 20, 0, None, None) == G.GOAT_EINVAL       # null M
+    assert L.goat_lap_device(8, dummy, 8, None, dummy, 1 << 20, 0, None, None) == G.GOAT_EINVAL       # null perm
+    assert L.goat_lap_device(1 << 20, dummy, 1 << 20, dummy, dummy, 1 << 40, 0, None, None) == G.GOAT_EINVAL  # n too large
+    o = G.default_options(lap=2)
+    s = L.goat_solve(4, dummy, dummy, 4, None, ctypes.byref(o), dummy, None, None, 0, None, dummy, 1 << 30, None)
+    assert s == G.GOAT_EINVAL and b"assignment mode" in L.goat_last_error()
