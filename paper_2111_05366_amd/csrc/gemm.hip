@@ -408,6 +408,29 @@ constexpr int BM3 = 256, BN3 = 256, BK3 = 64, LD3 = BK3 + 8;
 constexpr size_t kLdsW8 = (size_t)2 * 2 * BM3 * LD3 * sizeof(uint16_t);
 
 template <int OUT>
+__device__ inline void store_tile_w8(const GemmParams& p, const f32x16 (&acc)[4][2], int m0, int n0, int wm,
+                                     int wn, int lane) {
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + wm * 128 + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int col = n0 + wn * 64 + ni * 32 + (lane & 31);
+                const float x = p.alpha * acc[mi][ni][r];
+                if (OUT == OUT_F32) {
+                    if (row < p.m_valid && col < p.n_valid) p.C[(size_t)row * p.ldc + col] = x;
+                } else {
+                    const uint16_t h = f32_to_bf16_rne(x);
+                    const size_t idx = (size_t)row * p.ld_split + col;
+                    p.Chi[idx] = h;
+                    p.Clo[idx] = f32_to_bf16_rne(x - bf16_to_f32(h));
+                }
+            }
+}
+
+template <int OUT>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gemm_nt_bf16_w8_kernel(GemmParams p) {
     extern __shared__ __attribute__((aligned(16))) uint16_t smem16w[];
@@ -491,24 +514,7 @@ void gemm_nt_bf16_w8_kernel(GemmParams p) {
     }
 #undef GOAT_GLOADW8
 #undef GOAT_SSTOREW8
-#pragma unroll
-    for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + wm * 128 + mi * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int col = n0 + wn * 64 + ni * 32 + (lane & 31);
-                const float x = p.alpha * acc[mi][ni][r];
-                if (OUT == OUT_F32) {
-                    if (row < p.m_valid && col < p.n_valid) p.C[(size_t)row * p.ldc + col] = x;
-                } else {
-                    const uint16_t h = f32_to_bf16_rne(x);
-                    const size_t idx = (size_t)row * p.ld_split + col;
-                    p.Chi[idx] = h;
-                    p.Clo[idx] = f32_to_bf16_rne(x - bf16_to_f32(h));
-                }
-            }
+    store_tile_w8<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
 // ------------------------------------------------------------------ fp32
@@ -612,9 +618,12 @@ __global__ __launch_bounds__(256) void gemm_nt_f32_kernel(GemmParams p) {
 // (1034 against 951 TFLOP/s executed for the 128 x 128 tile at n = 10,000;
 // the 256 x 256 tile on four waves: 782, one wave per SIMD leaves its LDS and
 // global latencies exposed). GOAT_GEMM_TILE = 128 or 256 selects the others
-// (a measurement knob).
+// (a measurement knob). An eight-wave fp8 tile does not fit: its 32-byte
+// fragments push the registers past two waves per SIMD (spills; 1071
+// against 1735 TFLOP/s).
 int tile_choice(int M, int N, int K) {
-    // 0: 128 x 128, 1: 256 x 256 on four waves, 2: 256 x 256 on eight waves
+    // bf16 products: 0: 128 x 128, 1: 256 x 256 on four waves, 2: 256 x 256
+    // on eight waves
     static const int want = [] {
         const char* e = getenv("GOAT_GEMM_TILE");
         if (e && std::strcmp(e, "128") == 0) return 0;
