@@ -235,7 +235,7 @@ def main():
             "match_ratio_gap_vs_plain": (round(abs(main_form["match_ratio"] - plain["match_ratio"]), 5)
                                          if plain and main_form is not plain else None),
             "gemm_roofline": {
-                "bound": "mfma", "kernel": "gemm_nt (2 launches per gradient)",
+                "bound": "mfma", "kernel": "gemm_nt (2 products per gradient; a product is the 256x256 launch plus the last-rows 128x128 launch)",
                 "achieved_exec": round(main_form["gemm_exec_tflops"], 1) if main_form["gemm_exec_tflops"] else None,
                 "peak": MFMA_PEAK_TFLOPS["bf16" if main_form["prec"] != "fp32" else "fp32"],
                 "unit": "TFLOP/s",
