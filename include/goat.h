@@ -27,6 +27,20 @@
  *    message of the last failure on the calling thread is goat_last_error().
  *    Non-convergence of an iteration is not an error; it is reported in
  *    the outputs.
+ *
+ * Entry points
+ *  - one Frank-Wolfe iteration's pieces: goat_grad (Alg. 3 step 1),
+ *    goat_sinkhorn (LOT direction, Alg. 2), goat_linesearch (step 3);
+ *  - whole solves: goat_solve, goat_run_begin/steps/finish/gradient/free,
+ *    goat_solve_seeded (seeds, unequal sizes), goat_random_init (random
+ *    starts), goat_batch_* and goat_tune (many pairs and starts in one
+ *    launch);
+ *  - the final projection: goat_lap_max (host), goat_lap_device (device),
+ *    goat_score; soft matching: goat_nominate;
+ *  - the learned Sinkhorn warm start: goat_mlp_*;
+ *  - sizes, options, errors, timing: goat_workspace_size,
+ *    goat_default_options, goat_version, goat_last_error,
+ *    goat_profile_enable/read.
  */
 #ifndef GOAT_H
 #define GOAT_H
@@ -49,7 +63,10 @@ extern "C" {
  *  BF16X2 : A, B rounded to bf16 (exact for 0/1 adjacency), the P-side
  *           operand split into bf16 hi + lo parts: 2 bf16 products.
  *  BF16X3 : A, B and the P-side operand all split hi + lo; the lo*lo term
- *           is dropped: 3 bf16 products (weighted graphs).            */
+ *           is dropped: 3 bf16 products (weighted graphs).
+ *  FP8    : A, B in FP8 E4M3 (exact for 0/1 adjacency), the P-side operand
+ *           split into three scaled E4M3 terms: 3 fp8 products (see
+ *           goat_grad).                                                */
 #define GOAT_PREC_FP32    0
 #define GOAT_PREC_BF16X2  1
 #define GOAT_PREC_BF16X3  2
