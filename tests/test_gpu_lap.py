@@ -130,3 +130,27 @@ def test_lap_device_planted_full_size(G):
     perm, st = G.lap_device(M)
     assert torch.equal(perm.long(), truth)
     print(f"n=10000 planted: rounds {st.rounds}, tail bids {st.tail_bids}, phases {st.phases}")
+
+
+def test_lap_device_on_smooth_iterate_matches_host_optimum(G):
+    # the assignment the solver makes at the end of a short run on the
+    # weighted SBM workload (n = 4000): a smooth, nearly uniform P
+    n = 4000
+    g = I.weighted_sbm_pair([1000] * 4, [[0.02 if i == j else 0.005 for j in range(4)] for i in range(4)], 0.1,
+                            4242)
+    A = torch.as_tensor(g.A, device="cuda")
+    B = torch.as_tensor(g.B, device="cuda")
+    run = G.Run(A, B, prec="fp32", stop_on_stall=0, sk_max=300, lap=1)
+    run.steps(4)
+    P = run.finish(return_P=True).P
+    run.close()
+    perm, st = G.lap_device(P)
+    pd = perm.cpu().numpy().astype(np.int64)
+    Ph = P.double().cpu().numpy()
+    ph = G.lap_max(Ph).astype(np.int64)
+    rows = np.arange(n)
+    vd, vh = Ph[rows, pd].sum(), Ph[rows, ph].sum()
+    print(f"smooth iterate n={n}: device {vd:.9f} ({st.rounds} rounds, {st.tail_bids} sequential bids), "
+          f"host {vh:.9f}")
+    assert np.array_equal(np.sort(pd), rows)
+    assert abs(vd - vh) <= n * 2.0 ** -st.shift

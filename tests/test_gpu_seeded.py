@@ -24,7 +24,7 @@ def dev(x):
     return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda")
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x2"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x2", "fp8"])
 def test_seeded_matches_oracle(G, prec):
     g = I.rho_er_pair(80, 0.12, 0.8, 31)
     sA = [3, 17, 29, 44, 60, 71]
