@@ -209,7 +209,8 @@ void goat_default_options(goat_options* opt);
  *  stats_host host goat_stats (may be NULL).
  *  hist_host  host goat_iter_record[hist_cap] (may be NULL).
  *  P_out      device n x n (ld) final relaxed P, or NULL.
- * Host-synchronous on `stream`.
+ * Host-synchronous on `stream`. A or B holding a NaN or an infinity is
+ * refused with GOAT_EINVAL before any iteration (one device pass over each).
  */
 int goat_solve(int n, const float* A, const float* B, int ld,
                const float* P0, const goat_options* opt,

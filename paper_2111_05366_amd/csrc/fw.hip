@@ -303,6 +303,29 @@ int launch_score(int n, const float* A, const float* B, int ld, const int32_t* p
 
 namespace goat {
 
+namespace {
+
+// Sets *flag when any of the n x n entries (leading dimension ld) is NaN or
+// infinite.
+__global__ __launch_bounds__(RT) void check_finite_kernel(int n, const float* __restrict__ X, long ld,
+                                                          int* flag) {
+    bool bad = false;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const float* r = X + (long)i * ld;
+        for (int j = threadIdx.x; j < n; j += RT) bad |= !isfinite(r[j]);
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+int launch_check_finite(int n, const float* X, int ld, int* flag, hipStream_t s) {
+    if (n < 1) return GOAT_OK;
+    hipLaunchKernelGGL(check_finite_kernel, dim3(n < kRedWG ? n : kRedWG), dim3(RT), 0, s, n, X, (long)ld, flag);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
 int launch_arrange(int n, const float* X, int ldx, const int* order_dev, int adopted, float* Y, int ldy,
                    hipStream_t s) {
     if (n < 1) return GOAT_OK;

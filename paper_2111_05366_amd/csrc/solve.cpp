@@ -216,7 +216,19 @@ static int run_begin_impl(int n, const float* A, const float* B, int ld, const f
     Ptrs& p = r.p;
     const int np = L.np;
     RUN_HIP(hipMemsetAsync(ws, 0, L.total, r.s));
-    int rc = pack_graph(L, A, ld, p.A_hi, p.A_lo, r.s);
+    // non-finite adjacency entries are refused up front (the reduction
+    // partials are zero here and free until the first iteration)
+    int* bad_dev = reinterpret_cast<int*>(p.red);
+    int rc = launch_check_finite(n, A, ld, bad_dev, r.s);
+    if (!rc) rc = launch_check_finite(n, B, ld, bad_dev, r.s);
+    if (rc) return fail(rc);
+    RUN_HIP(hipMemcpyAsync(r.hbuf, bad_dev, sizeof(int), hipMemcpyDeviceToHost, r.s));
+    RUN_HIP(hipStreamSynchronize(r.s));
+    if (*static_cast<int*>(r.hbuf) != 0) {
+        set_error("goat_run_begin: A or B has a non-finite entry");
+        return fail(GOAT_EINVAL);
+    }
+    rc = pack_graph(L, A, ld, p.A_hi, p.A_lo, r.s);
     if (!rc) rc = pack_graph(L, B, ld, p.B_hi, p.B_lo, r.s);
     if (!rc) rc = P0 ? launch_copy_pad(n, P0, ld, p.P, np, np, r.s) : launch_fill_barycenter(n, np, p.P, r.s);
     if (rc) return fail(rc);

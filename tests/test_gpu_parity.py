@@ -258,3 +258,17 @@ def test_run_steps_equal_solve(G):
     G.profile_enable(G.PROF_SINKHORN_ROW, 0)
     assert cnt in (1, 10) and ms > 0.0      # one persistent launch, or one per iteration
     assert int(out.iters.item()) == 10
+
+
+@pytest.mark.parametrize("which,value", [("A", float("nan")), ("B", float("inf")), ("A", float("-inf"))])
+def test_nonfinite_graph_rejected(G, which, value):
+    g = I.workload_er_small()
+    A, B = g.A.copy(), g.B.copy()
+    (A if which == "A" else B)[5, 7] = value
+    with pytest.raises(G.GoatError) as e:
+        G.solve(dev(A), dev(B), sk_max=50, fw_max=2)
+    assert e.value.status == G.GOAT_EINVAL
+    assert "non-finite" in str(e.value)
+    # the library keeps working after the refusal
+    r = G.solve(dev(g.A), dev(g.B), sk_max=50, fw_max=2)
+    assert r.stats.fw_iters >= 1
