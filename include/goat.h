@@ -169,8 +169,7 @@ typedef struct goat_options {
     int   check_every;    /* Sinkhorn convergence flag polled every k iterations (16) */
     int   lap;            /* final assignment: 0 host Jonker-Volgenant on float64
                              scores (default); 1 device auction on the quantised
-                             scores (goat_lap_device), host if it reports
-                             GOAT_ENOTSUP                                        */
+                             scores (goat_lap_device; its errors are returned) */
     int   reserved[4];
     const float* mlp_params; /* device float[goat_mlp_param_count()] (warm 2, 3) */
 } goat_options;
@@ -204,7 +203,8 @@ void goat_default_options(goat_options* opt);
  * doubly stochastic device matrix with leading dimension ld), Frank-Wolfe
  * iterations (gradient, LOT direction, exact step, update), then
  * perm = argmax over permutations of <Pi, P_final> (or of
- * <Pi, grad f(P_final)> with opt->proj = 1) by a host linear assignment.
+ * <Pi, grad f(P_final)> with opt->proj = 1) by a host linear assignment
+ * (opt->lap = 0) or the device auction (opt->lap = 1).
  *  perm_host  host int32[n]: perm[i] = j matches A-node i to B-node j.
  *  stats_host host goat_stats (may be NULL).
  *  hist_host  host goat_iter_record[hist_cap] (may be NULL).

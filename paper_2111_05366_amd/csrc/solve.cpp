@@ -298,19 +298,19 @@ int goat_run_finish(goat_run* h, int32_t* perm_host, goat_stats* stats_host, flo
     const float* src = r.opt.proj ? p.GP : p.P;
     const auto lap0 = std::chrono::steady_clock::now();
     bool on_device = false;
-    if (r.opt.lap == 1 && auction_ws_bytes(n) <= (size_t)np * np * 4) {
-        // the direction buffer Q is free once the loop has ended
-        int rc = auction_lap(n, src, np, p.perm_dev, p.Q, (size_t)np * np * 4, 20000000ll, nullptr, r.s);
-        if (rc == GOAT_OK) {
-            on_device = true;
-            GOAT_HIP(hipMemcpyAsync(perm_host, p.perm_dev, (size_t)n * 4, hipMemcpyDeviceToHost, r.s));
-        } else if (rc == GOAT_ENOTSUP) {
-            clear_error();      // round cap or bid range: the host solver takes over
-        } else {
-            return rc;
+    if (r.opt.lap == 1) {
+        // the direction buffer Q is free once the loop has ended; errors of
+        // the device assignment (round cap, bid range) are returned as they
+        // are: the host solver runs only when the caller asks for it (lap 0)
+        if (auction_ws_bytes(n) > (size_t)np * np * 4) {
+            set_error("goat_run_finish: workspace too small for the device assignment");
+            return GOAT_ENOMEM;
         }
-    }
-    if (!on_device) {
+        int rc = auction_lap(n, src, np, p.perm_dev, p.Q, (size_t)np * np * 4, 20000000ll, nullptr, r.s);
+        if (rc) return rc;
+        on_device = true;
+        GOAT_HIP(hipMemcpyAsync(perm_host, p.perm_dev, (size_t)n * 4, hipMemcpyDeviceToHost, r.s));
+    } else {
         std::vector<float> hm((size_t)n * n);
         GOAT_HIP(hipMemcpy2DAsync(hm.data(), (size_t)n * 4, src, (size_t)np * 4, (size_t)n * 4, n,
                                   hipMemcpyDeviceToHost, r.s));
