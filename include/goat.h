@@ -169,7 +169,8 @@ typedef struct goat_options {
     int   check_every;    /* Sinkhorn convergence flag polled every k iterations (16) */
     int   lap;            /* final assignment: 0 host Jonker-Volgenant on float64
                              scores (default); 1 device auction on the quantised
-                             scores (goat_lap_device; its errors are returned) */
+                             scores (goat_lap_device; in a batch one workgroup
+                             per problem); its errors are returned            */
     int   reserved[4];
     const float* mlp_params; /* device float[goat_mlp_param_count()] (warm 2, 3) */
 } goat_options;

@@ -34,6 +34,8 @@ def main(argv=None):
     ap.add_argument("--sk-max", type=int, default=1000)
     ap.add_argument("--fw-max", type=int, default=30)
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--lap", type=int, default=0, choices=(0, 1),
+                    help="final assignments: 0 host, 1 device")
     ap.add_argument("--warm", type=int, default=0, choices=(0, 1),
                     help="Sinkhorn start: 0 cold, 1 the previous FW iteration's column potentials")
     ap.add_argument("--cpu-sample", type=int, default=2, help="problems timed with the oracle (0: skip)")
@@ -58,7 +60,7 @@ def main(argv=None):
     dev = [(torch.as_tensor(g.A, device="cuda"), torch.as_tensor(g.B, device="cuda"),
             torch.as_tensor(U, device="cuda")) for (g, U) in batch]
     b = goat.Batch(dev, restarts=a.restarts, sk_max=a.sk_max, fw_max=a.fw_max, sk_tol=1e-6, eps_rel=0.03,
-                   warm=a.warm)
+                   warm=a.warm, lap=a.lap)
     log("batch created (graph captured)")
     for _ in range(a.warmup):
         b.launch()
@@ -111,7 +113,7 @@ def main(argv=None):
         match_ratio_mean=round(mr, 4), dtype="f32+f64", data="synthetic",
         config=dict(workload=f"{a.pairs} correlated ER pairs, n in [{a.n_lo},{a.n_hi}], p in [0.05,0.3], "
                              f"rho in [0.6,1.0], {a.restarts} random starts each",
-                    sk_max=a.sk_max, fw_max=a.fw_max, sk_tol=1e-6, eps_rel=0.03, warm=a.warm),
+                    sk_max=a.sk_max, fw_max=a.fw_max, sk_tol=1e-6, eps_rel=0.03, warm=a.warm, lap=a.lap),
         cpu_baseline=cpu)
     b.close()
     print(json.dumps(line), flush=True)

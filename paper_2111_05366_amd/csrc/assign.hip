@@ -10,6 +10,7 @@
 // block then takes k rounds of a (score desc, column asc) arg-max over the
 // 256 list heads; the winning thread shifts its list by one. A row is read
 // once: HBM traffic is rows * cols * 4 bytes plus the output.
+#include "batch.h"
 #include "common.h"
 
 #include <algorithm>
@@ -733,6 +734,170 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     GOAT_HIP(hipMemcpyAsync(perm_dev, a.assign, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
     GOAT_HIP(hipStreamSynchronize(s));
     if (st) *st = loc;
+    return GOAT_OK;
+}
+
+// ---------------------------------------------------------------- batched assignment
+//
+// The final assignment of every (pair, start) problem of a batch (n <= 1024)
+// on the device: the same integer auction as above (same quantisation, bid
+// rule, epsilon schedule and phase-start filter) run by one 64-thread
+// workgroup per problem with prices, owners, assignment and the bid queue in
+// LDS, bids taken one after the other. A problem stops after `budget` bids;
+// its status is then GOAT_ENOTSUP.
+
+namespace {
+
+constexpr int BW = 64;                 // one wave per problem
+constexpr int kBatchLapMax = 1024;
+
+__device__ inline void wave_best(long long& v1, int& j1, long long& v2) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long ov1 = __shfl_xor(v1, o, 64);
+        const long long ov2 = __shfl_xor(v2, o, 64);
+        const int oj1 = __shfl_xor(j1, o, 64);
+        auc_merge(v1, j1, v2, ov1, oj1, ov2);
+    }
+}
+
+__global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restrict__ probs, int proj,
+                                                           const int* __restrict__ offs, int32_t* __restrict__ perms,
+                                                           int* __restrict__ status, long long budget, int theta) {
+    __shared__ long long price[kBatchLapMax];
+    __shared__ int owner[kBatchLapMax], assign[kBatchLapMax], queue[kBatchLapMax];
+    __shared__ int qn;
+    const int k = blockIdx.x, t = threadIdx.x;
+    const BProb& q = probs[k];
+    const int n = q.n;
+    const long ld = q.np;
+    if (n > kBatchLapMax || n < 1) {
+        if (t == 0) status[k] = GOAT_EINVAL;
+        return;
+    }
+    const float* M = proj ? q.GP : q.P;
+    int32_t* out = perms + offs[k];
+
+    // score range and finiteness
+    float mx = 0.0f, mn = INFINITY;
+    bool bad = false;
+    for (int i = 0; i < n; ++i)
+        for (int j = t; j < n; j += BW) {
+            const float x = M[i * ld + j];
+            bad |= !isfinite(x);
+            mx = fmaxf(mx, fabsf(x));
+            mn = fminf(mn, x);
+        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        mn = fminf(mn, __shfl_xor(mn, o, 64));
+    }
+    if (__any(bad)) {
+        if (t == 0) status[k] = GOAT_EINVAL;
+        return;
+    }
+    // integer scores: the quantisation of auction_lap
+    int b = 0;
+    while ((1ll << b) < (long long)n + 1) ++b;
+    const int R = min(40, 55 - b);
+    int e = 0;
+    if (mx > 0.0f) frexpf(mx, &e);
+    AuctionArgs a{};
+    a.M = M;
+    a.ld = ld;
+    a.n = n;
+    a.s = R - 1 - e;
+    a.qmin = (long long)rintf(ldexpf(mn, a.s));
+    a.np1 = (long long)n + 1;
+    a.price = price;
+    const long long cmax = (long long)rintf(ldexpf(mx, a.s)) - a.qmin;
+    for (int j = t; j < n; j += BW) {
+        price[j] = 0;
+        owner[j] = -1;
+        assign[j] = -1;
+    }
+    __syncthreads();
+    if (n == 1 || cmax == 0) {
+        for (int i = t; i < n; i += BW) out[i] = i;
+        if (t == 0) status[k] = 0;
+        return;
+    }
+    long long eps = max(1ll, cmax * a.np1 / 4);
+    long long bids = 0;
+    bool first = true;
+    for (;;) {
+        // phase start: rows whose pair is no longer eps-optimal are released
+        if (!first) {
+            for (int i = 0; i < n; ++i) {
+                const int ja = assign[i];
+                long long v1 = LLONG_MIN;
+                for (int j = t; j < n; j += BW) {
+                    const long long v = auc_cost(a, M[i * ld + j]) - price[j];
+                    v1 = v > v1 ? v : v1;
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const long long ov = __shfl_xor(v1, o, 64);
+                    v1 = ov > v1 ? ov : v1;
+                }
+                if (t == 0 && v1 - (auc_cost(a, M[i * ld + ja]) - price[ja]) > eps) {
+                    assign[i] = -1;
+                    owner[ja] = -1;
+                }
+            }
+            __syncthreads();
+        }
+        first = false;
+        if (t == 0) {
+            int c = 0;
+            for (int i = 0; i < n; ++i)
+                if (assign[i] < 0) queue[c++] = i;
+            qn = c;
+        }
+        __syncthreads();
+        while (qn > 0 && bids < budget) {
+            const int i = queue[0];
+            long long v1 = LLONG_MIN, v2 = LLONG_MIN;
+            int j1 = INT_MAX;
+            for (int j = t; j < n; j += BW) auc_push(v1, j1, v2, auc_cost(a, M[i * ld + j]) - price[j], j);
+            wave_best(v1, j1, v2);
+            if (t == 0) {
+                const long long bid = price[j1] + (v1 - v2) + eps;
+                const int old = owner[j1];
+                owner[j1] = i;
+                assign[i] = j1;
+                price[j1] = bid;
+                if (old >= 0) {
+                    assign[old] = -1;
+                    queue[0] = old;
+                } else {
+                    queue[0] = queue[qn - 1];
+                    qn = qn - 1;
+                }
+            }
+            ++bids;
+            __syncthreads();
+        }
+        if (qn > 0) {
+            if (t == 0) status[k] = GOAT_ENOTSUP;
+            return;
+        }
+        if (eps == 1) break;
+        eps = max(1ll, eps / theta);
+    }
+    for (int i = t; i < n; i += BW) out[i] = assign[i];
+    if (t == 0) status[k] = bids > INT_MAX ? INT_MAX : (int)bids;
+}
+
+}  // namespace
+
+int batch_auction_launch(const BProb* probs_dev, int nprob, int proj, const int* offs_dev, int32_t* perms_dev,
+                         int* status_dev, long long budget, hipStream_t s) {
+    if (nprob < 1) return GOAT_OK;
+    hipLaunchKernelGGL(batch_auction_kernel, dim3(nprob), dim3(BW), 0, s, probs_dev, proj, offs_dev, perms_dev,
+                       status_dev, budget, lap_knobs().theta);
+    GOAT_HIP(hipGetLastError());
     return GOAT_OK;
 }
 

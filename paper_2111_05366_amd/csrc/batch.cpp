@@ -55,7 +55,7 @@ BShape current_shape(int b) {
 }
 
 struct Plan {
-    size_t probs, order_off, jobs, hist, fwd, score, perms, offs, pairs_mat, probs_mat, total;
+    size_t probs, order_off, jobs, hist, fwd, score, perms, offs, lapst, pairs_mat, probs_mat, total;
     std::vector<size_t> pair_off, prob_off;
     int nprob = 0, total_blocks = 0, sum_n = 0;
     // per bucket: first block in the order array and number of blocks
@@ -79,7 +79,7 @@ int validate(const goat_pair* pairs, int npairs, int restarts, const goat_option
     }
     if (!(std::isfinite(opt->eps_rel) && opt->eps_rel > 0.0f) || !(std::isfinite(opt->sk_tol) && opt->sk_tol >= 0.0f) ||
         opt->sk_max < 1 || opt->fw_max < 1 || !(std::isfinite(opt->fw_tol) && opt->fw_tol >= 0.0f) ||
-        (opt->proj != 0 && opt->proj != 1)) {
+        (opt->proj != 0 && opt->proj != 1) || (opt->lap != 0 && opt->lap != 1)) {
         set_error("goat_batch: bad options");
         return GOAT_EINVAL;
     }
@@ -128,6 +128,7 @@ Plan make_plan(const goat_pair* pairs, int npairs, int restarts, const goat_opti
     for (int p = 0; p < npairs; ++p) pl.sum_n += pairs[p].n;
     pl.perms = off; off = al256(off + sizeof(int32_t) * (size_t)pl.sum_n * restarts);
     pl.offs = off; off = al256(off + sizeof(int) * pl.nprob);
+    pl.lapst = off; off = al256(off + sizeof(int) * pl.nprob);
     pl.pairs_mat = off;
     for (int p = 0; p < npairs; ++p) {
         const size_t np = batch_pad(pairs[p].n), m = np * np * sizeof(float);
@@ -395,6 +396,9 @@ int goat_batch_launch(goat_batch* b, void* stream) {
     return GOAT_OK;
 }
 
+// bids per problem before the device assignment reports GOAT_ENOTSUP
+constexpr long long kBatchLapBudget = 4000000;
+
 int goat_batch_results(goat_batch* b, int32_t* perm_host, double* score_host, int* best_host, double* all_score_host,
                        goat_iter_record* hist_host, int hist_cap, int* fw_iters_host, goat_batch_stats* stats_host) {
     if (!b || !b->launched) {
@@ -429,14 +433,33 @@ int goat_batch_results(goat_batch* b, int32_t* perm_host, double* score_host, in
             o += b->probs[k].n;
         }
     }
+    if (b->opt.lap == 1) {
+        // all assignments on the device, written into the batch's perm array
+        int rc = batch_auction_launch(reinterpret_cast<const BProb*>(b->ws + pl.probs), N, b->opt.proj,
+                                      reinterpret_cast<const int*>(b->ws + pl.offs),
+                                      reinterpret_cast<int32_t*>(b->ws + pl.perms),
+                                      reinterpret_cast<int*>(b->ws + pl.lapst), kBatchLapBudget, b->s0);
+        if (rc) return rc;
+        std::vector<int> st(N);
+        B_HIP(hipMemcpyAsync(st.data(), b->ws + pl.lapst, sizeof(int) * N, hipMemcpyDeviceToHost, b->s0));
+        B_HIP(hipMemcpyAsync(perms.data(), b->ws + pl.perms, sizeof(int32_t) * perms.size(), hipMemcpyDeviceToHost,
+                             b->s0));
+        B_HIP(hipStreamSynchronize(b->s0));
+        for (int k = 0; k < N; ++k)
+            if (st[k] < 0) {
+                set_error("goat_batch_results: device assignment of problem " + std::to_string(k) +
+                          (st[k] == GOAT_ENOTSUP ? " spent its bid budget" : " found a non-finite score"));
+                return st[k];
+            }
+    }
     const size_t chunk_bytes = (size_t)64 << 20;
-    if (!b->hbuf) {
+    if (b->opt.lap != 1 && !b->hbuf) {
         B_HIP(hipHostMalloc(&b->hbuf, chunk_bytes, hipHostMallocDefault));
         b->hbuf_bytes = chunk_bytes;
     }
     int status = GOAT_OK;
     std::string err_msg;
-    for (int k0 = 0; k0 < N && status == GOAT_OK;) {
+    for (int k0 = (b->opt.lap == 1 ? N : 0); k0 < N && status == GOAT_OK;) {
         size_t used = 0;
         int k1 = k0;
         std::vector<size_t> hoff;
@@ -477,7 +500,9 @@ int goat_batch_results(goat_batch* b, int32_t* perm_host, double* score_host, in
         return status;
     }
     const double ms_lap = now_ms() - t_lap;
-    B_HIP(hipMemcpyAsync(b->ws + pl.perms, perms.data(), sizeof(int32_t) * perms.size(), hipMemcpyHostToDevice, b->s0));
+    if (b->opt.lap != 1)
+        B_HIP(hipMemcpyAsync(b->ws + pl.perms, perms.data(), sizeof(int32_t) * perms.size(), hipMemcpyHostToDevice,
+                             b->s0));
     int rc = batch_score_launch(reinterpret_cast<const BProb*>(b->ws + pl.probs), N,
                                 reinterpret_cast<const int32_t*>(b->ws + pl.perms),
                                 reinterpret_cast<const int*>(b->ws + pl.offs), reinterpret_cast<double*>(b->ws + pl.score),

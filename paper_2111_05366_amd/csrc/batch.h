@@ -67,6 +67,11 @@ int batch_pack_launch(const BPack* jobs_dev, int njobs, int np_max, hipStream_t 
 int batch_score_launch(const BProb* probs_dev, int nprob, const int32_t* perms_dev, const int* perm_off_dev,
                        double* out_dev, hipStream_t st);
 int batch_fill_zero(float* p, size_t count, hipStream_t st);
+// final assignments of all problems on the device (assign.hip): status_dev[k]
+// = bids taken (>= 0), GOAT_EINVAL (non-finite scores) or GOAT_ENOTSUP
+// (bid budget spent)
+int batch_auction_launch(const BProb* probs_dev, int nprob, int proj, const int* offs_dev, int32_t* perms_dev,
+                         int* status_dev, long long budget, hipStream_t s);
 int batch_synth_launch(float* A, float* B, int n, int ld, uint32_t seed, hipStream_t st);
 int random_init_launch(int n, const float* U, int ldu, float* P, int ldp, float tol, int max_iter,
                        int* iters_dev, float* err_dev, hipStream_t st);

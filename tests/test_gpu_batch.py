@@ -177,3 +177,40 @@ def test_batch_fw_tol_stops_early(G):
     g = I.rho_er_pair(80, 0.1, 0.9, 81)
     res = G.solve_batch([(dev(g.A), dev(g.B))], restarts=1, sk_max=300, fw_max=10, fw_tol=1e9)
     assert int(res["fw_iters"][0][0]) == 1
+
+
+def test_batch_device_assignment(G):
+    # every problem's assignment on the device (goat_options.lap = 1): each
+    # returned map is a permutation whose integer score equals the oracle's
+    # optimum of the quantised P (several optima may exist); the chosen
+    # starts' float scores equal the host path's up to n 2^-s
+    specs = [(40, 0.2, 0.9, 11), (130, 0.1, 0.8, 12), (257, 0.05, 0.7, 13), (1024, 0.02, 0.8, 14)]
+    graphs = [I.rho_er_pair(n, p, rho, s) for (n, p, rho, s) in specs]
+    pairs = []
+    for k, g in enumerate(graphs):
+        n = g.A.shape[0]
+        U = I.uniform_matrix(2 * n, 800 + k)[:, :n]
+        pairs.append((dev(g.A), dev(g.B), dev(U)))
+    res = {}
+    for lap in (0, 1):
+        b = G.Batch(pairs, restarts=2, sk_max=300, fw_max=8, lap=lap)
+        b.launch()
+        out = b.results()
+        Ps = {(p, r): host(b.get_P(p, r)) for p in range(len(graphs)) for r in range(2)}
+        res[lap] = (out, Ps)
+        b.close()
+    out1, Ps = res[1]
+    out0, _ = res[0]
+    for p, g in enumerate(graphs):
+        n = g.A.shape[0]
+        perm = np.asarray(out1["perm"][p], dtype=np.int64)
+        assert is_perm(perm, n)
+        r = int(out1["best"][p])
+        P = Ps[(p, r)]
+        c, s = O.quantised_scores(P)
+        _, best = O.lap_quantised(P)
+        assert int(c[np.arange(n), perm].sum()) == best
+        print(f"n={n}: device score {out1['score'][p]:.0f} host {out0['score'][p]:.0f}, match "
+              f"{np.mean(perm == g.truth):.3f} / {np.mean(np.asarray(out0['perm'][p]) == g.truth):.3f}, "
+              f"assignments {out1['stats'].ms_lap:.1f} ms device, {out0['stats'].ms_lap:.1f} ms host")
+    assert out1["stats"].fw_iters_total == out0["stats"].fw_iters_total
