@@ -473,10 +473,14 @@ int goat_batch_create(const goat_pair* pairs, int npairs, int restarts,
 /* Launch the whole batch (one graph launch), stream-ordered on stream. */
 int goat_batch_launch(goat_batch* b, void* stream);
 /*
- * goat_batch_results - wait for the launch, then the final assignments on the
- * host (one LAP per problem, problems in parallel), scores
+ * goat_batch_results - wait for the launch, then the final assignments (on
+ * the host, one LAP per problem, problems in parallel; with opt->lap = 1 on
+ * the device, one workgroup per problem, the quantised auction of
+ * goat_lap_device with a budget of 4,000,000 bids per problem), scores
  * tr(A^T Pi B Pi^T) on the device, and per pair the start with the largest
- * score (ties to the lowest start index).
+ * score (ties to the lowest start index). A device assignment that spends
+ * its budget returns GOAT_ENOTSUP, one that meets a non-finite score
+ * GOAT_EINVAL.
  *  perm_host   int32[sum_p n_p]: kept permutation of each pair, concatenated
  *              in pair order (may be NULL).
  *  score_host  double[npairs] (may be NULL); best_host int[npairs] (may be NULL).
