@@ -33,6 +33,15 @@ Conventions (readings of points the paper leaves open are marked READING):
   * READING (final projection): perm = argmax over permutations of
     <Pi, P_final> by default (proj="P"); proj="GRAD" uses <Pi, grad f(P_final)>
     as printed in Alg. 3's return line.
+  * READING (FAQ, the comparison system): Alg. 1 with an argmax direction
+    (the maximisation form of its argmin steps), GOAT's exact step and stop
+    rules, the final assignment on P. Used only to compare against GOAT.
+  * READING (soft matching): the Discussion names vertex nomination as
+    future work; nominate() ranks, per row of P, the columns by score (ties
+    by column).
+  * READING (device assignment): the quantised scores the device solves
+    exactly are defined in quantised_scores().
+  * READING (seeds, unequal sizes): see the section of seeded_problem().
 """
 from __future__ import annotations
 
