@@ -462,8 +462,10 @@ typedef struct goat_batch_stats {
  * copied; A, B, U must stay valid and unchanged until goat_batch_destroy.
  *  ws, ws_bytes  device workspace of at least goat_batch_workspace_size bytes,
  *           owned by the caller, in use until goat_batch_destroy.
- * Status: GOAT_EINVAL (bad pair, restarts < 1, options), GOAT_ENOTSUP
- * (prec != FP32, warm > 1), GOAT_ENOMEM (workspace too small), GOAT_EHIP.
+ * Status: GOAT_EINVAL (bad pair, restarts < 1, options, or a pair whose A
+ * or B holds a NaN or an infinity, checked on the device at creation),
+ * GOAT_ENOTSUP (prec != FP32, warm > 1), GOAT_ENOMEM (workspace too
+ * small), GOAT_EHIP.
  */
 int goat_batch_workspace_size(const goat_pair* pairs, int npairs, int restarts,
                               const goat_options* opt, size_t* bytes);

@@ -338,6 +338,25 @@ int create_impl(const goat_pair* pairs, int npairs, int restarts, const goat_opt
     B_HIP(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
     B_HIP(hipEventCreate(&b->ev0));
     B_HIP(hipEventCreate(&b->ev1));
+    {
+        // adjacency with a NaN or an infinity is refused up front (one flag
+        // per pair in the assignment-status array, free until the results)
+        int* bad_dev = reinterpret_cast<int*>(b->ws + pl.lapst);
+        B_HIP(hipMemsetAsync(bad_dev, 0, sizeof(int) * npairs, b->s0));
+        for (int p = 0; p < npairs; ++p) {
+            rc = launch_check_finite(pairs[p].n, pairs[p].A, pairs[p].ld, bad_dev + p, b->s0);
+            if (!rc) rc = launch_check_finite(pairs[p].n, pairs[p].B, pairs[p].ld, bad_dev + p, b->s0);
+            if (rc) return rc;
+        }
+        std::vector<int> bad(npairs);
+        B_HIP(hipMemcpyAsync(bad.data(), bad_dev, sizeof(int) * npairs, hipMemcpyDeviceToHost, b->s0));
+        B_HIP(hipStreamSynchronize(b->s0));
+        for (int p = 0; p < npairs; ++p)
+            if (bad[p]) {
+                set_error("goat_batch_create: pair " + std::to_string(p) + " has a non-finite entry");
+                return GOAT_EINVAL;
+            }
+    }
     B_HIP(hipMemcpyAsync(b->ws + pl.probs, b->probs.data(), sizeof(BProb) * b->nprob, hipMemcpyHostToDevice, b->s0));
     if (pl.total_blocks > 0)
         B_HIP(hipMemcpyAsync(b->ws + pl.order_off, pl.order.data(), sizeof(int) * pl.total_blocks,

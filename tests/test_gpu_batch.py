@@ -214,3 +214,12 @@ def test_batch_device_assignment(G):
               f"{np.mean(perm == g.truth):.3f} / {np.mean(np.asarray(out0['perm'][p]) == g.truth):.3f}, "
               f"assignments {out1['stats'].ms_lap:.1f} ms device, {out0['stats'].ms_lap:.1f} ms host")
     assert out1["stats"].fw_iters_total == out0["stats"].fw_iters_total
+
+
+def test_batch_nonfinite_pair_rejected(G):
+    graphs = [I.rho_er_pair(n, 0.1, 0.9, 600 + n) for n in (30, 45)]
+    B1 = graphs[1].B.copy()
+    B1[3, 4] = float("nan")
+    with pytest.raises(G.GoatError) as e:
+        G.Batch([(dev(graphs[0].A), dev(graphs[0].B)), (dev(graphs[1].A), dev(B1))], restarts=1, sk_max=50)
+    assert e.value.status == G.GOAT_EINVAL and "pair 1" in str(e.value)
