@@ -231,7 +231,11 @@ int goat_solve(int n, const float* A, const float* B, int ld,
  *                   one record per iteration run, *done_out their number.
  *                   opt->fw_max does not limit this call.
  *  goat_run_finish  final assignment on P (or grad f(P)), the score of the
- *                   permutation, optional copy of P to P_out (ldp).
+ *                   permutation, optional copy of P to P_out (ldp). With
+ *                   opt->lap = 1 the device assignment may take G_Q and the
+ *                   packed operands as its workspace: goat_run_steps then
+ *                   returns GOAT_EINVAL (finish, gradient and free still
+ *                   work).
  *  goat_run_free    releases the handle (host memory, events).
  *  goat_run_gradient copies the current grad f(P) out (device to device).
  * All host-synchronous on the stream given to goat_run_begin.
@@ -312,7 +316,11 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
  * itself it is within n * 2^-s of the optimum. Equal bids go to the lowest
  * row, so the result is deterministic. All-equal c gives the identity.
  *  perm_dev   device int32[n] (row i -> column perm_dev[i]).
- *  ws         device workspace of goat_lap_device_workspace_size(n) bytes.
+ *  ws         device workspace of goat_lap_device_workspace_size(n) bytes
+ *             (about 8 n^2: the scaled scores are precomputed once as int64
+ *             and every scan reads them), or at least
+ *             goat_lap_device_workspace_min(n) bytes (about 44 n: every
+ *             scan converts M again). Both give the same result.
  *  max_rounds cap on parallel rounds plus tail bids over all phases
  *             (<= 0: 20,000,000).
  *  stats      host goat_lap_stats (may be NULL).
@@ -333,6 +341,7 @@ typedef struct goat_lap_stats {
     int pad;
 } goat_lap_stats;
 size_t goat_lap_device_workspace_size(int n);
+size_t goat_lap_device_workspace_min(int n);
 int goat_lap_device(int n, const float* M, int ld, int32_t* perm_dev,
                     void* ws, size_t ws_bytes, long long max_rounds,
                     goat_lap_stats* stats, void* stream);

@@ -355,7 +355,8 @@ int goat_score(int n, const float* A, const float* B, int ld, const int32_t* per
     return launch_score(n, A, B, ld, perm_dev, p.red, out_dev, static_cast<hipStream_t>(stream));
 }
 
-size_t goat_lap_device_workspace_size(int n) { return auction_ws_bytes(n); }
+size_t goat_lap_device_workspace_size(int n) { return auction_ws_bytes_fast(n); }
+size_t goat_lap_device_workspace_min(int n) { return auction_ws_bytes(n); }
 
 int goat_lap_device(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size_t ws_bytes,
                     long long max_rounds, goat_lap_stats* stats, void* stream) {

@@ -191,6 +191,8 @@ struct AuctionArgs {
     int32_t* assign;             // object held by row i, or -1
     int* ctl;                    // [0] rows assigned, [1] bid overflow, [2] parallel rounds,
                                  // [3] sequential bids
+    const long long* cp;         // precomputed scaled scores (row stride ldc), or null
+    long ldc;
 };
 
 __device__ inline long long auc_cost(const AuctionArgs& a, float m) {
@@ -241,7 +243,38 @@ __device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, 
     v2 = LLONG_MIN;
     j1 = INT_MAX;
     int j0 = 0;
-    if (a.vec4) {
+    if (a.cp) {
+        // precomputed scores: rows of ldc (a multiple of 4) int64, 32-byte aligned
+        const longlong2* c2 = reinterpret_cast<const longlong2*>(a.cp + (long)i * a.ldc);
+        const longlong2* p2 = reinterpret_cast<const longlong2*>(a.price);
+        const int c4 = a.n >> 2;
+        for (int q0 = t; q0 < c4; q0 += NT * U) {
+            longlong2 ca[U], cb[U], pa[U], pb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * NT;
+                if (q < c4) {
+                    ca[u] = c2[2 * q];
+                    cb[u] = c2[2 * q + 1];
+                    pa[u] = p2[2 * q];
+                    pb[u] = p2[2 * q + 1];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int q = q0 + u * NT;
+                if (q < c4) {
+                    const int j = 4 * q;
+                    auc_push(v1, j1, v2, ca[u].x - pa[u].x, j);
+                    auc_push(v1, j1, v2, ca[u].y - pa[u].y, j + 1);
+                    auc_push(v1, j1, v2, cb[u].x - pb[u].x, j + 2);
+                    auc_push(v1, j1, v2, cb[u].y - pb[u].y, j + 3);
+                }
+            }
+        }
+        for (int j = (c4 << 2) + t; j < a.n; j += NT) auc_push(v1, j1, v2, a.cp[(long)i * a.ldc + j] - a.price[j], j);
+        j0 = a.n;     // every column done
+    } else if (a.vec4) {
         const int c4 = a.n >> 2;
         const float4* r4 = reinterpret_cast<const float4*>(r);
         const longlong2* p2 = reinterpret_cast<const longlong2*>(a.price);
@@ -378,7 +411,7 @@ __global__ __launch_bounds__(AB) void auction_keep_kernel(AuctionArgs a, long lo
         const float* r = a.M + (long)i * a.ld;
         long long v1 = LLONG_MIN;
         for (int j = t; j < a.n; j += AB) {
-            const long long v = auc_value(a, r[j], j);
+            const long long v = a.cp ? a.cp[(long)i * a.ldc + j] - a.price[j] : auc_value(a, r[j], j);
             v1 = v > v1 ? v : v1;
         }
 #pragma unroll
@@ -390,7 +423,7 @@ __global__ __launch_bounds__(AB) void auction_keep_kernel(AuctionArgs a, long lo
         __syncthreads();
         if (t == 0) {
             for (int w = 1; w < AB / 64; ++w) v1 = sv[w] > v1 ? sv[w] : v1;
-            const long long va = auc_value(a, r[ja], ja);
+            const long long va = a.cp ? a.cp[(long)i * a.ldc + ja] - a.price[ja] : auc_value(a, r[ja], ja);
             if (v1 - va > eps) {
                 a.assign[i] = -1;
                 a.owner[ja] = -1;
@@ -399,6 +432,16 @@ __global__ __launch_bounds__(AB) void auction_keep_kernel(AuctionArgs a, long lo
             }
         }
         __syncthreads();
+    }
+}
+
+// Scaled integer scores c'_ij = (rint(M_ij 2^s) - qmin) (n + 1), written once
+// so that every later scan reads them instead of converting floats.
+__global__ __launch_bounds__(AB) void auction_cost_kernel(AuctionArgs a, long long* __restrict__ cp) {
+    for (int i = blockIdx.x; i < a.n; i += gridDim.x) {
+        const float* r = a.M + (long)i * a.ld;
+        long long* o = cp + (long)i * a.ldc;
+        for (int j = threadIdx.x; j < a.n; j += AB) o[j] = auc_cost(a, r[j]);
     }
 }
 
@@ -435,13 +478,31 @@ __global__ __launch_bounds__(AB) void auction_reset_kernel(AuctionArgs a, int mo
 // `budget` bids per launch, so every launch ends.
 constexpr int TB = 1024;
 
-__global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs a, int* __restrict__ q, long long eps,
+// LDSST: prices, owners and the assignment live in LDS for the launch
+// (16 bytes per vertex, dynamic shared memory), copied in at the start and
+// back at the end, so the scan's price reads and the updates of the bidding
+// thread stay on the CU.
+template <bool LDSST>
+__global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs g, int* __restrict__ q, long long eps,
                                                         long long budget) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char seq_smem[];
     __shared__ int qn, cur;
     __shared__ int wcnt[TB / 64];
     __shared__ long long sv1[TB / 64], sv2[TB / 64];
     __shared__ int sj1[TB / 64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    AuctionArgs a = g;
+    if (LDSST) {
+        const int nal = (g.n + 3) & ~3;
+        a.price = reinterpret_cast<long long*>(seq_smem);
+        a.owner = reinterpret_cast<int32_t*>(seq_smem + (size_t)8 * nal);
+        a.assign = a.owner + nal;
+        for (int j = t; j < g.n; j += TB) {
+            a.price[j] = g.price[j];
+            a.owner[j] = g.owner[j];
+            a.assign[j] = g.assign[j];
+        }
+    }
     if (t == 0) qn = 0;
     __syncthreads();
     for (int base = 0; base < a.n; base += TB) {
@@ -500,6 +561,13 @@ __global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs a, int* __r
         // workgroup after the barrier
         __syncthreads();
     }
+    if (LDSST) {
+        for (int j = t; j < g.n; j += TB) {
+            g.price[j] = a.price[j];
+            g.owner[j] = a.owner[j];
+            g.assign[j] = a.assign[j];
+        }
+    }
     if (t == 0) a.ctl[3] += (int)done;
 }
 
@@ -552,9 +620,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // (epsilon divisor between phases, default 3), GOAT_LAP_KEEP (0: every
 // phase restarts from no assignment; default 1 keeps the pairs that stay
 // eps-optimal), GOAT_LAP_BITS (score resolution R, default and maximum 40),
+// GOAT_LAP_SEQ_GLOBAL=1 (sequential bids keep their state in global memory),
 // GOAT_LAP_TRACE=1 (per-phase counts on stderr).
 struct LapKnobs {
-    int tail = 32, theta = 3, trace = 0, keep = 1, rate = 2;
+    int tail = 32, theta = 3, trace = 0, keep = 1, rate = 2, seq_global = 0;
 };
 const LapKnobs& lap_knobs() {
     static const LapKnobs k = [] {
@@ -564,9 +633,23 @@ const LapKnobs& lap_knobs() {
         if (const char* e = std::getenv("GOAT_LAP_THETA")) r.theta = std::max(2, std::atoi(e));
         if (const char* e = std::getenv("GOAT_LAP_TRACE")) r.trace = std::atoi(e);
         if (const char* e = std::getenv("GOAT_LAP_KEEP")) r.keep = std::atoi(e) != 0;
+        if (const char* e = std::getenv("GOAT_LAP_SEQ_GLOBAL")) r.seq_global = std::atoi(e) != 0;
         return r;
     }();
     return k;
+}
+
+constexpr size_t kSeqLdsMax = 159 * 1024;     // dynamic LDS of the sequential kernel, at most
+
+// LDS bytes of the sequential kernel's state for n vertices, or 0 when it
+// does not fit (the state then stays in global memory)
+size_t seq_lds_bytes(int n) {
+    const size_t b = (size_t)16 * ((n + 3) & ~3);
+    if (b > kSeqLdsMax || lap_knobs().seq_global) return 0;
+    static const bool ok = hipFuncSetAttribute(reinterpret_cast<const void*>(auction_seq_kernel<true>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)kSeqLdsMax) == hipSuccess;
+    return ok ? b : 0;
 }
 
 }  // namespace
@@ -574,6 +657,12 @@ const LapKnobs& lap_knobs() {
 size_t auction_ws_bytes(int n) {
     if (n < 1) return 0;
     return align256((size_t)n * 8) * 3 + align256((size_t)n * 4) * 5 + 256 + align256(kRangeWG * 3 * 4);
+}
+
+size_t auction_ws_bytes_fast(int n) {
+    if (n < 1) return 0;
+    const size_t ldc = (size_t)((n + 3) & ~3);
+    return auction_ws_bytes(n) + align256(ldc * n * 8);
 }
 
 int auction_resolution_bits(int n) {
@@ -617,6 +706,11 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     int* queue = reinterpret_cast<int*>(take((size_t)n * 4));
     a.ctl = reinterpret_cast<int*>(take(256));
     float* part = reinterpret_cast<float*>(take(kRangeWG * 3 * 4));
+    // with room for them, the scaled scores are precomputed once (8 bytes
+    // per entry) and every scan reads them
+    const long ldc = (n + 3) & ~3;
+    long long* cp = ws_bytes >= auction_ws_bytes_fast(n) ? reinterpret_cast<long long*>(take((size_t)ldc * n * 8))
+                                                         : nullptr;
 
     // score range: the quantisation's shift and offset
     const int nb = std::min(n, kRangeWG);
@@ -659,6 +753,14 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     }
     // bidding grid: one workgroup per row while many bid, a stride loop beyond
     const int gb = std::min(n, 2048);
+    if (cp) {
+        a.ldc = ldc;
+        hipLaunchKernelGGL(auction_cost_kernel, dim3(gb), dim3(AB), 0, s, a, cp);
+        GOAT_HIP(hipGetLastError());
+        a.cp = cp;
+    }
+    // sequential bids keep their state in LDS when 16 bytes per vertex fit
+    const size_t seq_lds = seq_lds_bytes(n);
     const long long cbig = cmax * a.np1;
     long long eps = std::max(1ll, cbig / 4);
     int ctl[4] = {0, 0, 0, 0};
@@ -685,7 +787,11 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
             const bool sequential = seq || left <= kn.tail;
             if (sequential) {
                 const long long budget = std::min(kSeqBudget, std::max(1ll, max_rounds - work));
-                hipLaunchKernelGGL(auction_seq_kernel, dim3(1), dim3(TB), 0, s, a, queue, eps, budget);
+                if (seq_lds)
+                    hipLaunchKernelGGL(auction_seq_kernel<true>, dim3(1), dim3(TB), seq_lds, s, a, queue, eps,
+                                       budget);
+                else
+                    hipLaunchKernelGGL(auction_seq_kernel<false>, dim3(1), dim3(TB), 0, s, a, queue, eps, budget);
                 work += budget;
             } else {
                 for (int k = 0; k < batch; ++k) {

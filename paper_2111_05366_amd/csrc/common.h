@@ -229,7 +229,8 @@ int launch_split_bf16(int n, int np, const float* src, int lds, uint16_t* hi, ui
 // Final assignment on the device (assign.hip): epsilon-scaling auction on
 // the integer-quantised scores; perm_dev receives the row -> column map.
 using AuctionStats = goat_lap_stats;
-size_t auction_ws_bytes(int n);
+size_t auction_ws_bytes(int n);         // minimum: scores converted in every scan
+size_t auction_ws_bytes_fast(int n);    // with the precomputed scores (+ 8 bytes per entry)
 int auction_resolution_bits(int n);
 int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size_t ws_bytes, long long max_rounds,
                 AuctionStats* st, hipStream_t s);

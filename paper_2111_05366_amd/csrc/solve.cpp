@@ -33,6 +33,7 @@ struct Run {
     const float* lin = nullptr;  // seeded problems: linear term C (np x np), added to every gradient
     int fw = 0;                 // iterations done
     bool stalled = false;
+    bool operands_spent = false;  // the device assignment reused G_Q and the packed operands
     double last_ls[8] = {0};
     goat_stats st{};
     void* hbuf = nullptr;       // pinned host scratch
@@ -260,6 +261,7 @@ int goat_run_steps(goat_run* h, int k, goat_iter_record* hist_host, int hist_cap
     GOAT_CHECK_ARG(k >= 0, "k < 0");
     GOAT_CHECK_ARG(hist_cap >= 0 && (hist_cap == 0 || hist_host), "bad history buffer");
     Run& r = h->r;
+    GOAT_CHECK_ARG(!r.operands_spent, "the device assignment of goat_run_finish reused this run's operands");
     int done = 0;
     GOAT_HIP(hipEventRecord(r.ev0, r.s));
     while (done < k && !r.stalled) {
@@ -302,11 +304,22 @@ int goat_run_finish(goat_run* h, int32_t* perm_host, goat_stats* stats_host, flo
         // the direction buffer Q is free once the loop has ended; errors of
         // the device assignment (round cap, bid range) are returned as they
         // are: the host solver runs only when the caller asks for it (lap 0)
-        if (auction_ws_bytes(n) > (size_t)np * np * 4) {
+        // G_Q and the packed operands after it are free once the loop has
+        // ended (the score uses the caller's A and B): room for the
+        // precomputed scores; else the direction buffer Q alone
+        void* aws = p.GQ;
+        size_t aws_bytes = r.L.total - r.L.GQ;
+        if (aws_bytes < auction_ws_bytes_fast(n)) {
+            aws = p.Q;
+            aws_bytes = (size_t)np * np * 4;
+        } else {
+            r.operands_spent = true;
+        }
+        if (auction_ws_bytes(n) > aws_bytes) {
             set_error("goat_run_finish: workspace too small for the device assignment");
             return GOAT_ENOMEM;
         }
-        int rc = auction_lap(n, src, np, p.perm_dev, p.Q, (size_t)np * np * 4, 20000000ll, nullptr, r.s);
+        int rc = auction_lap(n, src, np, p.perm_dev, aws, aws_bytes, 20000000ll, nullptr, r.s);
         if (rc) return rc;
         on_device = true;
         GOAT_HIP(hipMemcpyAsync(perm_host, p.perm_dev, (size_t)n * 4, hipMemcpyDeviceToHost, r.s));

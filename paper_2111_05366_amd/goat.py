@@ -101,6 +101,8 @@ def lib():
     L.goat_score.argtypes = [_I, _VP, _VP, _I, _VP, _VP, _VP, _SZ, _VP]
     L.goat_lap_device_workspace_size.restype = _SZ
     L.goat_lap_device_workspace_size.argtypes = [_I]
+    L.goat_lap_device_workspace_min.restype = _SZ
+    L.goat_lap_device_workspace_min.argtypes = [_I]
     L.goat_lap_device.restype = _I
     L.goat_lap_device.argtypes = [_I, _VP, _I, _VP, _VP, _SZ, ctypes.c_longlong, ctypes.POINTER(LapStats), _VP]
     L.goat_nominate.restype = _I
@@ -309,16 +311,18 @@ def score(A, B, perm):
     return out
 
 
-def lap_device(M, max_rounds: int = 0):
+def lap_device(M, max_rounds: int = 0, precompute: bool = True):
     """Device assignment maximising sum_i M[i, perm i] on the quantised
-    scores (goat_lap_device). M: row-major float32 device matrix. Returns
-    (perm int32 device tensor, LapStats)."""
+    scores (goat_lap_device). M: row-major float32 device matrix.
+    precompute=False passes the minimum workspace (scores converted in
+    every scan; same result). Returns (perm int32 device tensor, LapStats)."""
     torch = _torch()
     _mat(M, "M")
     n = M.shape[0]
     if M.shape[1] != n:
         raise ValueError("M must be square")
-    ws = torch.empty(max(int(lib().goat_lap_device_workspace_size(n)), 1), dtype=torch.uint8, device=M.device)
+    size = lib().goat_lap_device_workspace_size if precompute else lib().goat_lap_device_workspace_min
+    ws = torch.empty(max(int(size(n)), 1), dtype=torch.uint8, device=M.device)
     perm = torch.empty(n, dtype=torch.int32, device=M.device)
     st = LapStats()
     _check(lib().goat_lap_device(n, _ptr(M), M.stride(0), _ptr(perm), _ptr(ws), ws.numel(), max_rounds,

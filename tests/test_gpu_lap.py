@@ -54,9 +54,9 @@ def _device(M, ld=None):
     return buf[:, :n]
 
 
-def _check(G, M, ld=None):
+def _check(G, M, ld=None, precompute=True):
     n = M.shape[0]
-    perm, st = G.lap_device(_device(M, ld))
+    perm, st = G.lap_device(_device(M, ld), precompute=precompute)
     perm = perm.cpu().numpy().astype(np.int64)
     assert np.array_equal(np.sort(perm), np.arange(n))
     c, s = O.quantised_scores(M.astype(np.float64))
@@ -74,8 +74,14 @@ def _check(G, M, ld=None):
 ])
 def test_lap_device_parity(G, kind, n, ld):
     print(f"lap_device {kind} n={n} ld={ld}", flush=True)
-    _, st = _check(G, _scores(kind, n, 31 * n + len(kind)), ld)
+    M = _scores(kind, n, 31 * n + len(kind))
+    perm, st = _check(G, M, ld)
     print(f"  rounds {st.rounds}, tail bids {st.tail_bids}, phases {st.phases}", flush=True)
+    # the minimum workspace converts the scores in every scan: same bids,
+    # same permutation
+    perm_min, st_min = _check(G, M, ld, precompute=False)
+    assert np.array_equal(perm, perm_min)
+    assert (st.rounds, st.tail_bids, st.phases) == (st_min.rounds, st_min.tail_bids, st_min.phases)
 
 
 def test_lap_device_degenerate(G):
@@ -119,6 +125,22 @@ def test_solve_with_device_assignment(G):
     assert abs(v1 - v0) <= 300 * 2.0 ** -s
     print(f"match ratio device {O.match_ratio(r1.perm, g.truth):.4f}, host {O.match_ratio(r0.perm, g.truth):.4f}, "
           f"assignment ms device {r1.stats.ms_lap:.1f}, host {r0.stats.ms_lap:.1f}")
+
+
+def test_run_steps_refused_after_device_assignment(G):
+    # the device assignment takes G_Q and the packed operands as workspace
+    g = I.rho_sbm_pair([60, 60], [[0.2, 0.02], [0.02, 0.2]], 0.9, 77)
+    A = torch.as_tensor(g.A, device="cuda")
+    B = torch.as_tensor(g.B, device="cuda")
+    run = G.Run(A, B, prec="bf16x2", stop_on_stall=0, lap=1)
+    run.steps(2)
+    first = run.finish()
+    with pytest.raises(G.GoatError) as e:
+        run.steps(1)
+    assert e.value.status == G.GOAT_EINVAL
+    again = run.finish()
+    run.close()
+    assert np.array_equal(first.perm, again.perm)
 
 
 def test_lap_device_planted_full_size(G):
