@@ -309,7 +309,10 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
  * scaling on integer scores. Unassigned rows bid in parallel rounds; when
  * few are left, or a batch of rounds assigns few rows, one workgroup takes
  * the bids in sequence; each phase keeps the pairs that stay optimal to
- * within the new epsilon. With 2^(e-1) <= max|M| < 2^e,
+ * within the new epsilon. A bid in sequence first tries the row's list of
+ * 32 candidate columns, kept from its last scan with a bound on every
+ * other column's value (prices only rise, so the bound holds); only when
+ * the list cannot decide the bid is the row scanned again. With 2^(e-1) <= max|M| < 2^e,
  * R = min(40, 55 - ceil(log2(n+1))) and s = R - 1 - e, the scores are
  * c_ij = rint(M_ij * 2^s) - min_kl rint(M_kl * 2^s) (round half to even;
  * 0 <= c <= 2^R), and perm maximises sum_i c[i][perm i] exactly; on M
@@ -319,7 +322,7 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
  *  ws         device workspace of goat_lap_device_workspace_size(n) bytes
  *             (about 8 n^2: the scaled scores are precomputed once as int64
  *             and every scan reads them), or at least
- *             goat_lap_device_workspace_min(n) bytes (about 44 n: every
+ *             goat_lap_device_workspace_min(n) bytes (about 450 n: every
  *             scan converts M again). Both give the same result.
  *  max_rounds cap on parallel rounds plus tail bids over all phases
  *             (<= 0: 20,000,000).
@@ -338,7 +341,8 @@ typedef struct goat_lap_stats {
     int phases;                 /* epsilon phases                           */
     int shift;                  /* s above                                  */
     int resolution_bits;        /* R above                                  */
-    int pad;
+    int list_bids;              /* of the tail bids, those decided by the
+                                   row's candidate list without a row scan */
 } goat_lap_stats;
 size_t goat_lap_device_workspace_size(int n);
 size_t goat_lap_device_workspace_min(int n);

@@ -175,6 +175,8 @@ namespace {
 constexpr int AB = 256;             // threads per block
 constexpr long long kBidLimit = 1ll << 62;
 constexpr int kNoRow = 0x7fffffff;
+constexpr int kSeqThreads = 1024;   // threads of the sequential kernel
+constexpr int kCand = 2 * (kSeqThreads / 64);   // candidate slots per row: two per wave of that kernel
 
 struct AuctionArgs {
     const float* M;
@@ -193,6 +195,9 @@ struct AuctionArgs {
                                  // [3] sequential bids
     const long long* cp;         // precomputed scaled scores (row stride ldc), or null
     long ldc;
+    int32_t* cj;                 // per row: candidate columns (kCand slots; -1: empty)
+    long long* cc;               // per row: their scaled scores
+    long long* thr;              // per row: bound on every other column's value (LLONG_MAX: no list)
 };
 
 __device__ inline long long auc_cost(const AuctionArgs& a, float m) {
@@ -229,13 +234,12 @@ __device__ inline void auc_merge(long long& v1, int& j1, long long& v2, long lon
     }
 }
 
-// Best and second-best value of row i over all columns, reduced over the
-// block (NT threads); the result is valid in thread 0. On the aligned path
-// a thread issues the loads of up to four float4 chunks of the row and of
-// their prices before it uses any of them.
+// This thread's best value (lowest column among equals) and second-best
+// value over its columns of row i; thread t takes column quads t, t + NT,
+// ... On the aligned path a thread issues the loads of up to four chunks of
+// the row and of their prices before it uses any of them.
 template <int NT>
-__device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, int& j1, long long& v2,
-                                    long long* sv1, long long* sv2, int* sj1) {
+__device__ inline void auc_lane_scan(const AuctionArgs& a, int i, long long& v1, int& j1, long long& v2) {
     constexpr int U = 4;
     const int t = threadIdx.x;
     const float* r = a.M + (long)i * a.ld;
@@ -305,6 +309,15 @@ __device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, 
         j0 = c4 << 2;
     }
     for (int j = j0 + t; j < a.n; j += NT) auc_push(v1, j1, v2, auc_value(a, r[j], j), j);
+}
+
+// Best and second-best value of row i over all columns, reduced over the
+// block (NT threads); the result is valid in thread 0.
+template <int NT>
+__device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, int& j1, long long& v2,
+                                    long long* sv1, long long* sv2, int* sj1) {
+    const int t = threadIdx.x;
+    auc_lane_scan<NT>(a, i, v1, j1, v2);
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         const long long ov1 = __shfl_xor(v1, o, 64);
@@ -322,6 +335,128 @@ __device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, 
 #pragma unroll
         for (int w = 1; w < NT / 64; ++w) auc_merge(v1, j1, v2, sv1[w], sj1[w], sv2[w]);
     }
+}
+
+// Wave-wide best (v, j): larger value, then smaller column; every lane
+// ends with the result.
+__device__ inline void auc_wave_best(long long& v, int& j) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long ov = __shfl_xor(v, o, 64);
+        const int oj = __shfl_xor(j, o, 64);
+        const bool b = auc_better(ov, oj, v, j);
+        v = b ? ov : v;
+        j = b ? oj : j;
+    }
+}
+
+__device__ inline long long auc_wave_max(long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long ov = __shfl_xor(v, o, 64);
+        v = ov > v ? ov : v;
+    }
+    return v;
+}
+
+// Full scan of row i by the kSeqThreads threads of the sequential kernel,
+// with a refresh of the row's candidate list. Each wave contributes the two
+// best of its threads' maxima (e1, e2) and the largest value outside them
+// (tw: the other threads' maxima and every thread's second value). The
+// candidates are the e1, e2 of all waves; no other column is worth more
+// than thr_i = max_w tw, and since prices only rise this stays true for
+// the rest of the auction. Writes the list (slot k by lane k of wave 0);
+// the row's exact (v1, j1, v2), as auc_scan_row gives them, end in
+// thread 0.
+__device__ inline void auc_scan_row_lists(const AuctionArgs& a, int i, long long& v1, int& j1, long long& v2,
+                                          long long* se1, int* sje1, long long* se2, int* sje2,
+                                          long long* stw) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    long long lv1, lv2;
+    int lj1;
+    auc_lane_scan<kSeqThreads>(a, i, lv1, lj1, lv2);
+    long long b1 = lv1;
+    int bj1 = lj1;
+    auc_wave_best(b1, bj1);
+    // a column belongs to one thread, so the winner is the thread holding
+    // bj1 (threads without columns hold INT_MAX and LLONG_MIN: harmless)
+    const bool w1 = lj1 == bj1;
+    const long long cv = w1 ? LLONG_MIN : lv1;
+    const int cjj = w1 ? INT_MAX : lj1;
+    long long b2 = cv;
+    int bj2 = cjj;
+    auc_wave_best(b2, bj2);
+    long long rest = cjj == bj2 ? LLONG_MIN : cv;
+    rest = rest > lv2 ? rest : lv2;
+    const long long tw = auc_wave_max(rest);
+    if (lane == 0) {
+        se1[w] = b1;
+        sje1[w] = bj1;
+        se2[w] = b2;
+        sje2[w] = bj2;
+        stw[w] = tw;
+    }
+    __syncthreads();
+    if (w == 0) {
+        if (lane < kCand) {
+            const int ww = lane >> 1;
+            const long long ev = (lane & 1) ? se2[ww] : se1[ww];
+            const int ej = (lane & 1) ? sje2[ww] : sje1[ww];
+            const bool ok = ej >= 0 && ej < a.n;
+            a.cj[(long)i * kCand + lane] = ok ? ej : -1;
+            a.cc[(long)i * kCand + lane] = ok ? ev + a.price[ej] : 0;
+        }
+        if (lane == 0) {
+            v1 = se1[0];
+            j1 = sje1[0];
+            int wb = 0;
+            for (int ww = 1; ww < kSeqThreads / 64; ++ww)
+                if (auc_better(se1[ww], sje1[ww], v1, j1)) {
+                    v1 = se1[ww];
+                    j1 = sje1[ww];
+                    wb = ww;
+                }
+            long long T = LLONG_MIN;
+            v2 = LLONG_MIN;
+            for (int ww = 0; ww < kSeqThreads / 64; ++ww) {
+                T = stw[ww] > T ? stw[ww] : T;
+                const long long o = ww == wb ? (se2[ww] > stw[ww] ? se2[ww] : stw[ww]) : se1[ww];
+                v2 = o > v2 ? o : v2;
+            }
+            a.thr[i] = T;
+        }
+    }
+}
+
+// Bid of row i from its candidate list alone, by wave 0 (lane k reads slot
+// k, the lane that wrote it): the best candidate (lowest column among
+// equals) and the second-best candidate value. Exact whenever v1 > thr_i
+// and v2 >= thr_i, since no column outside the list is worth more than
+// thr_i; the return value says whether that holds (valid in lane 0).
+__device__ inline bool auc_try_list(const AuctionArgs& a, int i, long long& v1, int& j1, long long& v2) {
+    const int lane = threadIdx.x & 63;
+    const long long T = lane == 0 ? a.thr[i] : LLONG_MAX;
+    int c = -1;
+    long long sc = 0;
+    if (lane < kCand) {
+        c = a.cj[(long)i * kCand + lane];
+        sc = a.cc[(long)i * kCand + lane];
+    }
+    v1 = LLONG_MIN;
+    v2 = LLONG_MIN;
+    j1 = INT_MAX;
+    if (c >= 0 && c < a.n) {
+        v1 = sc - a.price[c];
+        j1 = c;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long ov1 = __shfl_xor(v1, o, 64);
+        const long long ov2 = __shfl_xor(v2, o, 64);
+        const int oj1 = __shfl_xor(j1, o, 64);
+        auc_merge(v1, j1, v2, ov1, oj1, ov2);
+    }
+    return v1 > T && v2 >= T;
 }
 
 // Parallel bids: one workgroup per bidding row; this block's rows are
@@ -455,6 +590,7 @@ __global__ __launch_bounds__(AB) void auction_reset_kernel(AuctionArgs a, int mo
             a.ctl[1] = 0;
             a.ctl[2] = 0;
             a.ctl[3] = 0;
+            a.ctl[4] = 0;
         }
     }
     if (j >= a.n) return;
@@ -463,6 +599,8 @@ __global__ __launch_bounds__(AB) void auction_reset_kernel(AuctionArgs a, int mo
         a.best[j] = 0;
         a.win[j] = kNoRow;
         a.tgt[j] = -1;
+        a.thr[j] = LLONG_MAX;
+        for (int k = 0; k < kCand; ++k) a.cj[(long)j * kCand + k] = -1;
     }
     if (mode == 2) return;
     a.owner[j] = -1;
@@ -476,20 +614,23 @@ __global__ __launch_bounds__(AB) void auction_reset_kernel(AuctionArgs a, int mo
 // rows form a queue in global memory (capacity n), built in increasing row
 // order; an evicted row takes its evictor's place at the head. At most
 // `budget` bids per launch, so every launch ends.
-constexpr int TB = 1024;
+constexpr int TB = kSeqThreads;
 
 // LDSST: prices, owners and the assignment live in LDS for the launch
 // (16 bytes per vertex, dynamic shared memory), copied in at the start and
 // back at the end, so the scan's price reads and the updates of the bidding
 // thread stay on the CU.
+// With `lists`, a bid first tries the row's candidate list (auc_try_list)
+// and scans the row only when the list cannot decide it; the scan then
+// refreshes the list. Both give the same bid.
 template <bool LDSST>
 __global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs g, int* __restrict__ q, long long eps,
-                                                        long long budget) {
+                                                        long long budget, int lists) {
     extern __shared__ __attribute__((aligned(16))) unsigned char seq_smem[];
-    __shared__ int qn, cur;
+    __shared__ int qn, cur, shit;
     __shared__ int wcnt[TB / 64];
-    __shared__ long long sv1[TB / 64], sv2[TB / 64];
-    __shared__ int sj1[TB / 64];
+    __shared__ long long sv1[TB / 64], sv2[TB / 64], stw[TB / 64];
+    __shared__ int sj1[TB / 64], sje2[TB / 64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     AuctionArgs a = g;
     if (LDSST) {
@@ -526,11 +667,39 @@ __global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs g, int* __r
     if (t == 0 && qn > 0) cur = q[0];
     __syncthreads();
     long long done = 0;
+    int hits = 0;
+    // lists that decide fewer than a quarter of a window of tries are left
+    // aside for the next kListSkip bids (every thread keeps the same count)
+    constexpr int kListWindow = 32, kListSkip = 256;
+    int tries = 0, wins = 0, skip = 0;
     while (qn > 0 && done < budget) {
         const int i = cur;
         long long v1, v2;
         int j1;
-        auc_scan_row<TB>(a, i, v1, j1, v2, sv1, sv2, sj1);
+        if (lists && skip == 0) {
+            if (w == 0) {
+                const bool hit = auc_try_list(a, i, v1, j1, v2);
+                if (lane == 0) shit = hit;
+            }
+            __syncthreads();
+            const bool hit = shit;
+            ++tries;
+            wins += hit;
+            if (tries == kListWindow) {
+                if (4 * wins < kListWindow) skip = kListSkip;
+                tries = 0;
+                wins = 0;
+            }
+            if (hit) {
+                hits += t == 0;
+            } else {
+                // sv1/sj1 hold e1 of each wave, sv2/sje2 e2
+                auc_scan_row_lists(a, i, v1, j1, v2, sv1, sj1, sv2, sje2, stw);
+            }
+        } else {
+            skip -= skip > 0;
+            auc_scan_row<TB>(a, i, v1, j1, v2, sv1, sv2, sj1);
+        }
         if (t == 0) {
             // both loads issue before either is used
             const long long pj = a.price[j1];
@@ -568,7 +737,10 @@ __global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs g, int* __r
             g.assign[j] = a.assign[j];
         }
     }
-    if (t == 0) a.ctl[3] += (int)done;
+    if (t == 0) {
+        a.ctl[3] += (int)done;
+        a.ctl[4] += hits;
+    }
 }
 
 // per block: max |x|, min x, and a flag for non-finite entries
@@ -621,9 +793,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // phase restarts from no assignment; default 1 keeps the pairs that stay
 // eps-optimal), GOAT_LAP_BITS (score resolution R, default and maximum 40),
 // GOAT_LAP_SEQ_GLOBAL=1 (sequential bids keep their state in global memory),
+// GOAT_LAP_LISTS=0 (sequential bids always scan the whole row),
 // GOAT_LAP_TRACE=1 (per-phase counts on stderr).
 struct LapKnobs {
-    int tail = 32, theta = 3, trace = 0, keep = 1, rate = 2, seq_global = 0;
+    int tail = 32, theta = 3, trace = 0, keep = 1, rate = 2, seq_global = 0, lists = 1;
 };
 const LapKnobs& lap_knobs() {
     static const LapKnobs k = [] {
@@ -634,6 +807,7 @@ const LapKnobs& lap_knobs() {
         if (const char* e = std::getenv("GOAT_LAP_TRACE")) r.trace = std::atoi(e);
         if (const char* e = std::getenv("GOAT_LAP_KEEP")) r.keep = std::atoi(e) != 0;
         if (const char* e = std::getenv("GOAT_LAP_SEQ_GLOBAL")) r.seq_global = std::atoi(e) != 0;
+        if (const char* e = std::getenv("GOAT_LAP_LISTS")) r.lists = std::atoi(e) != 0;
         return r;
     }();
     return k;
@@ -656,7 +830,8 @@ size_t seq_lds_bytes(int n) {
 
 size_t auction_ws_bytes(int n) {
     if (n < 1) return 0;
-    return align256((size_t)n * 8) * 3 + align256((size_t)n * 4) * 5 + 256 + align256(kRangeWG * 3 * 4);
+    return align256((size_t)n * 8) * 4 + align256((size_t)n * 4) * 5 + 256 + align256(kRangeWG * 3 * 4) +
+           align256((size_t)n * kCand * 4) + align256((size_t)n * kCand * 8);
 }
 
 size_t auction_ws_bytes_fast(int n) {
@@ -706,6 +881,9 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     int* queue = reinterpret_cast<int*>(take((size_t)n * 4));
     a.ctl = reinterpret_cast<int*>(take(256));
     float* part = reinterpret_cast<float*>(take(kRangeWG * 3 * 4));
+    a.thr = reinterpret_cast<long long*>(take((size_t)n * 8));
+    a.cj = reinterpret_cast<int32_t*>(take((size_t)n * kCand * 4));
+    a.cc = reinterpret_cast<long long*>(take((size_t)n * kCand * 8));
     // with room for them, the scaled scores are precomputed once (8 bytes
     // per entry) and every scan reads them
     const long ldc = (n + 3) & ~3;
@@ -763,10 +941,10 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     const size_t seq_lds = seq_lds_bytes(n);
     const long long cbig = cmax * a.np1;
     long long eps = std::max(1ll, cbig / 4);
-    int ctl[4] = {0, 0, 0, 0};
+    int ctl[5] = {0, 0, 0, 0, 0};
     long long work = 0;          // parallel rounds launched + sequential budgets
     const LapKnobs& kn = lap_knobs();
-    int prev_rounds = 0, prev_seq = 0;
+    int prev_rounds = 0, prev_seq = 0, prev_hits = 0;
     auto tp = std::chrono::steady_clock::now();
     for (;;) {
         ++loc.phases;
@@ -789,9 +967,10 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
                 const long long budget = std::min(kSeqBudget, std::max(1ll, max_rounds - work));
                 if (seq_lds)
                     hipLaunchKernelGGL(auction_seq_kernel<true>, dim3(1), dim3(TB), seq_lds, s, a, queue, eps,
-                                       budget);
+                                       budget, kn.lists);
                 else
-                    hipLaunchKernelGGL(auction_seq_kernel<false>, dim3(1), dim3(TB), 0, s, a, queue, eps, budget);
+                    hipLaunchKernelGGL(auction_seq_kernel<false>, dim3(1), dim3(TB), 0, s, a, queue, eps, budget,
+                                       kn.lists);
                 work += budget;
             } else {
                 for (int k = 0; k < batch; ++k) {
@@ -824,18 +1003,20 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
         }
         if (kn.trace) {
             const auto now = std::chrono::steady_clock::now();
-            std::fprintf(stderr, "[lap] phase %d eps %lld: rounds %d, sequential bids %d, %.2f ms\n", loc.phases, eps,
-                         ctl[2] - prev_rounds, ctl[3] - prev_seq,
+            std::fprintf(stderr, "[lap] phase %d eps %lld: rounds %d, sequential bids %d (list %d), %.2f ms\n",
+                         loc.phases, eps, ctl[2] - prev_rounds, ctl[3] - prev_seq, ctl[4] - prev_hits,
                          std::chrono::duration<double, std::milli>(now - tp).count());
             tp = now;
             prev_rounds = ctl[2];
             prev_seq = ctl[3];
+            prev_hits = ctl[4];
         }
         if (eps == 1) break;
         eps = std::max(1ll, eps / kn.theta);
     }
     loc.rounds = ctl[2];
     loc.tail_bids = ctl[3];
+    loc.list_bids = ctl[4];
     loc.rounds_launched = work;
     GOAT_HIP(hipMemcpyAsync(perm_dev, a.assign, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
     GOAT_HIP(hipStreamSynchronize(s));

@@ -53,7 +53,7 @@ class Stats(ctypes.Structure):
 class LapStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_longlong), ("rounds_launched", ctypes.c_longlong),
                 ("tail_bids", ctypes.c_longlong), ("phases", ctypes.c_int), ("shift", ctypes.c_int), ("resolution_bits", ctypes.c_int),
-                ("pad", ctypes.c_int)]
+                ("list_bids", ctypes.c_int)]
 
 
 class Pair(ctypes.Structure):

@@ -40,6 +40,9 @@ def _scores(kind, n, seed):
     elif kind == "nearperm":
         M = rng.random((n, n)) * 1e-3 / n
         M[np.arange(n), rng.permutation(n)] += 0.9
+    elif kind == "flat":
+        # nearly uniform, like a solver iterate far from a permutation
+        M = (1.0 + 0.05 * rng.standard_normal((n, n))) / n
     elif kind == "ds":
         X = rng.random((n, n)) ** 8
         M = O.sinkhorn_knopp(X + 1e-12, tol=1e-10)
@@ -82,6 +85,43 @@ def test_lap_device_parity(G, kind, n, ld):
     perm_min, st_min = _check(G, M, ld, precompute=False)
     assert np.array_equal(perm, perm_min)
     assert (st.rounds, st.tail_bids, st.phases) == (st_min.rounds, st_min.tail_bids, st_min.phases)
+
+
+_LISTS_OFF = """
+import sys, json
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+from paper_2111_05366_amd import goat
+M = torch.as_tensor(np.load(sys.argv[2]), device="cuda")
+perm, st = goat.lap_device(M)
+np.save(sys.argv[3], perm.cpu().numpy())
+print(json.dumps([st.rounds, st.tail_bids, st.phases, st.list_bids]))
+"""
+
+
+@pytest.mark.parametrize("kind,n", [("ds", 1500), ("flat", 2000)])
+def test_lap_device_candidate_lists_change_nothing(G, kind, n, tmp_path):
+    # a bid decided by the row's candidate list is the bid a full scan
+    # gives: with the lists switched off (in a fresh process, the switch is
+    # read once) every count and the permutation are the same
+    import json
+    import os
+    import subprocess
+    import sys
+    M = _scores(kind, n, 5 * n + 1)
+    perm, st = _check(G, M)
+    print(f"{kind} n={n}: tail bids {st.tail_bids}, decided by lists {st.list_bids}", flush=True)
+    assert st.list_bids > 0
+    np.save(tmp_path / "M.npy", M)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, GOAT_LAP_LISTS="0")
+    out = subprocess.run([sys.executable, "-c", _LISTS_OFF, root, str(tmp_path / "M.npy"), str(tmp_path / "p.npy")],
+                         env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    rounds, tail, phases, listed = json.loads(out.stdout.strip().splitlines()[-1])
+    assert listed == 0
+    assert (rounds, tail, phases) == (st.rounds, st.tail_bids, st.phases)
+    assert np.array_equal(np.load(tmp_path / "p.npy").astype(np.int64), perm)
 
 
 def test_lap_device_degenerate(G):
