@@ -225,13 +225,86 @@ __device__ inline void auc_push(long long& v1, int& j1, long long& v2, long long
 }
 
 __device__ inline void auc_merge(long long& v1, int& j1, long long& v2, long long ov1, int oj1, long long ov2) {
-    if (auc_better(ov1, oj1, v1, j1)) {
-        v2 = v1 > ov2 ? v1 : ov2;
-        v1 = ov1;
-        j1 = oj1;
-    } else {
-        v2 = v2 > ov1 ? v2 : ov1;
+    // top two of the union of two disjoint sets, without branches
+    const bool b = auc_better(ov1, oj1, v1, j1);
+    const long long lo = b ? v1 : ov1;     // the head that lost
+    const long long w2 = b ? ov2 : v2;     // the winner's second
+    v2 = lo > w2 ? lo : w2;
+    v1 = b ? ov1 : v1;
+    j1 = b ? oj1 : j1;
+}
+
+// Cross-lane moves on the data-parallel primitives (DPP) of the VALU, which
+// take a few cycles where a general lane shuffle goes through the LDS unit.
+// CTRL: 0xB1 lane ^ 1, 0x4E lane ^ 2 (quad permutations), 0x141 mirror
+// within each 8 lanes, 0x140 mirror within each 16 lanes (a row).
+template <int CTRL>
+__device__ inline int dpp_i(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline long long dpp_ll(long long x) {
+    const int lo = dpp_i<CTRL>((int)(unsigned long long)x);
+    const int hi = dpp_i<CTRL>((int)((unsigned long long)x >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ inline long long readlane_ll(long long x, int l) {
+    const int lo = __builtin_amdgcn_readlane((int)(unsigned long long)x, l);
+    const int hi = __builtin_amdgcn_readlane((int)((unsigned long long)x >> 32), l);
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+template <int CTRL>
+__device__ inline void auc_merge_dpp(long long& v1, int& j1, long long& v2) {
+    const long long ov1 = dpp_ll<CTRL>(v1), ov2 = dpp_ll<CTRL>(v2);
+    const int oj1 = dpp_i<CTRL>(j1);
+    auc_merge(v1, j1, v2, ov1, oj1, ov2);
+}
+
+// Top two over each row of 16 lanes (every lane of the row ends with its
+// row's result): each step merges the set a lane holds with a disjoint set
+// of the same size. The whole wave must be active.
+__device__ inline void auc_row_merge(long long& v1, int& j1, long long& v2) {
+    auc_merge_dpp<0xB1>(v1, j1, v2);
+    auc_merge_dpp<0x4E>(v1, j1, v2);
+    auc_merge_dpp<0x141>(v1, j1, v2);
+    auc_merge_dpp<0x140>(v1, j1, v2);
+}
+
+// Top two over the wave: rows merged, then the four row results read into
+// scalar registers and merged there. The result is uniform.
+__device__ inline void auc_wave_merge(long long& v1, int& j1, long long& v2) {
+    auc_row_merge(v1, j1, v2);
+    long long r1 = readlane_ll(v1, 0), r2 = readlane_ll(v2, 0);
+    int rj = __builtin_amdgcn_readlane(j1, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r)
+        auc_merge(r1, rj, r2, readlane_ll(v1, 16 * r), __builtin_amdgcn_readlane(j1, 16 * r), readlane_ll(v2, 16 * r));
+    v1 = r1;
+    j1 = rj;
+    v2 = r2;
+}
+
+// Largest value over each row of 16 lanes / over the wave (uniform).
+__device__ inline long long auc_row_max(long long v) {
+    long long o = dpp_ll<0xB1>(v);
+    v = o > v ? o : v;
+    o = dpp_ll<0x4E>(v);
+    v = o > v ? o : v;
+    o = dpp_ll<0x141>(v);
+    v = o > v ? o : v;
+    o = dpp_ll<0x140>(v);
+    return o > v ? o : v;
+}
+__device__ inline long long auc_wave_max(long long v) {
+    v = auc_row_max(v);
+    long long m = readlane_ll(v, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const long long o = readlane_ll(v, 16 * r);
+        m = o > m ? o : m;
     }
+    return m;
 }
 
 // This thread's best value (lowest column among equals) and second-best
@@ -316,47 +389,28 @@ __device__ inline void auc_lane_scan(const AuctionArgs& a, int i, long long& v1,
 template <int NT>
 __device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, int& j1, long long& v2,
                                     long long* sv1, long long* sv2, int* sj1) {
+    static_assert(NT % 64 == 0 && NT / 64 <= 16, "one row of wave 0 merges the waves");
     const int t = threadIdx.x;
     auc_lane_scan<NT>(a, i, v1, j1, v2);
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const long long ov1 = __shfl_xor(v1, o, 64);
-        const long long ov2 = __shfl_xor(v2, o, 64);
-        const int oj1 = __shfl_xor(j1, o, 64);
-        auc_merge(v1, j1, v2, ov1, oj1, ov2);
-    }
+    auc_wave_merge(v1, j1, v2);
     if ((t & 63) == 0) {
         sv1[t >> 6] = v1;
         sv2[t >> 6] = v2;
         sj1[t >> 6] = j1;
     }
     __syncthreads();
-    if (t == 0) {
-#pragma unroll
-        for (int w = 1; w < NT / 64; ++w) auc_merge(v1, j1, v2, sv1[w], sj1[w], sv2[w]);
+    if (t < 64) {
+        // wave 0: lane w takes wave w's result, one row merges them
+        v1 = LLONG_MIN;
+        v2 = LLONG_MIN;
+        j1 = INT_MAX;
+        if (t < NT / 64) {
+            v1 = sv1[t];
+            v2 = sv2[t];
+            j1 = sj1[t];
+        }
+        auc_row_merge(v1, j1, v2);
     }
-}
-
-// Wave-wide best (v, j): larger value, then smaller column; every lane
-// ends with the result.
-__device__ inline void auc_wave_best(long long& v, int& j) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const long long ov = __shfl_xor(v, o, 64);
-        const int oj = __shfl_xor(j, o, 64);
-        const bool b = auc_better(ov, oj, v, j);
-        v = b ? ov : v;
-        j = b ? oj : j;
-    }
-}
-
-__device__ inline long long auc_wave_max(long long v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const long long ov = __shfl_xor(v, o, 64);
-        v = ov > v ? ov : v;
-    }
-    return v;
 }
 
 // Full scan of row i by the kSeqThreads threads of the sequential kernel,
@@ -375,17 +429,17 @@ __device__ inline void auc_scan_row_lists(const AuctionArgs& a, int i, long long
     long long lv1, lv2;
     int lj1;
     auc_lane_scan<kSeqThreads>(a, i, lv1, lj1, lv2);
-    long long b1 = lv1;
+    long long b1 = lv1, d1 = LLONG_MIN;
     int bj1 = lj1;
-    auc_wave_best(b1, bj1);
+    auc_wave_merge(b1, bj1, d1);
     // a column belongs to one thread, so the winner is the thread holding
     // bj1 (threads without columns hold INT_MAX and LLONG_MIN: harmless)
     const bool w1 = lj1 == bj1;
     const long long cv = w1 ? LLONG_MIN : lv1;
     const int cjj = w1 ? INT_MAX : lj1;
-    long long b2 = cv;
+    long long b2 = cv, d2 = LLONG_MIN;
     int bj2 = cjj;
-    auc_wave_best(b2, bj2);
+    auc_wave_merge(b2, bj2, d2);
     long long rest = cjj == bj2 ? LLONG_MIN : cv;
     rest = rest > lv2 ? rest : lv2;
     const long long tw = auc_wave_max(rest);
@@ -406,25 +460,22 @@ __device__ inline void auc_scan_row_lists(const AuctionArgs& a, int i, long long
             a.cj[(long)i * kCand + lane] = ok ? ej : -1;
             a.cc[(long)i * kCand + lane] = ok ? ev + a.price[ej] : 0;
         }
-        if (lane == 0) {
-            v1 = se1[0];
-            j1 = sje1[0];
-            int wb = 0;
-            for (int ww = 1; ww < kSeqThreads / 64; ++ww)
-                if (auc_better(se1[ww], sje1[ww], v1, j1)) {
-                    v1 = se1[ww];
-                    j1 = sje1[ww];
-                    wb = ww;
-                }
-            long long T = LLONG_MIN;
-            v2 = LLONG_MIN;
-            for (int ww = 0; ww < kSeqThreads / 64; ++ww) {
-                T = stw[ww] > T ? stw[ww] : T;
-                const long long o = ww == wb ? (se2[ww] > stw[ww] ? se2[ww] : stw[ww]) : se1[ww];
-                v2 = o > v2 ? o : v2;
-            }
-            a.thr[i] = T;
+        // the row's exact result: wave w's top two are e1 and max(e2, tw),
+        // so merging those pairs over the waves gives (v1, j1, v2); lane w
+        // takes wave w, one row merges
+        long long tw_l = LLONG_MIN;
+        v1 = LLONG_MIN;
+        v2 = LLONG_MIN;
+        j1 = INT_MAX;
+        if (lane < kSeqThreads / 64) {
+            v1 = se1[lane];
+            j1 = sje1[lane];
+            tw_l = stw[lane];
+            v2 = se2[lane] > tw_l ? se2[lane] : tw_l;
         }
+        auc_row_merge(v1, j1, v2);
+        const long long T = auc_row_max(tw_l);
+        if (lane == 0) a.thr[i] = T;
     }
 }
 
@@ -449,13 +500,7 @@ __device__ inline bool auc_try_list(const AuctionArgs& a, int i, long long& v1, 
         v1 = sc - a.price[c];
         j1 = c;
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const long long ov1 = __shfl_xor(v1, o, 64);
-        const long long ov2 = __shfl_xor(v2, o, 64);
-        const int oj1 = __shfl_xor(j1, o, 64);
-        auc_merge(v1, j1, v2, ov1, oj1, ov2);
-    }
+    auc_wave_merge(v1, j1, v2);
     return v1 > T && v2 >= T;
 }
 
