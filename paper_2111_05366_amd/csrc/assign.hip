@@ -594,11 +594,7 @@ __global__ __launch_bounds__(AB) void auction_keep_kernel(AuctionArgs a, long lo
             const long long v = a.cp ? a.cp[(long)i * a.ldc + j] - a.price[j] : auc_value(a, r[j], j);
             v1 = v > v1 ? v : v1;
         }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const long long ov = __shfl_xor(v1, o, 64);
-            v1 = ov > v1 ? ov : v1;
-        }
+        v1 = auc_wave_max(v1);
         if ((t & 63) == 0) sv[t >> 6] = v1;
         __syncthreads();
         if (t == 0) {
@@ -1083,16 +1079,6 @@ namespace {
 constexpr int BW = 64;                 // one wave per problem
 constexpr int kBatchLapMax = 1024;
 
-__device__ inline void wave_best(long long& v1, int& j1, long long& v2) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const long long ov1 = __shfl_xor(v1, o, 64);
-        const long long ov2 = __shfl_xor(v2, o, 64);
-        const int oj1 = __shfl_xor(j1, o, 64);
-        auc_merge(v1, j1, v2, ov1, oj1, ov2);
-    }
-}
-
 __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restrict__ probs, int proj,
                                                            const int* __restrict__ offs, int32_t* __restrict__ perms,
                                                            int* __restrict__ status, long long budget, int theta) {
@@ -1168,11 +1154,7 @@ __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restri
                     const long long v = auc_cost(a, M[i * ld + j]) - price[j];
                     v1 = v > v1 ? v : v1;
                 }
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    const long long ov = __shfl_xor(v1, o, 64);
-                    v1 = ov > v1 ? ov : v1;
-                }
+                v1 = auc_wave_max(v1);
                 if (t == 0 && v1 - (auc_cost(a, M[i * ld + ja]) - price[ja]) > eps) {
                     assign[i] = -1;
                     owner[ja] = -1;
@@ -1193,7 +1175,7 @@ __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restri
             long long v1 = LLONG_MIN, v2 = LLONG_MIN;
             int j1 = INT_MAX;
             for (int j = t; j < n; j += BW) auc_push(v1, j1, v2, auc_cost(a, M[i * ld + j]) - price[j], j);
-            wave_best(v1, j1, v2);
+            auc_wave_merge(v1, j1, v2);
             if (t == 0) {
                 const long long bid = price[j1] + (v1 - v2) + eps;
                 const int old = owner[j1];
