@@ -158,7 +158,7 @@ def main():
     ap.add_argument("--host-lap", action="store_true", help="final assignment on the host instead of the device")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: the solver runs on one GPU; a run over several GPUs is not supported "
               "(use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
