@@ -99,11 +99,14 @@ print(json.dumps([st.rounds, st.tail_bids, st.phases, st.list_bids]))
 """
 
 
-@pytest.mark.parametrize("kind,n", [("ds", 1500), ("flat", 2000)])
-def test_lap_device_candidate_lists_change_nothing(G, kind, n, tmp_path):
+@pytest.mark.parametrize("kind,n,switch", [("ds", 1500, "GOAT_LAP_LISTS=0"), ("flat", 2000, "GOAT_LAP_LISTS=0"),
+                                           ("flat", 2000, "GOAT_LAP_SEQ_GLOBAL=1")])
+def test_lap_device_variants_change_nothing(G, kind, n, switch, tmp_path):
     # a bid decided by the row's candidate list is the bid a full scan
-    # gives: with the lists switched off (in a fresh process, the switch is
-    # read once) every count and the permutation are the same
+    # gives, and the sequential kernel's state in global memory (the path
+    # taken above about 10,000 vertices) gives the bids of the LDS state:
+    # with the switch set (in a fresh process, switches are read once)
+    # every count and the permutation are the same
     import json
     import os
     import subprocess
@@ -114,12 +117,16 @@ def test_lap_device_candidate_lists_change_nothing(G, kind, n, tmp_path):
     assert st.list_bids > 0
     np.save(tmp_path / "M.npy", M)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    env = dict(os.environ, GOAT_LAP_LISTS="0")
+    key, val = switch.split("=")
+    env = dict(os.environ, **{key: val})
     out = subprocess.run([sys.executable, "-c", _LISTS_OFF, root, str(tmp_path / "M.npy"), str(tmp_path / "p.npy")],
                          env=env, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr[-2000:]
     rounds, tail, phases, listed = json.loads(out.stdout.strip().splitlines()[-1])
-    assert listed == 0
+    if key == "GOAT_LAP_LISTS":
+        assert listed == 0
+    else:
+        assert listed == st.list_bids
     assert (rounds, tail, phases) == (st.rounds, st.tail_bids, st.phases)
     assert np.array_equal(np.load(tmp_path / "p.npy").astype(np.int64), perm)
 
