@@ -254,9 +254,11 @@ int  goat_run_gradient(goat_run* run, float* G_out, int ldg);
 
 /*
  * Kernel timing hook (measurement only). which = 0: Sinkhorn row sweep;
- * which = 1: gradient product (one matrix-core launch). With stride > 0,
- * every stride-th such launch made by the calling thread is bracketed by
- * HIP events on its stream (at most 8192 sampled launches are kept).
+ * which = 1: gradient product. With stride > 0, every stride-th such launch
+ * made by the calling thread is timed (at most 8192 samples are kept): a
+ * row sweep by events that its launch itself records at the kernel's start
+ * and end (hipExtLaunchKernel), a product (its matrix-core launches) by
+ * events recorded on its stream before and after.
  * goat_profile_read waits for the sampled launches, returns their summed
  * duration (ms) and count, and clears the samples. stride = 0 disables.
  */

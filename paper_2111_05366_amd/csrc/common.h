@@ -263,6 +263,10 @@ GradOps grad_ops(const Ptrs& p);
 // 1 gradient product
 void prof_begin(int which, hipStream_t s);
 void prof_end(int which, hipStream_t s);
+// events for a sampled launch to hand to hipExtLaunchKernel (false and null
+// events when this launch is not sampled); prof_commit after the launch
+bool prof_sample(int which, hipEvent_t* start, hipEvent_t* stop);
+void prof_commit(int which);
 
 // Learned warm start (mlp.hip)
 int mlp_param_count();

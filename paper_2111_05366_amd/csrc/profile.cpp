@@ -1,6 +1,10 @@
 // Sampled per-launch timing with HIP events on the launch stream, for two
 // kernel families: 0 = Sinkhorn row sweep, 1 = gradient product. Per calling
-// thread; off unless goat_profile_enable() set a stride.
+// thread; off unless goat_profile_enable() set a stride. The row sweep's
+// events are taken by the launch itself (prof_sample / prof_commit with
+// hipExtLaunchKernel: the kernel's own start and end); a gradient product
+// (two launches) is bracketed by events recorded on the stream
+// (prof_begin / prof_end).
 #include <utility>
 #include <vector>
 
@@ -40,6 +44,33 @@ void prof_end(int which, hipStream_t s) {
     Prof& P = g_prof[which];
     if (!P.open) return;
     if (hipEventRecord(P.pool[P.used].second, s) == hipSuccess) P.used += 1;
+    P.open = false;
+}
+
+bool prof_sample(int which, hipEvent_t* start, hipEvent_t* stop) {
+    Prof& P = g_prof[which];
+    *start = *stop = nullptr;
+    P.open = false;
+    if (P.stride <= 0) return false;
+    if ((P.counter++ % P.stride) != 0 || P.used >= kMaxPairs) return false;
+    if (P.used == P.pool.size()) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess) return false;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return false;
+        }
+        P.pool.emplace_back(a, b);
+    }
+    *start = P.pool[P.used].first;
+    *stop = P.pool[P.used].second;
+    P.open = true;
+    return true;
+}
+
+void prof_commit(int which) {
+    Prof& P = g_prof[which];
+    if (P.open) P.used += 1;
     P.open = false;
 }
 

@@ -36,6 +36,8 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace goat {
@@ -558,17 +560,28 @@ bool allow_lds(K kfn, size_t bytes) {
 }
 
 template <int T, int C, bool FIRST, bool PRECISE>
-void launch_row_TCP(const Geometry& g, const SkArgs& a, hipStream_t s) {
+void launch_row_TCP(const Geometry& g, const SkArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const size_t lds = (size_t)(PRECISE ? 32 : 16) * T * C;
     static const bool vlds = allow_lds(sk_row_kernel<T, C, FIRST, PRECISE, true>, lds);
+    if (e0) {
+        // a sampled launch: the events mark the kernel's own start and end
+        if (vlds)
+            hipExtLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, true>), dim3(g.W), dim3(T), (uint32_t)lds, s,
+                                  e0, e1, 0, a);
+        else
+            hipExtLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, false>), dim3(g.W), dim3(T), 0, s, e0, e1, 0,
+                                  a);
+        return;
+    }
     if (vlds) hipLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, true>), dim3(g.W), dim3(T), lds, s, a);
     else hipLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, false>), dim3(g.W), dim3(T), 0, s, a);
 }
 
 template <int T, bool FIRST>
-int launch_row_T(const Geometry& g, const SkArgs& a, hipStream_t s) {
+int launch_row_T(const Geometry& g, const SkArgs& a, hipStream_t s, hipEvent_t e0 = nullptr,
+                 hipEvent_t e1 = nullptr) {
     switch (g.C) {
-#define GOAT_SK_C(CC) case CC: launch_row_TCP<T, CC, FIRST, !FIRST>(g, a, s); break;
+#define GOAT_SK_C(CC) case CC: launch_row_TCP<T, CC, FIRST, !FIRST>(g, a, s, e0, e1); break;
         GOAT_SK_C(1) GOAT_SK_C(2) GOAT_SK_C(3) GOAT_SK_C(4) GOAT_SK_C(5) GOAT_SK_C(6)
         GOAT_SK_C(8) GOAT_SK_C(10) GOAT_SK_C(12) GOAT_SK_C(16)
 #undef GOAT_SK_C
@@ -635,11 +648,15 @@ int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, in
     SkArgs a = make_args(n, np, G, ldg, st, g);
     a.rev = iter & 1;
     int rc;
-    prof_begin(0, s);
-    if (g.T == 256) rc = first ? launch_row_T<256, true>(g, a, s) : launch_row_T<256, false>(g, a, s);
-    else if (g.T == 512) rc = first ? launch_row_T<512, true>(g, a, s) : launch_row_T<512, false>(g, a, s);
-    else rc = first ? launch_row_T<1024, true>(g, a, s) : launch_row_T<1024, false>(g, a, s);
-    prof_end(0, s);
+    hipEvent_t e0, e1;
+    const bool sampled = prof_sample(0, &e0, &e1);
+    if (g.T == 256)
+        rc = first ? launch_row_T<256, true>(g, a, s, e0, e1) : launch_row_T<256, false>(g, a, s, e0, e1);
+    else if (g.T == 512)
+        rc = first ? launch_row_T<512, true>(g, a, s, e0, e1) : launch_row_T<512, false>(g, a, s, e0, e1);
+    else
+        rc = first ? launch_row_T<1024, true>(g, a, s, e0, e1) : launch_row_T<1024, false>(g, a, s, e0, e1);
+    if (sampled && rc == GOAT_OK) prof_commit(0);
     if (rc) return rc;
     hipLaunchKernelGGL(sk_merge_kernel, dim3((n + 31) / 32), dim3(256), 0, s, a, g.W, check);
     GOAT_HIP(hipGetLastError());
