@@ -312,7 +312,7 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
  * few are left, or a batch of rounds assigns few rows, one workgroup takes
  * the bids in sequence; each phase keeps the pairs that stay optimal to
  * within the new epsilon. A bid in sequence first tries the row's list of
- * 32 candidate columns, kept from its last scan with a bound on every
+ * 64 candidate columns, kept from its last scan with a bound on every
  * other column's value (prices only rise, so the bound holds); only when
  * the list cannot decide the bid is the row scanned again. With 2^(e-1) <= max|M| < 2^e,
  * R = min(40, 55 - ceil(log2(n+1))) and s = R - 1 - e, the scores are

@@ -176,7 +176,9 @@ constexpr int AB = 256;             // threads per block
 constexpr long long kBidLimit = 1ll << 62;
 constexpr int kNoRow = 0x7fffffff;
 constexpr int kSeqThreads = 1024;   // threads of the sequential kernel
-constexpr int kCand = 2 * (kSeqThreads / 64);   // candidate slots per row: two per wave of that kernel
+constexpr int kPerWave = 4;          // candidates each wave of that kernel contributes
+constexpr int kCand = kPerWave * (kSeqThreads / 64);   // candidate slots per row (64: one per lane of a wave)
+static_assert(kCand == 64, "wave 0 holds one candidate per lane");
 
 struct AuctionArgs {
     const float* M;
@@ -414,64 +416,64 @@ __device__ inline void auc_scan_row(const AuctionArgs& a, int i, long long& v1, 
 }
 
 // Full scan of row i by the kSeqThreads threads of the sequential kernel,
-// with a refresh of the row's candidate list. Each wave contributes the two
-// best of its threads' maxima (e1, e2) and the largest value outside them
-// (tw: the other threads' maxima and every thread's second value). The
-// candidates are the e1, e2 of all waves; no other column is worth more
-// than thr_i = max_w tw, and since prices only rise this stays true for
-// the rest of the auction. Writes the list (slot k by lane k of wave 0);
-// the row's exact (v1, j1, v2), as auc_scan_row gives them, end in
-// thread 0.
+// with a refresh of the row's candidate list. Each wave contributes the
+// kPerWave best of its threads' maxima (e_1 .. e_k) and the largest value
+// outside them (tw: the other threads' maxima and every thread's second
+// value). The candidates are the e of all waves; no other column is worth
+// more than thr_i = max_w tw, and since prices only rise this stays true
+// for the rest of the auction. Writes the list (slot k by lane k of wave
+// 0); the row's exact (v1, j1, v2), as auc_scan_row gives them, end in
+// thread 0. se / sje: LDS [kPerWave][waves], stw: LDS [waves].
 __device__ inline void auc_scan_row_lists(const AuctionArgs& a, int i, long long& v1, int& j1, long long& v2,
-                                          long long* se1, int* sje1, long long* se2, int* sje2,
+                                          long long (*se)[kSeqThreads / 64], int (*sje)[kSeqThreads / 64],
                                           long long* stw) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     long long lv1, lv2;
     int lj1;
     auc_lane_scan<kSeqThreads>(a, i, lv1, lj1, lv2);
-    long long b1 = lv1, d1 = LLONG_MIN;
-    int bj1 = lj1;
-    auc_wave_merge(b1, bj1, d1);
-    // a column belongs to one thread, so the winner is the thread holding
-    // bj1 (threads without columns hold INT_MAX and LLONG_MIN: harmless)
-    const bool w1 = lj1 == bj1;
-    const long long cv = w1 ? LLONG_MIN : lv1;
-    const int cjj = w1 ? INT_MAX : lj1;
-    long long b2 = cv, d2 = LLONG_MIN;
-    int bj2 = cjj;
-    auc_wave_merge(b2, bj2, d2);
-    long long rest = cjj == bj2 ? LLONG_MIN : cv;
-    rest = rest > lv2 ? rest : lv2;
-    const long long tw = auc_wave_max(rest);
-    if (lane == 0) {
-        se1[w] = b1;
-        sje1[w] = bj1;
-        se2[w] = b2;
-        sje2[w] = bj2;
-        stw[w] = tw;
+    // a column belongs to one thread, so each round's winner is the thread
+    // holding its column (threads without columns hold INT_MAX and
+    // LLONG_MIN: harmless), which then drops out
+    long long cv = lv1;
+    int cjj = lj1;
+#pragma unroll
+    for (int k = 0; k < kPerWave; ++k) {
+        long long b = cv, d = LLONG_MIN;
+        int bj = cjj;
+        auc_wave_merge(b, bj, d);
+        if (lane == 0) {
+            se[k][w] = b;
+            sje[k][w] = bj;
+        }
+        const bool won = cjj == bj;
+        cv = won ? LLONG_MIN : cv;
+        cjj = won ? INT_MAX : cjj;
     }
+    const long long rest = cv > lv2 ? cv : lv2;
+    const long long tw = auc_wave_max(rest);
+    if (lane == 0) stw[w] = tw;
     __syncthreads();
     if (w == 0) {
-        if (lane < kCand) {
-            const int ww = lane >> 1;
-            const long long ev = (lane & 1) ? se2[ww] : se1[ww];
-            const int ej = (lane & 1) ? sje2[ww] : sje1[ww];
+        {
+            const int ww = lane / kPerWave, k = lane % kPerWave;
+            const long long ev = se[k][ww];
+            const int ej = sje[k][ww];
             const bool ok = ej >= 0 && ej < a.n;
             a.cj[(long)i * kCand + lane] = ok ? ej : -1;
             a.cc[(long)i * kCand + lane] = ok ? ev + a.price[ej] : 0;
         }
-        // the row's exact result: wave w's top two are e1 and max(e2, tw),
-        // so merging those pairs over the waves gives (v1, j1, v2); lane w
-        // takes wave w, one row merges
+        // the row's exact result: wave w's top two are e_1 and max(e_2, tw)
+        // (e_3 .. e_k are at most e_2), so merging those pairs over the
+        // waves gives (v1, j1, v2); lane w takes wave w, one row merges
         long long tw_l = LLONG_MIN;
         v1 = LLONG_MIN;
         v2 = LLONG_MIN;
         j1 = INT_MAX;
         if (lane < kSeqThreads / 64) {
-            v1 = se1[lane];
-            j1 = sje1[lane];
+            v1 = se[0][lane];
+            j1 = sje[0][lane];
             tw_l = stw[lane];
-            v2 = se2[lane] > tw_l ? se2[lane] : tw_l;
+            v2 = se[1][lane] > tw_l ? se[1][lane] : tw_l;
         }
         auc_row_merge(v1, j1, v2);
         const long long T = auc_row_max(tw_l);
@@ -671,7 +673,9 @@ __global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs g, int* __r
     __shared__ int qn, cur, shit;
     __shared__ int wcnt[TB / 64];
     __shared__ long long sv1[TB / 64], sv2[TB / 64], stw[TB / 64];
-    __shared__ int sj1[TB / 64], sje2[TB / 64];
+    __shared__ int sj1[TB / 64];
+    __shared__ long long se[kPerWave][TB / 64];
+    __shared__ int sje[kPerWave][TB / 64];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     AuctionArgs a = g;
     if (LDSST) {
@@ -734,8 +738,7 @@ __global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs g, int* __r
             if (hit) {
                 hits += t == 0;
             } else {
-                // sv1/sj1 hold e1 of each wave, sv2/sje2 e2
-                auc_scan_row_lists(a, i, v1, j1, v2, sv1, sj1, sv2, sje2, stw);
+                auc_scan_row_lists(a, i, v1, j1, v2, se, sje, stw);
             }
         } else {
             skip -= skip > 0;
@@ -854,7 +857,9 @@ const LapKnobs& lap_knobs() {
     return k;
 }
 
-constexpr size_t kSeqLdsMax = 159 * 1024;     // dynamic LDS of the sequential kernel, at most
+// dynamic LDS of the sequential kernel, at most: 160 KB per workgroup less
+// 2 KB for its static arrays
+constexpr size_t kSeqLdsMax = 160 * 1024 - 2048;
 
 // LDS bytes of the sequential kernel's state for n vertices, or 0 when it
 // does not fit (the state then stays in global memory)
