@@ -324,8 +324,9 @@ int goat_lap_max(int n, const double* M_host, int ld, int32_t* perm_host);
  *  ws         device workspace of goat_lap_device_workspace_size(n) bytes
  *             (about 8 n^2: the scaled scores are precomputed once as int64
  *             and every scan reads them), or at least
- *             goat_lap_device_workspace_min(n) bytes (about 450 n: every
- *             scan converts M again). Both give the same result.
+ *             goat_lap_device_workspace_min(n) bytes (about 820 n, most of
+ *             it the candidate lists: every scan converts M again). Both
+ *             give the same result.
  *  max_rounds cap on parallel rounds plus tail bids over all phases
  *             (<= 0: 20,000,000).
  *  stats      host goat_lap_stats (may be NULL).
