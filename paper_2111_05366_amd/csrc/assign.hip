@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <cstdlib>
 #include <vector>
 
@@ -583,10 +584,12 @@ __global__ __launch_bounds__(AB) void auction_resolve_kernel(AuctionArgs a) {
 // still satisfies eps-complementary slackness for the new, smaller eps
 // (its value is within eps of the row's best); later price rises only make
 // other objects worse, so kept pairs stay valid. Other rows are released.
-// ctl[0] counts the kept rows (the reset before this kernel zeroed it).
+// ctl[0] counts the kept rows and the int64 at ctl + 8 receives the largest
+// slack v1 - va among them (the reset before this kernel zeroed both).
 __global__ __launch_bounds__(AB) void auction_keep_kernel(AuctionArgs a, long long eps) {
     __shared__ long long sv[AB / 64];
     const int t = threadIdx.x;
+    long long dmax = -1;         // thread 0: largest kept slack of this block's rows
     for (int i = blockIdx.x; i < a.n; i += gridDim.x) {
         const int ja = a.assign[i];
         if (ja < 0) continue;
@@ -607,10 +610,12 @@ __global__ __launch_bounds__(AB) void auction_keep_kernel(AuctionArgs a, long lo
                 a.owner[ja] = -1;
             } else {
                 atomicAdd(&a.ctl[0], 1);
+                dmax = v1 - va > dmax ? v1 - va : dmax;
             }
         }
         __syncthreads();
     }
+    if (t == 0 && dmax >= 0) atomicMax(reinterpret_cast<unsigned long long*>(a.ctl + 8), (unsigned long long)dmax);
 }
 
 // Scaled integer scores c'_ij = (rint(M_ij 2^s) - qmin) (n + 1), written once
@@ -629,6 +634,7 @@ __global__ __launch_bounds__(AB) void auction_reset_kernel(AuctionArgs a, int mo
     const int j = blockIdx.x * AB + threadIdx.x;
     if (j == 0) {
         a.ctl[0] = 0;
+        *reinterpret_cast<unsigned long long*>(a.ctl + 8) = 0;
         if (mode == 0) {
             a.ctl[1] = 0;
             a.ctl[2] = 0;
@@ -838,9 +844,11 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // eps-optimal), GOAT_LAP_BITS (score resolution R, default and maximum 40),
 // GOAT_LAP_SEQ_GLOBAL=1 (sequential bids keep their state in global memory),
 // GOAT_LAP_LISTS=0 (sequential bids always scan the whole row),
+// GOAT_LAP_SKIP_IDLE=0 (run every phase, also those that would keep every
+// pair),
 // GOAT_LAP_TRACE=1 (per-phase counts on stderr).
 struct LapKnobs {
-    int tail = 32, theta = 3, trace = 0, keep = 1, rate = 2, seq_global = 0, lists = 1;
+    int tail = 32, theta = 3, trace = 0, keep = 1, rate = 2, seq_global = 0, lists = 1, skip_idle = 1;
 };
 const LapKnobs& lap_knobs() {
     static const LapKnobs k = [] {
@@ -852,6 +860,7 @@ const LapKnobs& lap_knobs() {
         if (const char* e = std::getenv("GOAT_LAP_KEEP")) r.keep = std::atoi(e) != 0;
         if (const char* e = std::getenv("GOAT_LAP_SEQ_GLOBAL")) r.seq_global = std::atoi(e) != 0;
         if (const char* e = std::getenv("GOAT_LAP_LISTS")) r.lists = std::atoi(e) != 0;
+        if (const char* e = std::getenv("GOAT_LAP_SKIP_IDLE")) r.skip_idle = std::atoi(e) != 0;
         return r;
     }();
     return k;
@@ -987,7 +996,7 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     const size_t seq_lds = seq_lds_bytes(n);
     const long long cbig = cmax * a.np1;
     long long eps = std::max(1ll, cbig / 4);
-    int ctl[5] = {0, 0, 0, 0, 0};
+    int ctl[12] = {0};           // device ctl[0..4]; ctl[8..9]: the keep filter's largest slack (int64)
     long long work = 0;          // parallel rounds launched + sequential budgets
     const LapKnobs& kn = lap_knobs();
     int prev_rounds = 0, prev_seq = 0, prev_hits = 0;
@@ -995,6 +1004,8 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
     for (;;) {
         ++loc.phases;
         int left = n;
+        bool idle = false;       // the phase filter kept every pair: no bid in this phase
+        long long slack = 0;
         if (loc.phases > 1) {
             hipLaunchKernelGGL(auction_reset_kernel, dim3(gr), dim3(AB), 0, s, a, kn.keep ? 2 : 1);
             if (kn.keep) hipLaunchKernelGGL(auction_keep_kernel, dim3(gb), dim3(AB), 0, s, a, eps);
@@ -1003,6 +1014,8 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
                 GOAT_HIP(hipMemcpyAsync(ctl, a.ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
                 GOAT_HIP(hipStreamSynchronize(s));
                 left = n - ctl[0];
+                idle = left == 0;
+                std::memcpy(&slack, &ctl[8], sizeof(slack));
             }
         }
         int batch = 4;
@@ -1059,6 +1072,22 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
         }
         if (eps == 1) break;
         eps = std::max(1ll, eps / kn.theta);
+        // No bid ran in an idle phase, so prices and slacks are what its
+        // filter measured: every later phase whose eps is at least the
+        // largest slack would keep every pair and bid nothing. Those phases
+        // are counted and passed over.
+        if (idle && kn.skip_idle) {
+            bool done = false;
+            while (slack <= eps) {
+                ++loc.phases;
+                if (eps == 1) {
+                    done = true;
+                    break;
+                }
+                eps = std::max(1ll, eps / kn.theta);
+            }
+            if (done) break;
+        }
     }
     loc.rounds = ctl[2];
     loc.tail_bids = ctl[3];
