@@ -1115,7 +1115,8 @@ constexpr int kBatchLapMax = 1024;
 
 __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restrict__ probs, int proj,
                                                            const int* __restrict__ offs, int32_t* __restrict__ perms,
-                                                           int* __restrict__ status, long long budget, int theta) {
+                                                           int* __restrict__ status, long long budget, int theta,
+                                                           int skip_idle) {
     __shared__ long long price[kBatchLapMax];
     __shared__ int owner[kBatchLapMax], assign[kBatchLapMax], queue[kBatchLapMax];
     __shared__ int qn;
@@ -1177,10 +1178,14 @@ __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restri
     }
     long long eps = max(1ll, cmax * a.np1 / 4);
     long long bids = 0;
+    __shared__ long long sdmax;
     bool first = true;
     for (;;) {
-        // phase start: rows whose pair is no longer eps-optimal are released
-        if (!first) {
+        // phase start: rows whose pair is no longer eps-optimal are released;
+        // sdmax: the largest slack among the kept pairs
+        const bool filtered = !first;
+        if (filtered) {
+            long long dmax = -1;
             for (int i = 0; i < n; ++i) {
                 const int ja = assign[i];
                 long long v1 = LLONG_MIN;
@@ -1189,11 +1194,17 @@ __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restri
                     v1 = v > v1 ? v : v1;
                 }
                 v1 = auc_wave_max(v1);
-                if (t == 0 && v1 - (auc_cost(a, M[i * ld + ja]) - price[ja]) > eps) {
-                    assign[i] = -1;
-                    owner[ja] = -1;
+                if (t == 0) {
+                    const long long d = v1 - (auc_cost(a, M[i * ld + ja]) - price[ja]);
+                    if (d > eps) {
+                        assign[i] = -1;
+                        owner[ja] = -1;
+                    } else {
+                        dmax = d > dmax ? d : dmax;
+                    }
                 }
             }
+            if (t == 0) sdmax = dmax;
             __syncthreads();
         }
         first = false;
@@ -1204,6 +1215,7 @@ __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restri
             qn = c;
         }
         __syncthreads();
+        const int qn0 = qn;
         while (qn > 0 && bids < budget) {
             const int i = queue[0];
             long long v1 = LLONG_MIN, v2 = LLONG_MIN;
@@ -1231,8 +1243,24 @@ __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restri
             if (t == 0) status[k] = GOAT_ENOTSUP;
             return;
         }
+        // the filter kept every pair (idle = no row was queued): phases whose
+        // eps is at least the largest slack would keep every pair too and
+        // bid nothing; they are passed over (as in auction_lap)
+        const bool idle = filtered && qn0 == 0;
         if (eps == 1) break;
         eps = max(1ll, eps / theta);
+        if (idle && skip_idle) {
+            const long long d = sdmax;
+            bool done = false;
+            while (d <= eps) {
+                if (eps == 1) {
+                    done = true;
+                    break;
+                }
+                eps = max(1ll, eps / theta);
+            }
+            if (done) break;
+        }
     }
     for (int i = t; i < n; i += BW) out[i] = assign[i];
     if (t == 0) status[k] = bids > INT_MAX ? INT_MAX : (int)bids;
@@ -1244,7 +1272,7 @@ int batch_auction_launch(const BProb* probs_dev, int nprob, int proj, const int*
                          int* status_dev, long long budget, hipStream_t s) {
     if (nprob < 1) return GOAT_OK;
     hipLaunchKernelGGL(batch_auction_kernel, dim3(nprob), dim3(BW), 0, s, probs_dev, proj, offs_dev, perms_dev,
-                       status_dev, budget, lap_knobs().theta);
+                       status_dev, budget, lap_knobs().theta, lap_knobs().skip_idle);
     GOAT_HIP(hipGetLastError());
     return GOAT_OK;
 }

@@ -223,3 +223,41 @@ def test_batch_nonfinite_pair_rejected(G):
     with pytest.raises(G.GoatError) as e:
         G.Batch([(dev(graphs[0].A), dev(graphs[0].B)), (dev(graphs[1].A), dev(B1))], restarts=1, sk_max=50)
     assert e.value.status == G.GOAT_EINVAL and "pair 1" in str(e.value)
+
+
+_SKIP_OFF = """
+import sys, json
+import numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+from paper_2111_05366_amd import goat, inputs as I
+specs = [(40, 0.2, 0.9, 21), (130, 0.1, 0.9, 22), (257, 0.05, 0.95, 23)]
+pairs = []
+for k, (n, p, rho, s) in enumerate(specs):
+    g = I.rho_er_pair(n, p, rho, s)
+    U = I.uniform_matrix(2 * n, 900 + k)[:, :n]
+    pairs.append(tuple(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda")
+                       for x in (g.A, g.B, U)))
+b = goat.Batch(pairs, restarts=2, sk_max=300, fw_max=12, lap=1)
+b.launch()
+out = b.results()
+print(json.dumps([np.asarray(p).tolist() for p in out["perm"]]))
+"""
+
+
+def test_batch_device_assignment_skip_changes_nothing(tmp_path):
+    # phases passed over because their filter would keep every pair change
+    # nothing: the same batch with GOAT_LAP_SKIP_IDLE=0 (a fresh process:
+    # switches are read once) returns the same permutations
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    outs = []
+    for env_val in ("1", "0"):
+        env = dict(os.environ, GOAT_LAP_SKIP_IDLE=env_val)
+        r = subprocess.run([sys.executable, "-c", _SKIP_OFF, root], env=env, capture_output=True, text=True,
+                           timeout=180)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    assert outs[0] == outs[1]
