@@ -669,6 +669,7 @@ constexpr int TB = kSeqThreads;
 // (16 bytes per vertex, dynamic shared memory), copied in at the start and
 // back at the end, so the scan's price reads and the updates of the bidding
 // thread stay on the CU.
+//
 // With `lists`, a bid first tries the row's candidate list (auc_try_list)
 // and scans the row only when the list cannot decide it; the scan then
 // refreshes the list. Both give the same bid.
@@ -676,7 +677,7 @@ template <bool LDSST>
 __global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs g, int* __restrict__ q, long long eps,
                                                         long long budget, int lists) {
     extern __shared__ __attribute__((aligned(16))) unsigned char seq_smem[];
-    __shared__ int qn, cur, shit;
+    __shared__ int qn, cur, list_hit;
     __shared__ int wcnt[TB / 64];
     __shared__ long long sv1[TB / 64], sv2[TB / 64], stw[TB / 64];
     __shared__ int sj1[TB / 64];
@@ -730,10 +731,10 @@ __global__ __launch_bounds__(TB) void auction_seq_kernel(AuctionArgs g, int* __r
         if (lists && skip == 0) {
             if (w == 0) {
                 const bool hit = auc_try_list(a, i, v1, j1, v2);
-                if (lane == 0) shit = hit;
+                if (lane == 0) list_hit = hit;
             }
             __syncthreads();
-            const bool hit = shit;
+            const bool hit = list_hit;
             ++tries;
             wins += hit;
             if (tries == kListWindow) {
