@@ -93,12 +93,16 @@ def run_form(goat, A, B, n, form, warmup, steps, sk_max, sk_tol, prof_stride, ml
     run.close()
     hist = res.history[warmup:]
     sk_iters = [h["sk_iters"] for h in hist]
+    sk_err = [h["sk_err"] for h in hist]
     np_ = (n + 255) // 256 * 256
     gemm_exec_flops = (12 if prec == "bf16x3" else 4) * float(np_) ** 3   # per gradient (2 launches)
     out = dict(
         form=form, prec=prec, warm=warm,
         fw_iters_per_s=steps / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / steps,
         sk_iters_mean=sum(sk_iters) / len(sk_iters), sk_capped=sum(1 for s in sk_iters if s >= sk_max),
+        sk_converged=sum(1 for e in sk_err if e <= sk_tol),
+        sk_err_mean=sum(sk_err) / len(sk_err), sk_err_max=max(sk_err),
+        stalled_at=next((k + 1 for k, h in enumerate(res.history) if h["t"] == 0.0), None),
         sk_row_ms=sk_ms / max(sk_cnt, 1), sk_row_samples=sk_cnt,
         gemm_ms_per_grad=2 * gm_ms / max(gm_cnt, 1), gemm_samples=gm_cnt,
         gemm_exec_tflops=gemm_exec_flops / (2 * gm_ms / max(gm_cnt, 1) * 1e-3) / 1e12 if gm_cnt else None,
@@ -112,19 +116,38 @@ def run_form(goat, A, B, n, form, warmup, steps, sk_max, sk_tol, prof_stride, ml
     return out
 
 
+def host_info():
+    """nproc and the CPU model of the host the baseline runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo", encoding="utf-8") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return dict(nproc=os.cpu_count(), affinity=affinity, cpu_model=model)
+
+
 def cpu_baseline(pair, n, sk_iters_per_fw):
     """Time the FP64 oracle on a bounded sample of the same workload (about
-    15 s of CPU work): two gradients (at the barycenter and at the first
-    Sinkhorn direction's start) and six Sinkhorn sweeps, scaled to one FW
-    iteration (two gradients + the measured number of sweeps)."""
+    25 s of CPU work), scaled to one FW iteration (two gradients + the
+    measured number of Sinkhorn sweeps):
+      all threads: two gradients at n and six sweeps at n;
+      one thread : one gradient of the leading n/4 x n/4 block (scaled by
+                   64, the cube of the size ratio) and two sweeps at n.
+    The oracle's gradient is BLAS matrix products (threaded); its sweep is
+    numpy element-wise work (one thread either way)."""
     import numpy as np
     from oracle import goat_oracle as O
-    try:
-        import threadpoolctl
-        info = threadpoolctl.threadpool_info()
-        cores = max([d.get("num_threads", 1) for d in info] + [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    import threadpoolctl
+    info = threadpoolctl.threadpool_info()
+    cores = max([d.get("num_threads", 1) for d in info] + [1])
     A = pair.A.astype(np.float64)
     B = pair.B.astype(np.float64)
     P = O.barycenter(n)
@@ -137,10 +160,47 @@ def cpu_baseline(pair, n, sk_iters_per_fw):
     O.log_sinkhorn_max(G, eps, tol=0.0, max_iter=6)
     t_sk = (time.perf_counter() - t0) / 6
     t_fw = 2 * t_grad + sk_iters_per_fw * t_sk
+    m = n // 4
+    with threadpoolctl.threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.gradient(A[:m, :m], B[:m, :m], O.barycenter(m))
+        t_grad1 = (time.perf_counter() - t0) * (n / m) ** 3
+        t0 = time.perf_counter()
+        O.log_sinkhorn_max(G, eps, tol=0.0, max_iter=2)
+        t_sk1 = (time.perf_counter() - t0) / 2
+    t_fw1 = 2 * t_grad1 + sk_iters_per_fw * t_sk1
     return dict(value=1.0 / t_fw, unit="FW iters/s", cores=int(cores), kind="oracle",
                 sample=(f"n={n}: 2 oracle gradients ({t_grad:.1f} s each) + 6 oracle Sinkhorn sweeps "
                         f"({t_sk:.2f} s each), scaled to one FW iteration = 2 gradients + "
-                        f"{sk_iters_per_fw:.0f} sweeps (the GPU plain form's mean)"))
+                        f"{sk_iters_per_fw:.0f} sweeps (the GPU plain form's mean)"),
+                one_core=dict(value=1.0 / t_fw1, unit="FW iters/s", cores=1,
+                              sample=(f"one gradient of the leading {m}x{m} block x 64 ({t_grad1:.0f} s "
+                                      f"scaled) + 2 sweeps at n ({t_sk1:.2f} s each)")),
+                host=host_info())
+
+
+def oracle_gate(match_mixed):
+    """The oracle's final match ratio on this pair, from the stored run of
+    tests/golden/make_weighted_sbm_n10000.py (Alg. 3 as printed: cold
+    Sinkhorn starts, FP64, stop at the first zero step), and whether the
+    timed form lies within 0.005 of it."""
+    path = os.path.join(ROOT, "tests", "golden", "weighted_sbm_n10000_plain_run.json")
+    try:
+        with open(path, encoding="utf-8") as fh:
+            run = json.load(fh)
+    except (OSError, ValueError):
+        return dict(oracle_match_ratio=None, oracle_gate="unmeasured (no stored oracle run)")
+    if not run.get("complete"):
+        after = run.get("match_ratio_after", {})
+        last = max(after, key=int) if after else None
+        return dict(oracle_match_ratio=None,
+                    oracle_gate=(f"unmeasured (the stored oracle run is incomplete: "
+                                 f"{len(run.get('iterations', []))} FW iterations"
+                                 + (f", match ratio {after[last]:.4f} after {last}" if last else "") + ")"))
+    mr = run["match_ratio"]
+    return dict(oracle_match_ratio=mr, oracle_fw_iters=run["fw_iters"], oracle_stalled=run["stalled"],
+                oracle_gate="pass" if abs(match_mixed - mr) <= 0.005 else "fail",
+                match_ratio_gap_vs_oracle=round(abs(match_mixed - mr), 5))
 
 
 def main():
@@ -208,8 +268,8 @@ def main():
         log(f"cpu baseline {cpu['value']:.2e} FW it/s on {cpu['cores']} threads")
 
     def summary(f):
-        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in f.items()
-                if k not in ("perm", "t_hist")}
+        return {k: (v if k.startswith("sk_err") else round(v, 4) if isinstance(v, float) else v)
+                for k, v in f.items() if k not in ("perm", "t_hist")}
 
     line = {
         "metric": "FW iters/s at n=10k, mixed+warm-start vs plain FP32, at oracle match ratio",
@@ -234,6 +294,7 @@ def main():
                                       if plain and main_form is not plain else None),
             "match_ratio_gap_vs_plain": (round(abs(main_form["match_ratio"] - plain["match_ratio"]), 5)
                                          if plain and main_form is not plain else None),
+            **oracle_gate(main_form["match_ratio"]),
             "gemm_roofline": {
                 "bound": "mfma", "kernel": "gemm_nt (2 products per gradient; a product is the 256x256 launch plus the last-rows 128x128 launch)",
                 "achieved_exec": round(main_form["gemm_exec_tflops"], 1) if main_form["gemm_exec_tflops"] else None,

@@ -346,6 +346,10 @@ typedef struct goat_lap_stats {
     int resolution_bits;        /* R above                                  */
     int list_bids;              /* of the tail bids, those decided by the
                                    row's candidate list without a row scan */
+    int skipped_phases;         /* of the phases, those passed over without
+                                   a launch: an idle phase's filter kept every
+                                   pair, and these later phases' epsilon is
+                                   at least its largest slack            */
 } goat_lap_stats;
 size_t goat_lap_device_workspace_size(int n);
 size_t goat_lap_device_workspace_min(int n);
@@ -464,6 +468,8 @@ typedef struct goat_batch_stats {
     double ms_graph;       /* device time of the graph launch (HIP events)      */
     double ms_lap;         /* host time of all final assignments                */
     double ms_total;       /* wall time of goat_batch_results                   */
+    long long lap_bids;    /* device assignments (opt.lap = 1): bids summed over
+                              problems; 0 with the host solver                 */
 } goat_batch_stats;
 
 /*

@@ -41,6 +41,10 @@ Conventions (readings of points the paper leaves open are marked READING):
     by column).
   * READING (device assignment): the quantised scores the device solves
     exactly are defined in quantised_scores().
+  * READING (warm starts, not in the paper): a Sinkhorn solve may start from
+    column potentials g0 other than 0 (the previous FW iteration's g, or the
+    warm-start network's prediction, mlp_oracle.warm_start); the fixed point,
+    the stop rule and the cap are unchanged.
   * READING (seeds, unequal sizes): see the section of seeded_problem().
 """
 from __future__ import annotations
@@ -273,6 +277,15 @@ class GoatOptions:
     fw_max: int = 30
     fw_tol: float = 0.0
     proj: str = "P"           # "P" or "GRAD"
+    # Sinkhorn start (READING, warm starts): "cold" g0 = 0 every iteration;
+    # "prev" the previous iteration's g; "net" the warm-start network every
+    # iteration; "net_prev" the network on the first iteration, then "prev".
+    warm: str = "cold"
+    stop_on_stall: bool = True   # False: run fw_max iterations even after t == 0
+    # final assignment: "hungarian" (hungarian_max below) or "scipy" (SciPy's
+    # exact solver for the same maximisation, for sizes where the plain
+    # Python loop would take hours)
+    lap: str = "hungarian"
 
 
 @dataclass
@@ -282,18 +295,56 @@ class GoatResult:
     P: np.ndarray
     fw_iters: int
     history: list = field(default_factory=list)
+    start: int = 0             # goat_restarts: index of the kept start
 
 
-def goat(A, B, P0=None, opt: GoatOptions | None = None, record: bool = False) -> GoatResult:
+def sinkhorn_start(opt: GoatOptions, it: int, G, eps: float, g_prev, net):
+    """Column potentials g0 that start iteration `it`'s Sinkhorn solve
+    (READING, warm starts; the paper always starts cold). Any start leads to
+    the same fixed point; only the number of sweeps to reach it changes.
+    `net(G, eps)` returns the warm-start network's g0 (see
+    mlp_oracle.warm_start)."""
+    if opt.warm == "cold":
+        return None
+    if opt.warm == "prev" or (opt.warm == "net_prev" and it > 1):
+        return g_prev
+    if opt.warm in ("net", "net_prev"):
+        if net is None:
+            raise ValueError("a network start needs the network")
+        return net(G, eps)
+    raise ValueError(f"unknown warm start {opt.warm!r}")
+
+
+def assign_max(M, how: str = "hungarian") -> np.ndarray:
+    """perm maximising sum_i M[i, perm[i]]: hungarian_max, or SciPy's exact
+    solver of the same problem."""
+    if how == "hungarian":
+        return hungarian_max(M)
+    if how == "scipy":
+        from scipy.optimize import linear_sum_assignment
+        rows, cols = linear_sum_assignment(np.asarray(M, np.float64), maximize=True)
+        perm = np.empty(len(rows), dtype=np.int64)
+        perm[rows] = cols
+        return perm
+    raise ValueError(f"unknown assignment {how!r}")
+
+
+def goat(A, B, P0=None, opt: GoatOptions | None = None, record: bool = False,
+         net=None, keep_rows=None, callback=None) -> GoatResult:
     """Alg. 3 (GOAT): Frank-Wolfe on the relaxed problem with the LAP
     direction of FAQ (Alg. 1) replaced by LOT (Alg. 2), then one Hungarian
-    projection. The gradient is recomputed plainly each iteration."""
+    projection. The gradient is recomputed plainly each iteration.
+    `net`: the warm-start network for opt.warm "net" / "net_prev";
+    `keep_rows`: with record, the history also keeps these rows of Q;
+    `callback(history, P)`: with record, called after every iteration (for
+    long runs that report as they go)."""
     opt = opt or GoatOptions()
     A = np.asarray(A, np.float64); B = np.asarray(B, np.float64)
     n = A.shape[0]
     P = barycenter(n) if P0 is None else np.asarray(P0, np.float64).copy()
     hist = []
     it = 0
+    g_prev = None
     for it in range(1, opt.fw_max + 1):
         G = gradient(A, B, P)                                   # step 1
         gmax = float(np.max(np.abs(G)))
@@ -301,8 +352,10 @@ def goat(A, B, P0=None, opt: GoatOptions | None = None, record: bool = False) ->
         if eps == 0.0:
             Q = barycenter(n); sk_it = 0; sk_err = 0.0
         else:
-            sk = log_sinkhorn_max(G, eps, opt.sk_tol, opt.sk_max)   # step 2
+            g0 = sinkhorn_start(opt, it, G, eps, g_prev, net)
+            sk = log_sinkhorn_max(G, eps, opt.sk_tol, opt.sk_max, g0=g0)   # step 2
             Q, sk_it, sk_err = sk.Q, sk.iters, sk.err
+            g_prev = sk.g
         GQ = gradient(A, B, Q)
         ls = linesearch(P, Q, G, GQ)                            # step 3
         P = P + ls.t * (Q - P)                                  # step 4
@@ -311,10 +364,14 @@ def goat(A, B, P0=None, opt: GoatOptions | None = None, record: bool = False) ->
             hist.append(dict(it=it, eps=eps, sk_iters=sk_it, sk_err=sk_err,
                              t=ls.t, a=ls.a, b=ls.b, fP=ls.fP, fQ=ls.fQ, c=ls.c,
                              f_next=ls.fP + ls.b * ls.t + ls.a * ls.t ** 2))
-        if ls.t == 0.0 or (opt.fw_tol > 0.0 and delta < opt.fw_tol):
+            if keep_rows is not None:
+                hist[-1]["Q_rows"] = Q[np.asarray(keep_rows)].copy()
+            if callback is not None:
+                callback(hist, P)
+        if (ls.t == 0.0 and opt.stop_on_stall) or (opt.fw_tol > 0.0 and delta < opt.fw_tol):
             break
     M = P if opt.proj == "P" else gradient(A, B, P)
-    perm = hungarian_max(M)
+    perm = assign_max(M, opt.lap)
     return GoatResult(perm, qap_value(A, B, perm), P, it, hist)
 
 
@@ -323,8 +380,9 @@ def goat_restarts(A, B, inits, opt: GoatOptions | None = None) -> GoatResult:
     permutation with the largest tr(A^T Pi B Pi^T) is kept, ties to the
     earliest start."""
     best = None
-    for P0 in inits:
+    for k, P0 in enumerate(inits):
         r = goat(A, B, P0, opt)
+        r.start = k
         if best is None or r.score > best.score:
             best = r
     return best

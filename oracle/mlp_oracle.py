@@ -94,3 +94,32 @@ def adam_step(p, g, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8
         mh = m[k] / (1.0 - beta1 ** step)
         vh = v[k] / (1.0 - beta2 ** step)
         p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
+
+
+def unpack(flat):
+    """Parameter dict from the flat float32 vector the library stores
+    (W1[128][4], b1[128], W2[128][128], b2[128], W3[128], b3[1], row-major),
+    promoted exactly to float64."""
+    x = np.asarray(flat, np.float64).ravel()
+    sizes = [("W1", (H, NFEAT)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (1, H)), ("b3", (1,))]
+    p, o = {}, 0
+    for name, shape in sizes:
+        k = int(np.prod(shape))
+        p[name] = x[o:o + k].reshape(shape)
+        o += k
+    if o != x.size:
+        raise ValueError(f"{x.size} parameters, expected {o}")
+    return p
+
+
+def warm_start(G, eps, p):
+    """Column potentials g0 = eps * network(features of G / eps) that start a
+    warm Sinkhorn solve (the network predicts the centred g / eps)."""
+    y, _ = forward(p, column_features(G, eps))
+    return eps * y
+
+
+def network(flat):
+    """warm_start as a function of (G, eps), for goat_oracle.goat(net=...)."""
+    p = unpack(flat)
+    return lambda G, eps: warm_start(G, eps, p)

@@ -1081,6 +1081,7 @@ int auction_lap(int n, const float* M, int ld, int32_t* perm_dev, void* ws, size
             bool done = false;
             while (slack <= eps) {
                 ++loc.phases;
+                ++loc.skipped_phases;
                 if (eps == 1) {
                     done = true;
                     break;
@@ -1120,7 +1121,7 @@ __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restri
                                                            int skip_idle) {
     __shared__ long long price[kBatchLapMax];
     __shared__ int owner[kBatchLapMax], assign[kBatchLapMax], queue[kBatchLapMax];
-    __shared__ int qn;
+    __shared__ int qn, overflow;
     const int k = blockIdx.x, t = threadIdx.x;
     const BProb& q = probs[k];
     const int n = q.n;
@@ -1171,6 +1172,7 @@ __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restri
         owner[j] = -1;
         assign[j] = -1;
     }
+    if (t == 0) overflow = 0;
     __syncthreads();
     if (n == 1 || cmax == 0) {
         for (int i = t; i < n; i += BW) out[i] = i;
@@ -1224,23 +1226,32 @@ __global__ __launch_bounds__(BW) void batch_auction_kernel(const BProb* __restri
             for (int j = t; j < n; j += BW) auc_push(v1, j1, v2, auc_cost(a, M[i * ld + j]) - price[j], j);
             auc_wave_merge(v1, j1, v2);
             if (t == 0) {
+                // n >= 2, so both values are real. Prices stay far below the
+                // limit (c <= 2^40 scaled by n + 1 <= 1025, epsilon at most a
+                // quarter of that), but a bid past it would wrap: the
+                // problem then fails as in auction_lap
                 const long long bid = price[j1] + (v1 - v2) + eps;
-                const int old = owner[j1];
-                owner[j1] = i;
-                assign[i] = j1;
-                price[j1] = bid;
-                if (old >= 0) {
-                    assign[old] = -1;
-                    queue[0] = old;
+                if (bid >= kBidLimit) {
+                    overflow = 1;
+                    qn = 0;
                 } else {
-                    queue[0] = queue[qn - 1];
-                    qn = qn - 1;
+                    const int old = owner[j1];
+                    owner[j1] = i;
+                    assign[i] = j1;
+                    price[j1] = bid;
+                    if (old >= 0) {
+                        assign[old] = -1;
+                        queue[0] = old;
+                    } else {
+                        queue[0] = queue[qn - 1];
+                        qn = qn - 1;
+                    }
                 }
             }
             ++bids;
             __syncthreads();
         }
-        if (qn > 0) {
+        if (qn > 0 || overflow) {
             if (t == 0) status[k] = GOAT_ENOTSUP;
             return;
         }

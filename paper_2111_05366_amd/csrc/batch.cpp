@@ -172,6 +172,7 @@ struct goat_batch {
     bool launched = false;
     void* hbuf = nullptr;   // pinned staging for the final matrices
     size_t hbuf_bytes = 0;
+    long long lap_bids = 0; // device assignments of the last results call: bids summed
 
     ~goat_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -464,6 +465,10 @@ int goat_batch_results(goat_batch* b, int32_t* perm_host, double* score_host, in
         B_HIP(hipMemcpyAsync(perms.data(), b->ws + pl.perms, sizeof(int32_t) * perms.size(), hipMemcpyDeviceToHost,
                              b->s0));
         B_HIP(hipStreamSynchronize(b->s0));
+        b->lap_bids = 0;
+        for (int k = 0; k < N; ++k) {
+            if (st[k] >= 0) b->lap_bids += st[k];
+        }
         for (int k = 0; k < N; ++k)
             if (st[k] < 0) {
                 set_error("goat_batch_results: device assignment of problem " + std::to_string(k) +
@@ -567,6 +572,7 @@ int goat_batch_results(goat_batch* b, int32_t* perm_host, double* score_host, in
         st.ms_graph = ms_graph;
         st.ms_lap = ms_lap;
         st.ms_total = now_ms() - t_start;
+        st.lap_bids = b->opt.lap == 1 ? b->lap_bids : 0;
         *stats_host = st;
     }
     return GOAT_OK;

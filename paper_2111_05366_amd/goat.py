@@ -47,13 +47,13 @@ class Stats(ctypes.Structure):
                 ("sk_capped", ctypes.c_int), ("lap_device", ctypes.c_int),
                 ("f_final", ctypes.c_double), ("score", ctypes.c_double),
                 ("ms_loop", ctypes.c_double), ("ms_lap", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("lap_bids", ctypes.c_longlong)]
 
 
 class LapStats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_longlong), ("rounds_launched", ctypes.c_longlong),
                 ("tail_bids", ctypes.c_longlong), ("phases", ctypes.c_int), ("shift", ctypes.c_int), ("resolution_bits", ctypes.c_int),
-                ("list_bids", ctypes.c_int)]
+                ("list_bids", ctypes.c_int), ("skipped_phases", ctypes.c_int)]
 
 
 class Pair(ctypes.Structure):

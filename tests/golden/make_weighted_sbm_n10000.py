@@ -1,0 +1,117 @@
+"""Writes the FP64 oracle's Frank-Wolfe iterations on the weighted 4-block
+SBM pair at n = 10,000 (the benchmark's workload) for the two forms the
+benchmark times:
+
+  plain : cold Sinkhorn start in every iteration (Alg. 3 as printed);
+  mixed : the warm-start network on the first iteration (its stored
+          parameters, evaluated in float64), the previous iteration's column
+          potentials afterwards.
+
+Both run Alg. 3 with eps = 0.03 max|G|, Sinkhorn to a 1e-6 row-marginal error
+or 1000 sweeps, and the exact step. Written:
+
+  weighted_sbm_n10000_<form>.npz : the first 3 iterations: eps, Sinkhorn
+      sweeps and final error, the line-search scalars (fP, fQ, c, a, b, t),
+      and 8 rows of Q from the first iteration;
+  weighted_sbm_n10000_plain_run.json : (plain only) the whole run to its stop
+      (an exact zero step, or 30 iterations), with the match ratio of the
+      final assignment of P after every iteration from the third on, and the
+      final one.
+
+The mixed form never takes a zero step on this pair, so its run is cut at 3
+iterations (30 would take about a day of CPU). Calls only oracle/ and the
+seeded input module; the parameter file is data. About 45 minutes of CPU per
+FW iteration:
+
+    python tests/golden/make_weighted_sbm_n10000.py plain   # or mixed
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import goat_oracle as O        # noqa: E402
+from oracle import mlp_oracle as M         # noqa: E402
+from paper_2111_05366_amd import inputs    # noqa: E402
+
+N = 10000
+FW = 3
+ROWS = [0, 1, 2499, 2500, 5000, 7499, 7500, 9999]
+PARAMS = os.path.join(ROOT, "paper_2111_05366_amd", "data", "warmstart_mlp.safetensors")
+
+
+def out_path(form: str) -> str:
+    return os.path.join(HERE, f"weighted_sbm_n10000_{form}.npz")
+
+
+RUN_JSON = os.path.join(HERE, "weighted_sbm_n10000_plain_run.json")
+KEYS = ["eps", "sk_iters", "sk_err", "fP", "fQ", "c", "a", "b", "t"]
+
+
+def write_first(form: str, hist, opt, t0) -> None:
+    arrays = {k: np.array([h[k] for h in hist[:FW]], dtype=np.float64) for k in KEYS}
+    arrays["rows"] = np.array(ROWS, dtype=np.int64)
+    arrays["Q_rows_it1"] = hist[0]["Q_rows"]
+    meta = dict(workload="weighted 4-block SBM n=10000 (inputs.workload_weighted_sbm)", form=form,
+                warm=opt.warm, eps_rel=opt.eps_rel, sk_tol=opt.sk_tol, sk_max=opt.sk_max, fw=FW,
+                seconds=round(time.time() - t0, 1))
+    arrays["meta"] = np.array(json.dumps(meta))
+    np.savez_compressed(out_path(form), **arrays)
+    print(json.dumps({k: arrays[k].tolist() for k in KEYS} | meta), flush=True)
+
+
+def main(form: str) -> None:
+    from safetensors.numpy import load_file
+    pair = inputs.workload_weighted_sbm(N)
+    full = form == "plain"
+    opt = O.GoatOptions(eps_rel=0.03, sk_tol=1e-6, sk_max=1000, fw_max=30 if full else FW,
+                        stop_on_stall=full, warm="cold" if form == "plain" else "net_prev", lap="scipy")
+    net = None
+    if form == "mixed":
+        net = M.network(load_file(PARAMS)["params"])
+    t0 = time.time()
+    run = dict(workload="weighted 4-block SBM n=10000 (inputs.workload_weighted_sbm)", form=form,
+               eps_rel=opt.eps_rel, sk_tol=opt.sk_tol, sk_max=opt.sk_max, fw_max=opt.fw_max,
+               assignment="scipy linear_sum_assignment on P", iterations=[], match_ratio_after={},
+               complete=False)
+
+    def report(hist, P):
+        k = len(hist)
+        h = {key: float(hist[-1][key]) for key in KEYS}
+        print(f"it {k}: {json.dumps(h)} ({time.time() - t0:.0f} s)", flush=True)
+        if k == FW:
+            write_first(form, hist, opt, t0)
+        if full:
+            run["iterations"].append(h)
+            if k >= FW:
+                perm = O.assign_max(P, "scipy")
+                run["match_ratio_after"][str(k)] = O.match_ratio(perm, pair.truth)
+                print(f"it {k}: match ratio {run['match_ratio_after'][str(k)]:.4f}", flush=True)
+            with open(RUN_JSON, "w") as fh:
+                json.dump(run, fh, indent=1)
+
+    r = O.goat(pair.A, pair.B, opt=opt, record=True, net=net, keep_rows=ROWS, callback=report)
+    if full:
+        run["fw_iters"] = r.fw_iters
+        run["stalled"] = bool(r.history[-1]["t"] == 0.0)
+        run["match_ratio"] = O.match_ratio(r.perm, pair.truth)
+        run["score"] = r.score
+        run["complete"] = True
+        run["seconds"] = round(time.time() - t0, 1)
+        with open(RUN_JSON, "w") as fh:
+            json.dump(run, fh, indent=1)
+        print(f"final: {r.fw_iters} iterations, match ratio {run['match_ratio']:.4f}", flush=True)
+
+
+if __name__ == "__main__":
+    if len(sys.argv) != 2 or sys.argv[1] not in ("plain", "mixed"):
+        sys.exit("usage: make_weighted_sbm_n10000.py plain|mixed")
+    main(sys.argv[1])

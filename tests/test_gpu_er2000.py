@@ -2,9 +2,9 @@
 start, eps = 0.03 max|G|, Sinkhorn tolerance 1e-6 with at most 1000
 iterations, at most 30 FW iterations) end to end: the device solver in fp32
 against the FP64 oracle run on the same pair. Same number of FW iterations
-and the same step sequence, Sinkhorn iteration counts within one polling
-interval, the same objective to FP32 accuracy, and match ratios within
-0.005 of each other."""
+and the same step sequence, Sinkhorn iteration counts within one sweep, the
+relaxed objective within 1e-5 relative, and match ratios within 0.005 of
+each other."""
 import time
 
 import numpy as np
@@ -49,8 +49,15 @@ def test_er2000_end_to_end(G, lap):
     assert st.fw_iters == ref.fw_iters
     for h, o in zip(r.history, ref.history):
         assert h["t"] == pytest.approx(o["t"], abs=1e-4)
-        # convergence is polled every 16 iterations on the device
-        assert abs(h["sk_iters"] - o["sk_iters"]) <= 16
-    assert st.f_final == pytest.approx(O.relaxed_objective(g.A.astype(np.float64), g.B.astype(np.float64), ref.P),
-                                       rel=1e-4)
+        # The stop rule is tested after every sweep on both sides. The
+        # device's row-marginal error differs from the FP64 one by at most
+        # its compensated-potential floor (about 2.4e-7 at n = 10,000, less
+        # here), so a solve whose error crosses the 1e-6 tolerance within
+        # that band can stop one sweep earlier or later.
+        assert abs(h["sk_iters"] - o["sk_iters"]) <= 1
+        assert h["fP"] == pytest.approx(o["fP"], rel=1e-5)
+        assert h["c"] == pytest.approx(o["c"], rel=1e-5)
+    f_ref = O.relaxed_objective(g.A.astype(np.float64), g.B.astype(np.float64), ref.P)
+    print(f"final objective {st.f_final!r} vs oracle {f_ref!r}: rel {abs(st.f_final - f_ref) / abs(f_ref):.2e}")
+    assert st.f_final == pytest.approx(f_ref, rel=1e-5)
     assert abs(mg - mo) <= 0.005

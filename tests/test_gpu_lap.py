@@ -95,7 +95,7 @@ from paper_2111_05366_amd import goat
 M = torch.as_tensor(np.load(sys.argv[2]), device="cuda")
 perm, st = goat.lap_device(M)
 np.save(sys.argv[3], perm.cpu().numpy())
-print(json.dumps([st.rounds, st.tail_bids, st.phases, st.list_bids]))
+print(json.dumps([st.rounds, st.tail_bids, st.phases, st.list_bids, st.skipped_phases]))
 """
 
 
@@ -126,11 +126,19 @@ def test_lap_device_variants_change_nothing(G, kind, n, switch, tmp_path):
     out = subprocess.run([sys.executable, "-c", _LISTS_OFF, root, str(tmp_path / "M.npy"), str(tmp_path / "p.npy")],
                          env=env, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr[-2000:]
-    rounds, tail, phases, listed = json.loads(out.stdout.strip().splitlines()[-1])
+    rounds, tail, phases, listed, skipped = json.loads(out.stdout.strip().splitlines()[-1])
     if key == "GOAT_LAP_LISTS":
         assert listed == 0
     else:
         assert listed == st.list_bids
+    if key == "GOAT_LAP_SKIP_IDLE":
+        print(f"  phases passed over: {st.skipped_phases} (with the switch off: {skipped})")
+        assert skipped == 0
+        if kind == "nearperm":
+            # a near-permutation leaves every later phase idle
+            assert st.skipped_phases > 0
+    else:
+        assert skipped == st.skipped_phases
     assert (rounds, tail, phases) == (st.rounds, st.tail_bids, st.phases)
     assert np.array_equal(np.load(tmp_path / "p.npy").astype(np.int64), perm)
 
@@ -220,10 +228,11 @@ def test_lap_device_on_smooth_iterate_matches_host_optimum(G):
     perm, st = G.lap_device(P)
     pd = perm.cpu().numpy().astype(np.int64)
     Ph = P.double().cpu().numpy()
-    ph = G.lap_max(Ph).astype(np.int64)
+    from scipy.optimize import linear_sum_assignment
+    ph = linear_sum_assignment(Ph, maximize=True)[1].astype(np.int64)   # independent reference
     rows = np.arange(n)
     vd, vh = Ph[rows, pd].sum(), Ph[rows, ph].sum()
     print(f"smooth iterate n={n}: device {vd:.9f} ({st.rounds} rounds, {st.tail_bids} sequential bids), "
-          f"host {vh:.9f}")
+          f"scipy {vh:.9f}")
     assert np.array_equal(np.sort(pd), rows)
     assert abs(vd - vh) <= n * 2.0 ** -st.shift

@@ -23,9 +23,12 @@ def G():
 
 @pytest.mark.parametrize("n", [250, 1000])
 def test_lot_within_half_percent_of_lap(G, n):
+    from scipy.optimize import linear_sum_assignment
     for r in range(2):
         M = I.cost_matrix(n, 1000 * n + r).astype(np.float64)
-        perm = O.hungarian_max(-M) if n <= 250 else G.lap_max(-M)
+        # exact assignment: the oracle's Hungarian method at n = 250, SciPy's
+        # solver at n = 1000 (the plain Python loop would take minutes)
+        perm = O.hungarian_max(-M) if n <= 250 else linear_sum_assignment(M)[1]
         ofv_lap = float(M[np.arange(n), perm].sum())
         out = G.sinkhorn(torch.as_tensor(-M.astype(np.float32), device="cuda"), eps=0.01, max_iter=5000, tol=1e-4)
         Q = out.Q.double().cpu().numpy()
@@ -34,7 +37,12 @@ def test_lot_within_half_percent_of_lap(G, n):
         gap_round = (ofv_lap - float(M[np.arange(n), pr].sum())) / ofv_lap
         print(f"n={n} rep {r}: soft gap {gap_soft:.2e}, rounded gap {gap_round:.2e}, "
               f"iters {int(out.iters.item())}, err {float(out.err.item()):.1e}")
-        # the soft plan's rows are exact only to the tolerance, so its
-        # objective may fall slightly below the optimum; a permutation cannot
-        assert abs(gap_soft) <= 5e-3
+        # gap = (OFV_LAP - OFV_LOT) / OFV_LAP of a minimisation: a doubly
+        # stochastic plan costs at least the optimal assignment, so gap <= 0
+        # up to the plan's marginal slack. The device plan meets its row
+        # marginals only to tol = 1e-4, which can lower <M, Q> below the
+        # optimum by about tol * max M / mean M = 1e-4 * 150 / 125 = 1.2e-4 of
+        # it (upper bound 1.5e-4). The paper's claim is a gap within 0.5 %.
+        assert -5e-3 <= gap_soft <= 1.5e-4
+        # a permutation cannot beat the optimum at all
         assert -5e-3 <= gap_round <= 1e-12
