@@ -32,9 +32,9 @@
  *  - one Frank-Wolfe iteration's pieces: goat_grad (Alg. 3 step 1),
  *    goat_sinkhorn (LOT direction, Alg. 2), goat_linesearch (step 3);
  *  - whole solves: goat_solve, goat_run_begin/steps/finish/gradient/free,
- *    goat_solve_seeded (seeds, unequal sizes), goat_random_init (random
- *    starts), goat_batch_* and goat_tune (many pairs and starts in one
- *    launch);
+ *    goat_solve_seeded (seeds, unequal sizes), goat_random_init and
+ *    goat_solve_restarts (random starts), goat_batch_* and goat_tune (many
+ *    pairs and starts in one launch);
  *  - the final projection: goat_lap_max (host), goat_lap_device (device),
  *    goat_score; soft matching: goat_nominate;
  *  - the learned Sinkhorn warm start: goat_mlp_*;
@@ -75,6 +75,8 @@ extern "C" {
 /* Sinkhorn starting potentials. */
 #define GOAT_INIT_COLD  0   /* g = 0                                   */
 #define GOAT_INIT_G     1   /* start from the caller's g               */
+#define GOAT_INIT_MLP   2   /* g from the warm-start network (see the
+                               learned warm start below)               */
 
 /* Library version as 10000*major + 100*minor + patch. */
 int goat_version(void);
@@ -121,6 +123,13 @@ int goat_grad(int n, const float* A, const float* B, int ld,
  *           computed on the device. If the resulting eps is 0, Q = J.
  *  f, g     device float[n]: final potentials (natural units). With
  *           init == GOAT_INIT_G, g is read first as the starting point.
+ *  init     GOAT_INIT_COLD (g = 0), GOAT_INIT_G (the caller's g) or
+ *           GOAT_INIT_MLP: g = eps * network(column features of G / eps)
+ *           with the parameters at mlp_params (device float, the packed
+ *           layout of goat_mlp_param_count; n <= 20480). Every start
+ *           leads to the same fixed point; only the sweeps to reach it
+ *           differ.
+ *  mlp_params  device parameters for GOAT_INIT_MLP, else ignored (NULL).
  *  Q        n x n output (ldq), or NULL to skip forming it.
  *  iters_dev, err_dev, eps_out  device int / float / float outputs (each
  *           may be NULL): column updates run, max_i |sum_j Q_ij - 1| of the
@@ -133,7 +142,7 @@ int goat_grad(int n, const float* A, const float* B, int ld,
  */
 int goat_sinkhorn(int n, const float* G, int ldg,
                   const float* eps_dev, float eps_rel,
-                  float* f, float* g, int init,
+                  float* f, float* g, int init, const float* mlp_params,
                   int max_iter, float tol,
                   float* Q, int ldq,
                   int* iters_dev, float* err_dev, float* eps_out,
@@ -426,20 +435,53 @@ int goat_solve_seeded(int nA, const float* A, int lda, int nB, const float* B, i
 /*
  * goat_random_init - P0 = (J + K) / 2, where J = 1 1^T / n is the barycenter
  * and K = diag(r) U diag(c) is the Sinkhorn-Knopp scaling of a positive n x n
- * matrix U to a doubly stochastic one. Scaling alternates r = 1 / (U c),
- * c = 1 / (U^T r) from c = 1 until max_i |(K 1)_i - 1| <= tol (checked from
- * the second sweep) or max_iter sweeps; float32 on the device.
+ * matrix U to a doubly stochastic one. Sweeps run until
+ * max_i |(K 1)_i - 1| <= tol (checked from the second sweep) or max_iter
+ * sweeps; float32 on the device. For n <= GOAT_BATCH_NMAX one workgroup
+ * alternates r = 1 / (U c), c = 1 / (U^T r) from c = 1 in LDS (no
+ * workspace). Above, K is the entropic plan of the cost ln U at eps = 1,
+ * computed by goat_sinkhorn's sweeps (column potentials from 0) on ln U kept
+ * in the workspace.
  *  U        device n x n (ldu >= n), entries > 0 (e.g. U(0,1) draws).
  *  P        device n x n output (ldp >= n).
  *  iters_dev, err_dev  device int / float (may be NULL): sweeps run and the
  *           final row-sum error of K.
- * Status: GOAT_EINVAL for n < 1, n > GOAT_BATCH_NMAX, bad ld, null U or P,
- * tol < 0 or max_iter < 1. Non-positive entries of U are not checked (the
- * scaling then produces inf or nan).
+ *  ws       device workspace of goat_random_init_workspace_size(n) bytes
+ *           (0, and ws may be NULL, for n <= GOAT_BATCH_NMAX; about 4 n^2
+ *           above).
+ * Asynchronous on `stream`.
+ * Status: GOAT_EINVAL for n < 1, bad ld, null U or P, tol < 0 or not finite,
+ * max_iter < 1; GOAT_ENOMEM for a short workspace. Non-positive entries of U
+ * are not checked (the scaling then produces inf or nan).
  */
 #define GOAT_BATCH_NMAX 1024
+size_t goat_random_init_workspace_size(int n);
 int goat_random_init(int n, const float* U, int ldu, float* P, int ldp, float tol, int max_iter,
-                     int* iters_dev, float* err_dev, void* stream);
+                     int* iters_dev, float* err_dev, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * goat_solve_restarts - GOAT from several random starts for one pair of any
+ * size (GOAT section, random initialisations): restart r starts at
+ * P0 = (J + SK(U_r)) / 2 (goat_random_init, tolerance 1e-6, at most 1000
+ * sweeps) with U_r the n x n matrix at U + r * n * ldu, and runs goat_solve
+ * with opt; the permutation with the largest tr(A^T Pi B Pi^T) is kept, ties
+ * to the lowest r.
+ *  U            device, restarts stacked n x n positive draws (ldu >= n).
+ *  perm_host    host int32[n]: the kept permutation.
+ *  scores_host  host double[restarts] (may be NULL): each restart's score.
+ *  best_host    host int (may be NULL): the kept restart.
+ *  stats_host   host goat_stats (may be NULL): the kept restart's stats.
+ *  ws           goat_solve_restarts_workspace_size(n, ld, prec, symmetric)
+ *               bytes: goat_solve's workspace, P0 (n x ld) and the random
+ *               start's.
+ * Host-synchronous, like goat_solve. Status: GOAT_EINVAL for bad sizes,
+ * pointers, restarts < 1 or options; GOAT_ENOMEM; goat_solve's errors.
+ */
+size_t goat_solve_restarts_workspace_size(int n, int ld, int prec, int symmetric);
+int goat_solve_restarts(int n, const float* A, const float* B, int ld, const float* U, int ldu,
+                        int restarts, const goat_options* opt, int32_t* perm_host,
+                        double* scores_host, int* best_host, goat_stats* stats_host,
+                        void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Batched solve: many graph pairs of uneven size, several starts each

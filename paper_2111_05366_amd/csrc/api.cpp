@@ -287,13 +287,15 @@ int goat_grad(int n, const float* A, const float* B, int ld, const float* P, int
 }
 
 int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float eps_rel, float* f, float* g,
-                  int init, int max_iter, float tol, float* Q, int ldq, int* iters_dev, float* err_dev,
-                  float* eps_out, void* ws, size_t ws_bytes, void* stream) {
+                  int init, const float* mlp_params, int max_iter, float tol, float* Q, int ldq, int* iters_dev,
+                  float* err_dev, float* eps_out, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     GOAT_CHECK_ARG(n >= 1, "n < 1");
     GOAT_CHECK_ARG(G && ws, "null pointer");
     GOAT_CHECK_ARG(ldg >= n && (!Q || ldq >= n), "leading dimension < n");
-    GOAT_CHECK_ARG(init == GOAT_INIT_COLD || (init == GOAT_INIT_G && g), "bad init");
+    GOAT_CHECK_ARG(init == GOAT_INIT_COLD || (init == GOAT_INIT_G && g) || (init == GOAT_INIT_MLP && mlp_params),
+                   "bad init (GOAT_INIT_G needs g, GOAT_INIT_MLP needs mlp_params)");
+    GOAT_CHECK_ARG(init != GOAT_INIT_MLP || n <= 20480, "the warm-start network takes n <= 20480");
     GOAT_CHECK_ARG(max_iter >= 0, "max_iter < 0");
     GOAT_CHECK_ARG(std::isfinite(tol) && tol >= 0.0f, "bad tol");
     GOAT_CHECK_ARG(eps_dev || (std::isfinite(eps_rel) && eps_rel > 0.0f), "bad eps_rel");
@@ -318,6 +320,14 @@ int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float ep
     int rc = sk_prepare(n, Gk, ldk, eps_dev, eps_rel, nullptr, init == GOAT_INIT_G ? g : nullptr, tol, p.sk,
                         p.fscal, p.red, s);
     if (rc) return rc;
+    if (init == GOAT_INIT_MLP) {
+        // features of G / eps with the eps just set, the network, then the
+        // column potentials (the column partials are scratch until the sweeps)
+        rc = mlp_features(n, L.np, Gk, ldk, &p.sk.ctrl->eps, p.sk.colpart, p.feat, s);
+        if (!rc) rc = mlp_forward(n, p.feat, mlp_params, p.pred, s);
+        if (!rc) rc = warm_seed(n, p.pred, p.sk.ctrl, p.sk.vg, p.sk.vs, s);
+        if (rc) return rc;
+    }
     for (int k = 0; k < max_iter; ++k) {
         rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, k, s);
         if (rc) return rc;

@@ -599,13 +599,41 @@ void goat_batch_destroy(goat_batch* b) {
     delete b;
 }
 
+size_t goat_random_init_workspace_size(int n) {
+    if (n <= GOAT_BATCH_NMAX) return 0;
+    const Layout L = make_layout(n, GOAT_PREC_FP32, 1);
+    return small_bytes(L) + (size_t)L.np * L.np * sizeof(float);
+}
+
+// Up to GOAT_BATCH_NMAX one workgroup scales U in place of LDS. Above, the
+// Sinkhorn-Knopp scaling of U is the entropic plan of the cost ln U at
+// eps = 1 (Q = diag(e^f) U diag(e^g)), so the LOT sweeps do it: ln U goes
+// into the workspace, the sweeps run with the same stop rule (row sums of
+// K within tol), and K is written into P before P = (J + K) / 2.
 int goat_random_init(int n, const float* U, int ldu, float* P, int ldp, float tol, int max_iter, int* iters_dev,
-                     float* err_dev, void* stream) {
-    if (n < 1 || n > GOAT_BATCH_NMAX || !U || !P || ldu < n || ldp < n || !(tol >= 0.0f) || max_iter < 1) {
+                     float* err_dev, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    if (n < 1 || !U || !P || ldu < n || ldp < n || !(tol >= 0.0f) || !std::isfinite(tol) || max_iter < 1) {
         set_error("goat_random_init: bad arguments");
         return GOAT_EINVAL;
     }
-    return random_init_launch(n, U, ldu, P, ldp, tol, max_iter, iters_dev, err_dev, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n <= GOAT_BATCH_NMAX) return random_init_launch(n, U, ldu, P, ldp, tol, max_iter, iters_dev, err_dev, s);
+    if (!ws || ws_bytes < goat_random_init_workspace_size(n)) {
+        set_error("goat_random_init: workspace smaller than goat_random_init_workspace_size(n)");
+        return GOAT_ENOMEM;
+    }
+    const Layout L = make_layout(n, GOAT_PREC_FP32, 1);
+    Ptrs p = make_ptrs(L, ws);
+    float* one = reinterpret_cast<float*>(p.scal + 20);
+    int rc = launch_log_pad(n, U, ldu, p.P, L.np, one, s);
+    if (!rc) rc = sk_prepare(n, p.P, L.np, one, 0.0f, nullptr, nullptr, tol, p.sk, p.fscal, p.red, s);
+    for (int k = 0; !rc && k < max_iter; ++k) rc = sk_iterate(n, L.np, p.P, L.np, p.sk, k == 0, k >= 1, k, s);
+    if (!rc)
+        rc = sk_finalize(n, L.np, p.P, L.np, p.sk, P, ldp, nullptr, nullptr, nullptr, nullptr, iters_dev, err_dev,
+                         nullptr, p.red, s);
+    if (!rc) rc = launch_half_bary(n, P, ldp, s);
+    return rc;
 }
 
 // Each bucket up to n_max: a synthetic batch of 64 pairs x 8 starts at the

@@ -217,6 +217,8 @@ int launch_arrange(int n, const float* X, int ldx, const int* order_dev, int ado
 int launch_pack_rect(const float* src, int ld, int rows, int cols, int transpose, float* dst, int ldd, int prows,
                      int pcols, hipStream_t s);
 int launch_add_mat(int n, float* G, const float* C, int ld, hipStream_t s);
+int launch_log_pad(int n, const float* U, int ldu, float* dst, int np, float* one_out, hipStream_t s);
+int launch_half_bary(int n, float* P, int ld, hipStream_t s);
 // atomically ORs 1 into *flag when X (n x n, ld) holds a NaN or an infinity
 int launch_check_finite(int n, const float* X, int ld, int* flag, hipStream_t s);
 int launch_fw_update(int n, float* P, const float* Q, float* GP, const float* GQ, int ld,

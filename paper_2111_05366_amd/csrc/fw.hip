@@ -343,6 +343,36 @@ int launch_pack_rect(const float* src, int ld, int rows, int cols, int transpose
     return GOAT_OK;
 }
 
+// ln U into an np x np buffer (zero padding), and the scalar 1 at one_out:
+// the Sinkhorn-Knopp scaling of U is the entropic plan of the cost ln U at
+// eps = 1, Q = exp(ln U + f + g) = diag(e^f) U diag(e^g)
+__global__ __launch_bounds__(RT) void log_pad_kernel(int n, const float* __restrict__ U, int ldu, float* dst,
+                                                     int np, float* one_out) {
+    const int i = blockIdx.x;
+    for (int j = threadIdx.x; j < np; j += RT)
+        dst[(size_t)i * np + j] = (i < n && j < n) ? logf(U[(size_t)i * ldu + j]) : 0.0f;
+    if (i == 0 && threadIdx.x == 0) *one_out = 1.0f;
+}
+
+// P = (J + K) / 2 in place (K doubly stochastic, n x n, ld)
+__global__ __launch_bounds__(RT) void half_bary_kernel(int n, float* P, int ld) {
+    const float h = 0.5f / (float)n;
+    const int i = blockIdx.x;
+    for (int j = threadIdx.x; j < n; j += RT) P[(size_t)i * ld + j] = fmaf(0.5f, P[(size_t)i * ld + j], h);
+}
+
+int launch_log_pad(int n, const float* U, int ldu, float* dst, int np, float* one_out, hipStream_t s) {
+    hipLaunchKernelGGL(log_pad_kernel, dim3(np), dim3(RT), 0, s, n, U, ldu, dst, np, one_out);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+int launch_half_bary(int n, float* P, int ld, hipStream_t s) {
+    hipLaunchKernelGGL(half_bary_kernel, dim3(n), dim3(RT), 0, s, n, P, ld);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
 int launch_add_mat(int n, float* G, const float* C, int ld, hipStream_t s) {
     if (n < 1) return GOAT_OK;
     hipLaunchKernelGGL(add_mat_kernel, dim3(n), dim3(RT), 0, s, n, G, C, ld);

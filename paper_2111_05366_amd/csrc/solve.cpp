@@ -521,4 +521,56 @@ int goat_solve(int n, const float* A, const float* B, int ld, const float* P0, c
     return rc;
 }
 
+// Workspace of goat_solve_restarts: [goat_solve's][P0, n x ld][the random
+// start's], each 256-byte aligned.
+static size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+size_t goat_solve_restarts_workspace_size(int n, int ld, int prec, int symmetric) {
+    if (n < 1 || ld < n) return 0;
+    return align256(goat_workspace_size(n, prec, symmetric)) + align256((size_t)n * ld * sizeof(float)) +
+           goat_random_init_workspace_size(n);
+}
+
+int goat_solve_restarts(int n, const float* A, const float* B, int ld, const float* U, int ldu, int restarts,
+                        const goat_options* opt, int32_t* perm_host, double* scores_host, int* best_host,
+                        goat_stats* stats_host, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    goat_options o;
+    if (opt) o = *opt; else goat_default_options(&o);
+    GOAT_CHECK_ARG(n >= 1 && ld >= n && ldu >= n, "n < 1 or a leading dimension < n");
+    GOAT_CHECK_ARG(A && B && U && perm_host && ws, "null pointer");
+    GOAT_CHECK_ARG(restarts >= 1, "restarts < 1");
+    const size_t need = goat_solve_restarts_workspace_size(n, ld, o.prec, o.symmetric);
+    if (ws_bytes < need) {
+        set_error("goat_solve_restarts: workspace smaller than goat_solve_restarts_workspace_size");
+        return GOAT_ENOMEM;
+    }
+    char* base = static_cast<char*>(ws);
+    const size_t solve_bytes = align256(goat_workspace_size(n, o.prec, o.symmetric));
+    float* P0 = reinterpret_cast<float*>(base + solve_bytes);
+    char* init_ws = base + solve_bytes + align256((size_t)n * ld * sizeof(float));
+    const size_t init_bytes = goat_random_init_workspace_size(n);
+    std::vector<int32_t> perm(n);
+    double best_score = 0.0;
+    int best = -1;
+    for (int r = 0; r < restarts; ++r) {
+        const float* Ur = U + (size_t)r * n * ldu;
+        int rc = goat_random_init(n, Ur, ldu, P0, ld, 1e-6f, 1000, nullptr, nullptr, init_bytes ? init_ws : nullptr,
+                                  init_bytes, stream);
+        goat_stats st{};
+        if (!rc) rc = goat_solve(n, A, B, ld, P0, &o, perm.data(), &st, nullptr, 0, nullptr, ws, solve_bytes, stream);
+        if (rc) return rc;
+        if (scores_host) scores_host[r] = st.score;
+        // the largest score is kept; a tie keeps the earlier start
+        if (best < 0 || st.score > best_score) {
+            best = r;
+            best_score = st.score;
+            std::memcpy(perm_host, perm.data(), sizeof(int32_t) * n);
+            if (stats_host) *stats_host = st;
+        }
+    }
+    if (best_host) *best_host = best;
+    return GOAT_OK;
+}
+
 }  // extern "C"

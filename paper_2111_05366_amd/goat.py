@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libgoat.so")
 
 GOAT_OK, GOAT_EINVAL, GOAT_EHIP, GOAT_ENOMEM, GOAT_ENOTSUP = 0, -1, -2, -3, -4
 PREC = {"fp32": 0, "bf16x2": 1, "bf16x3": 2, "fp8": 3}
-INIT_COLD, INIT_G = 0, 1
+INIT_COLD, INIT_G, INIT_MLP = 0, 1, 2
 
 
 class GoatError(RuntimeError):
@@ -47,7 +47,7 @@ class Stats(ctypes.Structure):
                 ("sk_capped", ctypes.c_int), ("lap_device", ctypes.c_int),
                 ("f_final", ctypes.c_double), ("score", ctypes.c_double),
                 ("ms_loop", ctypes.c_double), ("ms_lap", ctypes.c_double),
-                ("ms_total", ctypes.c_double), ("lap_bids", ctypes.c_longlong)]
+                ("ms_total", ctypes.c_double)]
 
 
 class LapStats(ctypes.Structure):
@@ -65,7 +65,7 @@ class BatchStats(ctypes.Structure):
     _fields_ = [("problems", ctypes.c_int), ("fw_iters_total", ctypes.c_int),
                 ("sk_iters_total", ctypes.c_longlong), ("sk_capped", ctypes.c_int),
                 ("launches", ctypes.c_int), ("ms_graph", ctypes.c_double), ("ms_lap", ctypes.c_double),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("lap_bids", ctypes.c_longlong)]
 
 
 _lib = None
@@ -88,7 +88,7 @@ def lib():
     L.goat_grad.restype = _I
     L.goat_grad.argtypes = [_I, _VP, _VP, _I, _VP, _I, _VP, _I, _I, _I, _VP, _SZ, _VP]
     L.goat_sinkhorn.restype = _I
-    L.goat_sinkhorn.argtypes = [_I, _VP, _I, _VP, _F, _VP, _VP, _I, _I, _F, _VP, _I, _VP, _VP, _VP,
+    L.goat_sinkhorn.argtypes = [_I, _VP, _I, _VP, _F, _VP, _VP, _I, _VP, _I, _F, _VP, _I, _VP, _VP, _VP,
                                 _VP, _SZ, _VP]
     L.goat_linesearch.restype = _I
     L.goat_linesearch.argtypes = [_I, _VP, _VP, _VP, _VP, _I, _VP, _VP, _SZ, _VP]
@@ -138,8 +138,15 @@ def lib():
     L.goat_solve_seeded.restype = _I
     L.goat_solve_seeded.argtypes = [_I, _VP, _I, _I, _VP, _I, _I, _VP, _VP, _I, ctypes.POINTER(Options), _VP,
                                     ctypes.POINTER(Stats), ctypes.POINTER(IterRecord), _I, _VP, _SZ, _VP]
+    L.goat_random_init_workspace_size.restype = _SZ
+    L.goat_random_init_workspace_size.argtypes = [_I]
     L.goat_random_init.restype = _I
-    L.goat_random_init.argtypes = [_I, _VP, _I, _VP, _I, _F, _I, _VP, _VP, _VP]
+    L.goat_random_init.argtypes = [_I, _VP, _I, _VP, _I, _F, _I, _VP, _VP, _VP, _SZ, _VP]
+    L.goat_solve_restarts_workspace_size.restype = _SZ
+    L.goat_solve_restarts_workspace_size.argtypes = [_I, _I, _I, _I]
+    L.goat_solve_restarts.restype = _I
+    L.goat_solve_restarts.argtypes = [_I, _VP, _VP, _I, _VP, _I, _I, ctypes.POINTER(Options), _VP, _VP, _VP,
+                                      ctypes.POINTER(Stats), _VP, _SZ, _VP]
     L.goat_batch_workspace_size.restype = _I
     L.goat_batch_workspace_size.argtypes = [ctypes.POINTER(Pair), _I, _I, ctypes.POINTER(Options),
                                             ctypes.POINTER(ctypes.c_size_t)]
@@ -260,8 +267,9 @@ class SinkhornOut:
 
 
 def sinkhorn(G, eps_rel: float = 0.03, max_iter: int = 1000, tol: float = 1e-6, g0=None, eps=None,
-             want_Q: bool = True) -> SinkhornOut:
-    """LOT direction on the device (goat_sinkhorn)."""
+             want_Q: bool = True, mlp_params=None) -> SinkhornOut:
+    """LOT direction on the device (goat_sinkhorn). Start: g0 if given, else
+    the warm-start network if mlp_params is given, else cold."""
     torch = _torch()
     _mat(G, "G")
     n = G.shape[0]
@@ -276,8 +284,9 @@ def sinkhorn(G, eps_rel: float = 0.03, max_iter: int = 1000, tol: float = 1e-6, 
     if eps is not None:
         eps_t = torch.tensor([eps], dtype=torch.float32, device=dev)
     ws = workspace(n, "fp32", True, dev)
+    init = INIT_G if g0 is not None else (INIT_MLP if mlp_params is not None else INIT_COLD)
     _check(lib().goat_sinkhorn(n, _ptr(G), G.stride(0), _ptr(eps_t), float(eps_rel), _ptr(f), _ptr(g),
-                               INIT_G if g0 is not None else INIT_COLD, int(max_iter), float(tol),
+                               init, _ptr(mlp_params), int(max_iter), float(tol),
                                _ptr(Q), Q.stride(0) if Q is not None else n, _ptr(it), _ptr(err),
                                _ptr(eps_out), _ptr(ws), ws.numel(), _stream()))
     return SinkhornOut(f, g, Q, it, err, eps_out)
@@ -526,9 +535,43 @@ def random_init(U, tol: float = 1e-6, max_iter: int = 1000):
     P = torch.empty((n, n), dtype=torch.float32, device=U.device)
     it = torch.zeros(1, dtype=torch.int32, device=U.device)
     err = torch.zeros(1, dtype=torch.float32, device=U.device)
+    need = int(lib().goat_random_init_workspace_size(n))
+    ws = torch.empty(need, dtype=torch.uint8, device=U.device) if need else None
     _check(lib().goat_random_init(n, _ptr(U), U.stride(0), _ptr(P), P.stride(0), float(tol), int(max_iter),
-                                  _ptr(it), _ptr(err), _stream()))
+                                  _ptr(it), _ptr(err), _ptr(ws), need, _stream()))
     return P, it, err
+
+
+@dataclass
+class RestartsResult:
+    perm: np.ndarray
+    stats: Stats
+    scores: np.ndarray
+    best: int
+
+
+def solve_restarts(A, B, U, restarts: int, **opts) -> RestartsResult:
+    """GOAT from `restarts` random starts (goat_solve_restarts): U holds the
+    starts' n x n positive draws stacked as a (restarts * n, n) tensor."""
+    torch = _torch()
+    _mat(A, "A"); _mat(B, "B"); _mat(U, "U")
+    n = A.shape[0]
+    if A.stride(0) != B.stride(0):
+        raise ValueError("A and B must share a leading dimension")
+    if U.shape[0] < restarts * n or U.shape[1] < n:
+        raise ValueError("U must hold restarts stacked n x n matrices")
+    o = default_options(**opts)
+    need = int(lib().goat_solve_restarts_workspace_size(n, A.stride(0), o.prec, o.symmetric))
+    ws = torch.empty(need, dtype=torch.uint8, device=A.device)
+    perm = np.empty(n, dtype=np.int32)
+    scores = np.empty(restarts, dtype=np.float64)
+    best = ctypes.c_int(-1)
+    st = Stats()
+    _check(lib().goat_solve_restarts(n, _ptr(A), _ptr(B), A.stride(0), _ptr(U), U.stride(0), int(restarts),
+                                     ctypes.byref(o), perm.ctypes.data_as(ctypes.c_void_p),
+                                     scores.ctypes.data_as(ctypes.c_void_p), ctypes.byref(best),
+                                     ctypes.byref(st), _ptr(ws), need, _stream()))
+    return RestartsResult(perm.astype(np.int64), st, scores, best.value)
 
 
 class Batch:

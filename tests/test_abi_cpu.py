@@ -149,13 +149,24 @@ def test_bad_arguments_rejected_before_device(G):
     s = L.goat_grad(4, ctypes.c_void_p(16), ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 4,
                     ctypes.c_void_p(16), 4, 0, 1, ctypes.c_void_p(16), 16, None)
     assert s == G.GOAT_ENOMEM          # workspace too small
-    s = L.goat_sinkhorn(4, ctypes.c_void_p(16), 4, None, ctypes.c_float(0.0), None, None, 0, 10,
+    s = L.goat_sinkhorn(4, ctypes.c_void_p(16), 4, None, ctypes.c_float(0.0), None, None, 0, None, 10,
                         ctypes.c_float(1e-6), None, 4, None, None, None, ctypes.c_void_p(16), 1 << 30, None)
     assert s == G.GOAT_EINVAL          # eps_rel <= 0
-    s = L.goat_sinkhorn(4, ctypes.c_void_p(16), 4, None, ctypes.c_float(0.03), None, None, 1, 10,
+    s = L.goat_sinkhorn(4, ctypes.c_void_p(16), 4, None, ctypes.c_float(0.03), None, None, 1, None, 10,
                         ctypes.c_float(1e-6), None, 4, None, None, None, ctypes.c_void_p(16), 1 << 30, None)
     assert s == G.GOAT_EINVAL          # warm start without g
-    s = L.goat_sinkhorn(4, ctypes.c_void_p(16), 4, None, ctypes.c_float(0.03), None, None, 0, 10,
+    s = L.goat_sinkhorn(4, ctypes.c_void_p(16), 4, None, ctypes.c_float(0.03), None, None, 2, None, 10,
+                        ctypes.c_float(1e-6), None, 4, None, None, None, ctypes.c_void_p(16), 1 << 30, None)
+    assert s == G.GOAT_EINVAL          # network start without parameters
+    assert b"GOAT_INIT_MLP needs mlp_params" in L.goat_last_error()
+    s = L.goat_sinkhorn(30000, ctypes.c_void_p(16), 30000, None, ctypes.c_float(0.03), None, None, 2,
+                        ctypes.c_void_p(16), 10, ctypes.c_float(1e-6), None, 30000, None, None, None,
+                        ctypes.c_void_p(16), 1 << 40, None)
+    assert s == G.GOAT_EINVAL          # the network's size limit
+    s = L.goat_sinkhorn(4, ctypes.c_void_p(16), 4, None, ctypes.c_float(0.03), None, None, 3, None, 10,
+                        ctypes.c_float(1e-6), None, 4, None, None, None, ctypes.c_void_p(16), 1 << 30, None)
+    assert s == G.GOAT_EINVAL          # unknown start
+    s = L.goat_sinkhorn(4, ctypes.c_void_p(16), 4, None, ctypes.c_float(0.03), None, None, 0, None, 10,
                         ctypes.c_float(float("nan")), None, 4, None, None, None, ctypes.c_void_p(16), 1 << 30, None)
     assert s == G.GOAT_EINVAL          # non-finite tol
     s = L.goat_linesearch(4, None, None, None, None, 4, None, None, 0, None)
@@ -193,9 +204,30 @@ def test_batch_arguments_rejected_before_device(G):
         ob = G.default_options(**kw)
         assert L.goat_batch_workspace_size(pairs, 2, 8, ctypes.byref(ob), ctypes.byref(need)) == status, kw
     assert L.goat_random_init(0, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 4, ctypes.c_float(1e-6), 10,
-                              None, None, None) == G.GOAT_EINVAL
+                              None, None, None, 0, None) == G.GOAT_EINVAL
     assert L.goat_random_init(4, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 4, ctypes.c_float(1e-6), 0,
-                              None, None, None) == G.GOAT_EINVAL
+                              None, None, None, 0, None) == G.GOAT_EINVAL
+    assert L.goat_random_init(4, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 4, ctypes.c_float(float("inf")),
+                              10, None, None, None, 0, None) == G.GOAT_EINVAL
+    # no workspace needed up to 1024 nodes; above, a short workspace is refused
+    assert L.goat_random_init_workspace_size(1024) == 0
+    need = L.goat_random_init_workspace_size(1025)
+    assert need >= 4 * 1025 * 1025
+    assert L.goat_random_init(1025, ctypes.c_void_p(16), 1025, ctypes.c_void_p(16), 1025, ctypes.c_float(1e-6),
+                              10, None, None, ctypes.c_void_p(16), need - 1, None) == G.GOAT_ENOMEM
+    assert b"goat_random_init_workspace_size" in L.goat_last_error()
+    # restarts: sizes, pointers, count and workspace checked before the device
+    o = G.default_options()
+    ws_need = L.goat_solve_restarts_workspace_size(2000, 2000, 0, 1)
+    assert ws_need >= L.goat_workspace_size(2000, 0, 1) + 4 * 2000 * 2000 + L.goat_random_init_workspace_size(2000)
+    dummy = ctypes.c_void_p(16)
+    for args, status in (((2000, dummy, dummy, 2000, dummy, 2000, 0), G.GOAT_EINVAL),
+                         ((2000, dummy, dummy, 1999, dummy, 2000, 2), G.GOAT_EINVAL),
+                         ((2000, None, dummy, 2000, dummy, 2000, 2), G.GOAT_EINVAL)):
+        assert L.goat_solve_restarts(*args, ctypes.byref(o), dummy, None, None, None, dummy, ws_need,
+                                     None) == status, args
+    assert L.goat_solve_restarts(2000, dummy, dummy, 2000, dummy, 2000, 2, ctypes.byref(o), dummy, None, None,
+                                 None, dummy, ws_need - 1, None) == G.GOAT_ENOMEM
     assert L.goat_tune(0, 1, None) == G.GOAT_EINVAL
     assert L.goat_tune_get(2000, None, None) == G.GOAT_EINVAL
 
@@ -225,3 +257,38 @@ def test_lap_device_arguments_rejected_before_device(G):
     o = G.default_options(lap=2)
     s = L.goat_solve(4, dummy, dummy, 4, None, ctypes.byref(o), dummy, None, None, 0, None, dummy, 1 << 30, None)
     assert s == G.GOAT_EINVAL and b"assignment mode" in L.goat_last_error()
+
+
+def test_ctypes_structs_match_header(tmp_path):
+    """Every struct the binding mirrors has the size and field offsets of
+    its declaration in goat.h (a mismatch lets the library write past a
+    Python-side buffer). Checked by compiling the header with the host C
+    compiler."""
+    import os
+    import shutil
+    import subprocess
+    from paper_2111_05366_amd import goat as G
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"goat_options": G.Options, "goat_iter_record": G.IterRecord, "goat_stats": G.Stats,
+               "goat_lap_stats": G.LapStats, "goat_pair": G.Pair, "goat_batch_stats": G.BatchStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "goat.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I" + os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, value = line.split()
+        got[(cname, field)] = int(value)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

@@ -38,7 +38,7 @@ def is_perm(p, n):
     return sorted(int(x) for x in p) == list(range(n))
 
 
-@pytest.mark.parametrize("n", [1, 5, 64, 257, 1024])
+@pytest.mark.parametrize("n", [1, 5, 64, 257, 1024, 1025, 2000])
 def test_random_init_parity(G, n):
     U = I.uniform_matrix(n, 300 + n)
     P, it, err = G.random_init(dev(U))
@@ -284,3 +284,24 @@ def test_batch_device_assignment_skip_changes_nothing(tmp_path):
     # that is passed over
     assert outs[0] == outs[1]
     assert outs[0][1] > 0
+
+
+def test_solve_restarts_matches_oracle(G):
+    # a single pair above the one-workgroup limit (its random starts use the
+    # LOT sweeps on ln U): every restart's score, the kept restart and the
+    # kept permutation equal the oracle's goat_restarts on the same U draws
+    n, R = 1100, 3
+    g = I.rho_er_pair(n, 0.05, 1.0, 7100)
+    U = I.uniform_matrix(R * n, 7200)[:, :n].copy()
+    opts = dict(sk_max=300, fw_max=6)
+    res = G.solve_restarts(dev(g.A), dev(g.B), dev(U), R, prec="fp32", **opts)
+    inits = [O.random_init(U[r * n:(r + 1) * n].astype(np.float64)) for r in range(R)]
+    oo = O.GoatOptions(sk_max=300, fw_max=6, lap="scipy")
+    per = [O.goat(g.A, g.B, P0=P0, opt=oo) for P0 in inits]
+    ref = O.goat_restarts(g.A, g.B, inits, opt=oo)
+    print(f"restarts n={n}: device scores {list(res.scores)} kept {res.best}; oracle "
+          f"{[r.score for r in per]} kept {ref.start}; match {np.mean(res.perm == g.truth):.4f}")
+    assert list(res.scores) == [r.score for r in per]
+    assert res.best == ref.start
+    assert list(res.perm) == list(ref.perm)
+    assert res.stats.score == ref.score == O.qap_value(g.A, g.B, res.perm)

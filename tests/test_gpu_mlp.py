@@ -159,3 +159,29 @@ def test_warm_start_same_fixed_point(G):
     warm = G.sinkhorn(Gd, max_iter=5000, tol=1e-6, g0=(pred * eps).contiguous())
     assert float(cold.err.item()) <= 1e-6 and float(warm.err.item()) <= 1e-6
     assert np.max(np.abs(host(cold.Q) - host(warm.Q))) <= 1e-4
+
+
+@pytest.mark.parametrize("n,iters", [(300, 5), (1000, 40), (2051, 12)])
+def test_sinkhorn_network_start_parity(G, n, iters):
+    """goat_sinkhorn with GOAT_INIT_MLP: the network's start evaluated in
+    FP64 by the oracle from the same parameters, then the same number of
+    sweeps, gives the same plan."""
+    print(f"sinkhorn network start n={n} iters={iters}", flush=True)
+    Gm = _grad_problem(n, 600 + n)
+    params = _params(31)
+    out = G.sinkhorn(dev(Gm), eps_rel=0.03, max_iter=iters, tol=0.0, mlp_params=dev(params))
+    Gd = Gm.astype(np.float64)
+    eps = 0.03 * float(np.max(np.abs(Gd)))
+    assert float(out.eps.item()) == pytest.approx(eps, rel=1e-6)
+    g0 = M.warm_start(Gd, eps, M.unpack(params))
+    ref = O.log_sinkhorn_max(Gd, eps, tol=0.0, max_iter=iters, g0=g0)
+    Qd = host(out.Q)
+    err = float(np.linalg.norm(Qd - ref.Q) / np.linalg.norm(ref.Q))
+    m = ref.Q >= 1e-30
+    emax = float(np.max(np.abs(Qd[m] - ref.Q[m]) / ref.Q[m]))
+    # the start differs from a cold one (so the network was applied)
+    cold = O.log_sinkhorn_max(Gd, eps, tol=0.0, max_iter=iters)
+    sep = float(np.linalg.norm(cold.Q - ref.Q) / np.linalg.norm(ref.Q))
+    print(f"  Q rel_fro={err:.2e} elem={emax:.2e}; network vs cold start {sep:.2e}")
+    assert err <= 1e-4 and emax <= 1e-4
+    assert sep > 1e-3
