@@ -27,18 +27,53 @@ def _torch():
     return torch
 
 
+def _pair_edges(spec):
+    """Worker: the seeded pair of `spec` = (n, p, rho, seed) as the upper
+    triangles' nonzero positions of A and B (both symmetric 0/1, hollow), so
+    that a worker process sends a few MB instead of two dense matrices."""
+    n, p, rho, seed = spec
+    g = inputs.rho_er_pair(n, p, rho, seed)
+    out = [n, seed]
+    for X in (g.A, g.B):
+        iu, ju = np.nonzero(np.triu(X, 1))
+        out.append((iu.astype(np.int32) * np.int64(n) + ju).astype(np.int64))
+    return tuple(out)
+
+
+def _dense_from_edges(n, flat, torch):
+    X = torch.zeros(n * n, dtype=torch.float32, device="cuda")
+    idx = torch.as_tensor(flat, device="cuda")
+    X[idx] = 1.0
+    X = X.view(n, n)
+    return X + X.t()
+
+
+def _pairs_stream(pairs, workers):
+    """(n, seed, A, B) device tensors for each pair spec, drawn by `workers`
+    spawned processes (0: in this process)."""
+    torch = _torch()
+    if workers <= 0:
+        for (n, p, rho, seed) in pairs:
+            g = inputs.rho_er_pair(n, p, rho, seed)
+            yield n, seed, torch.as_tensor(g.A, device="cuda"), torch.as_tensor(g.B, device="cuda")
+        return
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for (n, seed, ea, eb) in pool.imap(_pair_edges, pairs, chunksize=1):
+            yield n, seed, _dense_from_edges(n, ea, torch), _dense_from_edges(n, eb, torch)
+
+
 def generate(pairs, fw_iters: int = 6, sk_tol: float = 1e-6, sk_cap: int = 3000, eps_rel: float = 0.03,
-             log=None):
+             log=None, max_solves: int = 0, workers: int = 0):
     """Samples (F [N,4], target [N], solves) from a list of (n, p, rho, seed).
     Each FW iterate of the plain fp32 solver gives one Sinkhorn problem;
     iterates after a zero step (same G as before) and solves that did not
-    reach sk_tol within sk_cap are skipped (their g is not the fixed point)."""
+    reach sk_tol within sk_cap are skipped (their g is not the fixed point).
+    Stops after max_solves kept solves (0: all pairs); pairs are drawn by
+    `workers` processes."""
     torch = _torch()
     feats, targs, meta = [], [], []
-    for (n, p, rho, seed) in pairs:
-        g = inputs.rho_er_pair(n, p, rho, seed)
-        A = torch.as_tensor(g.A, device="cuda")
-        B = torch.as_tensor(g.B, device="cuda")
+    for (n, seed, A, B) in _pairs_stream(pairs, workers):
         run = goat.Run(A, B, prec="fp32", sk_max=1000, stop_on_stall=1, eps_rel=eps_rel)
         kept = []
         for k in range(fw_iters):
@@ -56,8 +91,11 @@ def generate(pairs, fw_iters: int = 6, sk_tol: float = 1e-6, sk_cap: int = 3000,
             if run.steps(1) == 0 or run.history[-1]["t"] == 0.0:
                 break   # a zero step leaves P, hence G, unchanged
         run.close()
+        del A, B
         if log:
-            log(f"warmstart data: n={n} seed={seed} kept solves (iters) {kept}")
+            log(f"warmstart data: n={n} seed={seed} kept solves (iters) {kept}; {len(meta)} solves so far")
+        if max_solves and len(meta) >= max_solves:
+            break
     return torch.cat(feats), torch.cat(targs), meta
 
 
@@ -66,6 +104,11 @@ def training_pairs(count: int = 48, seed: int = 0):
     pairs with n uniform in [500, 5000], p = 0.02, rho = 0.7."""
     rng = np.random.default_rng(inputs.SEED_BASE + 600 + seed)
     return [(int(rng.integers(500, 5001)), 0.02, 0.7, inputs.SEED_BASE + 1000 + i) for i in range(count)]
+
+
+# Pair seeds of the training set start at SEED_BASE + 1000; held-out pairs
+# must lie outside [SEED_BASE + 1000, SEED_BASE + 1000 + TRAINING_PAIRS_MAX).
+TRAINING_PAIRS_MAX = 8000
 
 
 def train(F, t, steps: int = 2000, batch: int = 4096, lr: float = 1e-3, seed: int = 0, params=None, log=None):
@@ -115,27 +158,33 @@ def main(argv=None):
     """Generate samples with the plain solver, train on the GPU, save."""
     import argparse
     ap = argparse.ArgumentParser(description="train the Sinkhorn warm-start network")
-    ap.add_argument("--pairs", type=int, default=48)
-    ap.add_argument("--fw-iters", type=int, default=6)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--pairs", type=int, default=TRAINING_PAIRS_MAX, help="pairs available to draw from")
+    ap.add_argument("--solves", type=int, default=20000, help="stop generating after this many solves")
+    ap.add_argument("--fw-iters", type=int, default=30)
+    ap.add_argument("--workers", type=int, default=12, help="processes drawing the pairs")
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--out", default=DEFAULT_PATH)
     a = ap.parse_args(argv)
+    if a.pairs > TRAINING_PAIRS_MAX:
+        ap.error(f"--pairs must be at most {TRAINING_PAIRS_MAX} (held-out seeds follow)")
 
     def log(msg):
         print(msg, flush=True)
 
     t0 = time.time()
     pairs = training_pairs(a.pairs)
-    F, t, meta = generate(pairs, fw_iters=a.fw_iters, log=log)
-    log(f"{F.shape[0]} samples from {len(meta)} converged solves ({time.time() - t0:.0f} s)")
+    F, t, meta = generate(pairs, fw_iters=a.fw_iters, log=log, max_solves=a.solves, workers=a.workers)
+    used = len({m["seed"] for m in meta})
+    log(f"{F.shape[0]} samples from {len(meta)} converged solves of {used} pairs ({time.time() - t0:.0f} s)")
     params, hist = train(F, t, steps=a.steps, batch=a.batch, lr=a.lr, seed=a.seed)
     log(f"loss {hist[0][1]:.4f} -> {hist[-1][1]:.4f} ({time.time() - t0:.0f} s)")
-    save(params, a.out, meta=dict(pairs=a.pairs, fw_iters=a.fw_iters, steps=a.steps, batch=a.batch,
+    save(params, a.out, meta=dict(pairs=used, fw_iters=a.fw_iters, steps=a.steps, batch=a.batch,
                                   lr=a.lr, seed=a.seed, samples=int(F.shape[0]), solves=len(meta),
-                                  loss_first=hist[0][1], loss_last=hist[-1][1]))
+                                  loss_first=hist[0][1], loss_last=hist[-1][1],
+                                  seconds=round(time.time() - t0, 1)))
     log(f"saved {a.out}")
 
 

@@ -179,9 +179,14 @@ def test_sinkhorn_network_start_parity(G, n, iters):
     err = float(np.linalg.norm(Qd - ref.Q) / np.linalg.norm(ref.Q))
     m = ref.Q >= 1e-30
     emax = float(np.max(np.abs(Qd[m] - ref.Q[m]) / ref.Q[m]))
-    # the start differs from a cold one (so the network was applied)
-    cold = O.log_sinkhorn_max(Gd, eps, tol=0.0, max_iter=iters)
-    sep = float(np.linalg.norm(cold.Q - ref.Q) / np.linalg.norm(ref.Q))
-    print(f"  Q rel_fro={err:.2e} elem={emax:.2e}; network vs cold start {sep:.2e}")
+    # the network's start is not the cold one: after one sweep the device
+    # plan is the oracle's network-started plan, far from the cold-started one
+    one = G.sinkhorn(dev(Gm), eps_rel=0.03, max_iter=1, tol=0.0, mlp_params=dev(params))
+    ref1 = O.log_sinkhorn_max(Gd, eps, tol=0.0, max_iter=1, g0=g0)
+    cold1 = O.log_sinkhorn_max(Gd, eps, tol=0.0, max_iter=1)
+    Q1 = host(one.Q)
+    sep = float(np.linalg.norm(cold1.Q - ref1.Q) / np.linalg.norm(ref1.Q))
+    err1 = float(np.linalg.norm(Q1 - ref1.Q) / np.linalg.norm(ref1.Q))
+    print(f"  Q rel_fro={err:.2e} elem={emax:.2e}; after one sweep {err1:.2e}, network vs cold start {sep:.2e}")
     assert err <= 1e-4 and emax <= 1e-4
-    assert sep > 1e-3
+    assert err1 <= 1e-4 and sep > 10 * err1

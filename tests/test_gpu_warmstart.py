@@ -35,7 +35,7 @@ def params(G):
 
 def test_training_seeds_disjoint_from_held_out():
     from paper_2111_05366_amd import warmstart
-    train_seeds = {s for (_, _, _, s) in warmstart.training_pairs()}
+    train_seeds = {s for (_, _, _, s) in warmstart.training_pairs(warmstart.TRAINING_PAIRS_MAX)}
     assert not train_seeds & {s for (_, _, _, s) in HELD_OUT}
 
 
