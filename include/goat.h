@@ -149,6 +149,33 @@ int goat_sinkhorn(int n, const float* G, int ldg,
                   void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * goat_sinkhorn_noalloc - goat_sinkhorn without a workspace, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc). Same arguments, kernels
+ * and results as goat_sinkhorn (bit for bit); the solver's state lives in a
+ * static device array of goat_sinkhorn_noalloc_scratch_bytes() (64 MiB) that
+ * every GPU the library runs on holds until the process ends. The call
+ * allocates nothing and never takes profiler events.
+ *  n        1 <= n <= goat_sinkhorn_noalloc_max_n() (about 16,000 nodes).
+ *  G        16-byte aligned, ldg a multiple of 4, and of 64 when
+ *           max_iter >= 8 (G is never repacked).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (different streams or host threads) race and give wrong results; calls
+ * ordered on one stream are safe. Each call initialises the state it reads.
+ * Status: as goat_sinkhorn; GOAT_EINVAL also for n above the limit or a G
+ * that would need repacking.
+ */
+size_t goat_sinkhorn_noalloc_scratch_bytes(void);
+int    goat_sinkhorn_noalloc_max_n(void);
+int    goat_sinkhorn_noalloc(int n, const float* G, int ldg,
+                             const float* eps_dev, float eps_rel,
+                             float* f, float* g, int init, const float* mlp_params,
+                             int max_iter, float tol,
+                             float* Q, int ldq,
+                             int* iters_dev, float* err_dev, float* eps_out,
+                             void* stream);
+
+/*
  * goat_linesearch - exact step of Alg. 3 step 3. With D = Q - P the
  * objective is the quadratic f(P + tD) = fP + b t + a t^2 where
  *     fP = <P,GP>/2, fQ = <Q,GQ>/2, c = <Q,GP>, a = fP + fQ - c, b = c - 2 fP

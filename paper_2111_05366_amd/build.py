@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libgoat.so")
 ARCH = os.environ.get("GOAT_OFFLOAD_ARCH", "gfx950")
 OMP_LIBDIR = "/opt/rocm/lib/llvm/lib"   # host OpenMP runtime of the ROCm clang
 
-HIP_SOURCES = ["pack.hip", "gemm.hip", "sinkhorn.hip", "fw.hip", "mlp.hip", "batch.hip", "assign.hip"]
+HIP_SOURCES = ["pack.hip", "gemm.hip", "sinkhorn.hip", "fw.hip", "mlp.hip", "batch.hip", "assign.hip", "noalloc.hip"]
 CPP_SOURCES = ["api.cpp", "solve.cpp", "profile.cpp", "lap.cpp", "batch.cpp"]
 
 # packed-fp32 instructions stay disabled for all device code

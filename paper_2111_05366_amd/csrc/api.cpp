@@ -238,6 +238,52 @@ static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 
 using namespace goat;
 
+namespace goat {
+
+int sinkhorn_check(int n, const float* G, int ldg, const float* eps_dev, float eps_rel, const float* g, int init,
+                   const float* mlp_params, int max_iter, float tol, const float* Q, int ldq) {
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(G, "null pointer");
+    GOAT_CHECK_ARG(ldg >= n && (!Q || ldq >= n), "leading dimension < n");
+    GOAT_CHECK_ARG(init == GOAT_INIT_COLD || (init == GOAT_INIT_G && g) || (init == GOAT_INIT_MLP && mlp_params),
+                   "bad init (GOAT_INIT_G needs g, GOAT_INIT_MLP needs mlp_params)");
+    GOAT_CHECK_ARG(init != GOAT_INIT_MLP || n <= 20480, "the warm-start network takes n <= 20480");
+    GOAT_CHECK_ARG(max_iter >= 0, "max_iter < 0");
+    GOAT_CHECK_ARG(std::isfinite(tol) && tol >= 0.0f, "bad tol");
+    GOAT_CHECK_ARG(eps_dev || (std::isfinite(eps_rel) && eps_rel > 0.0f), "bad eps_rel");
+    return GOAT_OK;
+}
+
+bool sinkhorn_needs_repack(const float* G, int ldg, int max_iter) {
+    return (ldg % 4) != 0 || !aligned16(G) || ((ldg % 64) != 0 && max_iter >= 8);
+}
+
+// The LOT solve of goat_sinkhorn on G (ldg) with the small state at p:
+// starting potentials, sweeps (each launch samples the profiler only when
+// `sample`), then Q and the outputs.
+int sinkhorn_run(int n, const float* G, int ldg, const float* eps_dev, float eps_rel, float* f, float* g, int init,
+                 const float* mlp_params, int max_iter, float tol, float* Q, int ldq, int* iters_dev,
+                 float* err_dev, float* eps_out, const Ptrs& p, int np, bool sample, hipStream_t s) {
+    int rc = sk_prepare(n, G, ldg, eps_dev, eps_rel, nullptr, init == GOAT_INIT_G ? g : nullptr, tol, p.sk,
+                        p.fscal, p.red, s);
+    if (rc) return rc;
+    if (init == GOAT_INIT_MLP) {
+        // features of G / eps with the eps just set, the network, then the
+        // column potentials (the column partials are scratch until the sweeps)
+        rc = mlp_features(n, np, G, ldg, &p.sk.ctrl->eps, p.sk.colpart, p.feat, s);
+        if (!rc) rc = mlp_forward(n, p.feat, mlp_params, p.pred, s);
+        if (!rc) rc = warm_seed(n, p.pred, p.sk.ctrl, p.sk.vg, p.sk.vs, s);
+        if (rc) return rc;
+    }
+    for (int k = 0; k < max_iter; ++k) {
+        rc = sk_iterate(n, np, G, ldg, p.sk, k == 0, k >= 1, k, s, sample);
+        if (rc) return rc;
+    }
+    return sk_finalize(n, np, G, ldg, p.sk, Q, ldq, nullptr, nullptr, f, g, iters_dev, err_dev, eps_out, p.red, s);
+}
+
+}  // namespace goat
+
 extern "C" {
 
 int goat_version(void) { return 100; }
@@ -290,21 +336,15 @@ int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float ep
                   int init, const float* mlp_params, int max_iter, float tol, float* Q, int ldq, int* iters_dev,
                   float* err_dev, float* eps_out, void* ws, size_t ws_bytes, void* stream) {
     clear_error();
-    GOAT_CHECK_ARG(n >= 1, "n < 1");
-    GOAT_CHECK_ARG(G && ws, "null pointer");
-    GOAT_CHECK_ARG(ldg >= n && (!Q || ldq >= n), "leading dimension < n");
-    GOAT_CHECK_ARG(init == GOAT_INIT_COLD || (init == GOAT_INIT_G && g) || (init == GOAT_INIT_MLP && mlp_params),
-                   "bad init (GOAT_INIT_G needs g, GOAT_INIT_MLP needs mlp_params)");
-    GOAT_CHECK_ARG(init != GOAT_INIT_MLP || n <= 20480, "the warm-start network takes n <= 20480");
-    GOAT_CHECK_ARG(max_iter >= 0, "max_iter < 0");
-    GOAT_CHECK_ARG(std::isfinite(tol) && tol >= 0.0f, "bad tol");
-    GOAT_CHECK_ARG(eps_dev || (std::isfinite(eps_rel) && eps_rel > 0.0f), "bad eps_rel");
+    int rc = sinkhorn_check(n, G, ldg, eps_dev, eps_rel, g, init, mlp_params, max_iter, tol, Q, ldq);
+    if (rc) return rc;
+    GOAT_CHECK_ARG(ws, "null workspace");
     const Layout L = make_layout(n, GOAT_PREC_FP32, 1);
     // rows are swept as float4 and read best at 256-byte alignment: G is
     // copied into the padded layout when it is misaligned for float4, or when
     // its rows are not 256-byte multiples and enough sweeps follow to pay back
     // the copy (one read and one write of G)
-    const bool repack = (ldg % 4) != 0 || !aligned16(G) || ((ldg % 64) != 0 && max_iter >= 8);
+    const bool repack = sinkhorn_needs_repack(G, ldg, max_iter);
     const size_t need = small_bytes(L) + (repack ? (size_t)L.np * L.np * 4 : 0);
     if (ws_bytes < need) { set_error("goat_sinkhorn: workspace too small"); return GOAT_ENOMEM; }
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -312,28 +352,13 @@ int goat_sinkhorn(int n, const float* G, int ldg, const float* eps_dev, float ep
     const float* Gk = G;
     int ldk = ldg;
     if (repack) {
-        int rc = launch_copy_pad(n, G, ldg, p.P, L.np, L.np, s);
+        rc = launch_copy_pad(n, G, ldg, p.P, L.np, L.np, s);
         if (rc) return rc;
         Gk = p.P;
         ldk = L.np;
     }
-    int rc = sk_prepare(n, Gk, ldk, eps_dev, eps_rel, nullptr, init == GOAT_INIT_G ? g : nullptr, tol, p.sk,
-                        p.fscal, p.red, s);
-    if (rc) return rc;
-    if (init == GOAT_INIT_MLP) {
-        // features of G / eps with the eps just set, the network, then the
-        // column potentials (the column partials are scratch until the sweeps)
-        rc = mlp_features(n, L.np, Gk, ldk, &p.sk.ctrl->eps, p.sk.colpart, p.feat, s);
-        if (!rc) rc = mlp_forward(n, p.feat, mlp_params, p.pred, s);
-        if (!rc) rc = warm_seed(n, p.pred, p.sk.ctrl, p.sk.vg, p.sk.vs, s);
-        if (rc) return rc;
-    }
-    for (int k = 0; k < max_iter; ++k) {
-        rc = sk_iterate(n, L.np, Gk, ldk, p.sk, k == 0, k >= 1, k, s);
-        if (rc) return rc;
-    }
-    return sk_finalize(n, L.np, Gk, ldk, p.sk, Q, ldq, nullptr, nullptr, f, g, iters_dev, err_dev, eps_out,
-                       p.red, s);
+    return sinkhorn_run(n, Gk, ldk, eps_dev, eps_rel, f, g, init, mlp_params, max_iter, tol, Q, ldq, iters_dev,
+                        err_dev, eps_out, p, L.np, true, s);
 }
 
 int goat_linesearch(int n, const float* P, const float* Q, const float* GP, const float* GQ, int ld,

@@ -195,8 +195,10 @@ int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_r
 // the solve (row-walk direction alternates with its parity).
 // The first iteration shifts by the row maximum with single-float column
 // potentials; every later one uses the compensated potentials.
+// sample: the launch may take the profiler's sampled events (false: never,
+// so the call creates no event)
 int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check, int iter,
-               hipStream_t s);
+               hipStream_t s, bool sample = true);
 // Form Q (fp32 and optional bf16 split), its row-marginal error, potentials
 // in natural units, and (when P != NULL) the traces <Q,G>, <P,G>, ||Q-P||^2.
 int sk_finalize(int n, int np, const float* G, int ldg, SkState st,
@@ -258,6 +260,15 @@ struct Ptrs {
 };
 size_t small_bytes(const Layout& L);
 Ptrs make_ptrs(const Layout& L, void* ws);
+
+// goat_sinkhorn's argument checks, whether G must be repacked into the
+// workspace, and the solve itself on a prepared small state (api.cpp)
+int sinkhorn_check(int n, const float* G, int ldg, const float* eps_dev, float eps_rel, const float* g, int init,
+                   const float* mlp_params, int max_iter, float tol, const float* Q, int ldq);
+bool sinkhorn_needs_repack(const float* G, int ldg, int max_iter);
+int sinkhorn_run(int n, const float* G, int ldg, const float* eps_dev, float eps_rel, float* f, float* g, int init,
+                 const float* mlp_params, int max_iter, float tol, float* Q, int ldq, int* iters_dev,
+                 float* err_dev, float* eps_out, const Ptrs& p, int np, bool sample, hipStream_t s);
 int pack_graph(const Layout& L, const float* X, int ld, void* hi, void* lo, hipStream_t s);
 GradOps grad_ops(const Ptrs& p);
 

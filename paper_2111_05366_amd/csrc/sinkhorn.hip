@@ -643,13 +643,13 @@ int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_r
 }
 
 int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, int check, int iter,
-               hipStream_t s) {
+               hipStream_t s, bool sample) {
     const Geometry g = geometry(n);
     SkArgs a = make_args(n, np, G, ldg, st, g);
     a.rev = iter & 1;
     int rc;
-    hipEvent_t e0, e1;
-    const bool sampled = prof_sample(0, &e0, &e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const bool sampled = sample && prof_sample(0, &e0, &e1);
     if (g.T == 256)
         rc = first ? launch_row_T<256, true>(g, a, s, e0, e1) : launch_row_T<256, false>(g, a, s, e0, e1);
     else if (g.T == 512)
