@@ -207,7 +207,12 @@ typedef struct goat_options {
                              scores (default); 1 device auction on the quantised
                              scores (goat_lap_device; in a batch one workgroup
                              per problem); its errors are returned            */
-    int   reserved[4];
+    int   sk_g24;         /* 1: the Sinkhorn sweeps and Q read a 24-bit fixed-point
+                             copy of grad f(P), q = rint(G (2^23-1) / max|G|), made
+                             once per FW iteration: 3 bytes per entry instead of 4,
+                             G eps^-1 within max|G|/eps 2^-24 of the float value
+                             (mixed precisions only; 0: float G, the default)  */
+    int   reserved[3];
     const float* mlp_params; /* device float[goat_mlp_param_count()] (warm 2, 3) */
 } goat_options;
 
@@ -287,6 +292,14 @@ int  goat_run_finish(goat_run* run, int32_t* perm_host, goat_stats* stats_host,
 void goat_run_free(goat_run* run);
 /* Copy of the run's current gradient grad f(P) (n x n, ldg) into G_out. */
 int  goat_run_gradient(goat_run* run, float* G_out, int ldg);
+/* Copy of the last iteration's LOT direction Q (Alg. 3 step 2; n x n, ldq)
+ * into Q_out. GOAT_EINVAL before the first iteration or after a device
+ * assignment that reused the run's buffers. */
+int  goat_run_direction(goat_run* run, float* Q_out, int ldq);
+/* Sinkhorn cap and tolerance for the following goat_run_steps calls (a
+ * schedule per iteration, e.g. a fixed sweep count to replay another run).
+ * GOAT_EINVAL for sk_max < 1 or a negative or non-finite tolerance. */
+int  goat_run_set_sinkhorn(goat_run* run, int sk_max, float sk_tol);
 
 /*
  * Kernel timing hook (measurement only). which = 0: Sinkhorn row sweep;

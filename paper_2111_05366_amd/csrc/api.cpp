@@ -41,6 +41,8 @@ Layout make_layout(int n, int prec, int sym) {
     L.Q = take(pl * 4);
     L.GP = take(pl * 4);
     L.GQ = take(pl * 4);
+    // 24-bit copy of G for the Sinkhorn sweeps (mixed forms only)
+    if (prec != GOAT_PREC_FP32) L.g24 = take(pl * 3);
     // packed operands
     const int rows = L.sym ? 1 : 2;
     if (prec == GOAT_PREC_FP8) {

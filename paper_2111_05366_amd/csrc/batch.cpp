@@ -83,8 +83,8 @@ int validate(const goat_pair* pairs, int npairs, int restarts, const goat_option
         set_error("goat_batch: bad options");
         return GOAT_EINVAL;
     }
-    if (opt->prec != GOAT_PREC_FP32 || opt->warm < 0 || opt->warm > 1) {
-        set_error("goat_batch: only fp32 products and warm 0/1 are supported");
+    if (opt->prec != GOAT_PREC_FP32 || opt->warm < 0 || opt->warm > 1 || opt->sk_g24 != 0) {
+        set_error("goat_batch: only fp32 products, warm 0/1 and float G (sk_g24 = 0) are supported");
         return GOAT_ENOTSUP;
     }
     return GOAT_OK;

@@ -49,7 +49,7 @@ struct SkCtrl {                    // Sinkhorn control block (device)
     float err;                     // last checked row-marginal error
     float tol;
     float h;                       // grid step of the compensated potentials
-    int   pad;
+    float g24;                     // 24-bit storage of G: G kappa = q * g24
 };
 
 // Workspace layout. All internal matrices have leading dimension np.
@@ -59,6 +59,7 @@ struct Layout {
     size_t opP = 0;                // packed P-side operand
     size_t opY = 0;                // intermediate product (transposed layout)
     size_t P = 0, Q = 0, GP = 0, GQ = 0;   // solver matrices (fp32)
+    size_t g24 = 0;                // 24-bit copy of G_P (np rows of 3 np / 4 words; mixed forms), 0 = none
     size_t pot = 0;                // potentials: ug, us, ung, uns, vg, vs ([np] each)
     size_t colpart = 0, errpart = 0, ctrl = 0;
     size_t red = 0;                // float64 reduction partials
@@ -185,7 +186,17 @@ struct SkState {
     float* ung; float* uns;        // row potentials of the sweep in flight
     float* vg; float* vs;          // column potentials
     float* colpart; float* errpart; SkCtrl* ctrl;
+    // optional 24-bit fixed-point copy of G (sk_pack_g24): the sweeps and Q
+    // read it instead of the float G when set
+    const uint32_t* g24 = nullptr;
+    int ld24 = 0;                  // row stride in 32-bit words (3 np / 4)
 };
+// Writes the 24-bit copy of G into st.g24 (n rows of ld24 words, zero past
+// column n): q_ij = rint(G_ij (2^23 - 1) / max|G|), packed four to three
+// words, and ctrl->g24 = kappa max|G| / (2^23 - 1) so that G_ij kappa is read
+// back as q_ij * g24 (within max|G kappa| 2^-24 of the float value). Runs after
+// sk_prepare (kappa known); absmax_dev is the max|G| that sk_prepare used.
+int sk_pack_g24(int n, int np, const float* G, int ldg, const float* absmax_dev, SkState st, hipStream_t s);
 // eps = *eps_dev if given, else eps_rel * *absmax_dev if given, else
 // eps_rel * max|G| computed here (into fscal[0]).
 int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_rel,

@@ -35,6 +35,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include <hip/hip_ext.h>
 
@@ -131,7 +132,25 @@ struct SkArgs {
     float* colpart;            // [W][np]
     float* errpart;            // [W]
     SkCtrl* ctrl;
+    const uint32_t* G24;       // 24-bit copy of G (or null), ld24 words per row
+    int ld24;
 };
+
+// Four consecutive 24-bit two's-complement values packed little-endian in
+// three words (value k occupies bits 24k .. 24k + 23 of the 96-bit group).
+struct W3 {
+    uint32_t x, y, z;
+};
+__device__ inline float4 dec24(const W3 w) {
+    const int q0 = static_cast<int>(w.x << 8) >> 8;
+    const int q1 = static_cast<int>(__builtin_amdgcn_alignbit(w.y, w.x, 24) << 8) >> 8;
+    const int q2 = static_cast<int>(__builtin_amdgcn_alignbit(w.z, w.y, 16) << 8) >> 8;
+    const int q3 = static_cast<int>(w.z) >> 8;
+    return make_float4(static_cast<float>(q0), static_cast<float>(q1), static_cast<float>(q2),
+                       static_cast<float>(q3));
+}
+__device__ inline float4 as_f4(const float4 x) { return x; }
+__device__ inline float4 as_f4(const W3 w) { return dec24(w); }
 
 // Thread t of a strip owns the float4 column groups t, t + T, ..., t + (C-1)T.
 // VLDS: the column potentials sit in LDS (32 T C bytes) instead of
@@ -140,7 +159,7 @@ struct SkArgs {
 // between iterations re-reads first the rows streamed last.
 // Occupancy target: two strips per compute unit (4 waves per SIMD for 512
 // threads, 2 for 256), which caps the registers at 128 / 256.
-template <int T, int C, bool FIRST, bool PRECISE, bool VLDS>
+template <int T, int C, bool FIRST, bool PRECISE, bool VLDS, bool Q24>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(T >= 512 ? 4 : 2)))
 void sk_row_kernel(SkArgs a) {
     static_assert(!(FIRST && PRECISE), "the first sweep uses the plain form");
@@ -150,7 +169,8 @@ void sk_row_kernel(SkArgs a) {
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * a.rpw;
     const int r1 = min(a.n, r0 + a.rpw);
-    const float kappa = a.ctrl->kappa;
+    // Q24: G is read as 24-bit integers q with G kappa = q * g24
+    const float kappa = Q24 ? a.ctrl->g24 : a.ctrl->kappa;
     const float h = a.ctrl->h, inv_h = 1.0f / h;
 
     float4 vgr[VLDS ? 1 : C], vsr[VLDS ? 1 : C];
@@ -185,11 +205,13 @@ void sk_row_kernel(SkArgs a) {
     // column groups past the row end re-read the last group (in bounds since
     // ld >= 4 ceil(n/4)); their v = -inf makes them contribute exactly 0
     const int n4m1 = ((a.n + 3) >> 2) - 1;
-    float4 xa[C], xb[C];
+    using XT = typename std::conditional<Q24, W3, float4>::type;
+    XT xa[C], xb[C];
 #define GOAT_ROW_OF(K) (a.rev ? r1 - 1 - (K) : r0 + (K))
 #define GOAT_LOAD_ROW(X, I)                                                                        \
     do {                                                                                           \
-        const float4* row_ = reinterpret_cast<const float4*>(a.G + (size_t)(I) * a.ldg);          \
+        const XT* row_ = Q24 ? reinterpret_cast<const XT*>(a.G24 + (size_t)(I) * a.ld24)           \
+                             : reinterpret_cast<const XT*>(a.G + (size_t)(I) * a.ldg);            \
         _Pragma("unroll") for (int c = 0; c < C; ++c) X[c] = row_[min(tid + T * c, n4m1)];        \
     } while (0)
 #define GOAT_LOAD_U(U, I)                                                                          \
@@ -213,17 +235,18 @@ void sk_row_kernel(SkArgs a) {
         float y[C][4];                                                                             \
         _Pragma("unroll") for (int c = 0; c < C; ++c) {                                            \
             const float4 g4 = VLDS ? sv4[tid + T * c] : vgr[VLDS ? 0 : c];                         \
+            const float4 x4 = as_f4(XC[c]);                                                        \
             if (PRECISE) {                                                                         \
                 const float4 r4 = VLDS ? sv4[T * C + tid + T * c] : vsr[VLDS ? 0 : c];             \
-                y[c][0] = fmaf(XC[c].x, kappa, g4.x + ug) + r4.x;                                  \
-                y[c][1] = fmaf(XC[c].y, kappa, g4.y + ug) + r4.y;                                  \
-                y[c][2] = fmaf(XC[c].z, kappa, g4.z + ug) + r4.z;                                  \
-                y[c][3] = fmaf(XC[c].w, kappa, g4.w + ug) + r4.w;                                  \
+                y[c][0] = fmaf(x4.x, kappa, g4.x + ug) + r4.x;                                     \
+                y[c][1] = fmaf(x4.y, kappa, g4.y + ug) + r4.y;                                     \
+                y[c][2] = fmaf(x4.z, kappa, g4.z + ug) + r4.z;                                     \
+                y[c][3] = fmaf(x4.w, kappa, g4.w + ug) + r4.w;                                     \
             } else { /* plain: g4 holds v_grid + v_rem */                                          \
-                y[c][0] = fmaf(XC[c].x, kappa, g4.x) + uu;                                         \
-                y[c][1] = fmaf(XC[c].y, kappa, g4.y) + uu;                                         \
-                y[c][2] = fmaf(XC[c].z, kappa, g4.z) + uu;                                         \
-                y[c][3] = fmaf(XC[c].w, kappa, g4.w) + uu;                                         \
+                y[c][0] = fmaf(x4.x, kappa, g4.x) + uu;                                            \
+                y[c][1] = fmaf(x4.y, kappa, g4.y) + uu;                                            \
+                y[c][2] = fmaf(x4.z, kappa, g4.z) + uu;                                            \
+                y[c][3] = fmaf(x4.w, kappa, g4.w) + uu;                                            \
             }                                                                                      \
         }                                                                                          \
         /* XC is consumed before the next row's loads are issued: issued     */                    \
@@ -426,14 +449,15 @@ struct FinArgs {
     uint16_t* Qhi; uint16_t* Qlo;
 };
 
-template <int T, int C>
+template <int T, int C, bool Q24>
 __global__ __launch_bounds__(T) void sk_finalize_kernel(FinArgs fa) {
     const SkArgs& a = fa.a;
     __shared__ float red[2][T / 64];
     const int tid = threadIdx.x;
     const int r0 = blockIdx.x * a.rpw;
     const int r1 = min(a.n, r0 + a.rpw);
-    const float kappa = a.ctrl->kappa;
+    // Q24: Q is formed from the same 24-bit G the sweeps read
+    const float kappa = Q24 ? a.ctrl->g24 : a.ctrl->kappa;
     const bool flat = a.ctrl->done == 2;
     const float jval = 1.0f / (float)a.n;
     float errmax = 0.0f;
@@ -446,7 +470,10 @@ __global__ __launch_bounds__(T) void sk_finalize_kernel(FinArgs fa) {
         for (int c = 0; c < C; ++c) {
             const int j0 = 4 * (tid + T * c);
             if (j0 >= a.np && j0 >= a.n) continue;
-            const float4 g4 = j0 < a.n ? *reinterpret_cast<const float4*>(grow + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+            float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j0 < a.n)
+                g4 = Q24 ? dec24(reinterpret_cast<const W3*>(a.G24 + (size_t)i * a.ld24)[j0 >> 2])
+                         : *reinterpret_cast<const float4*>(grow + j0);
             const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
             float q[4];
 #pragma unroll
@@ -559,22 +586,28 @@ bool allow_lds(K kfn, size_t bytes) {
                                (int)bytes) == hipSuccess;
 }
 
-template <int T, int C, bool FIRST, bool PRECISE>
-void launch_row_TCP(const Geometry& g, const SkArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+template <int T, int C, bool FIRST, bool PRECISE, bool Q24>
+void launch_row_TCPQ(const Geometry& g, const SkArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const size_t lds = (size_t)(PRECISE ? 32 : 16) * T * C;
-    static const bool vlds = allow_lds(sk_row_kernel<T, C, FIRST, PRECISE, true>, lds);
+    static const bool vlds = allow_lds(sk_row_kernel<T, C, FIRST, PRECISE, true, Q24>, lds);
     if (e0) {
         // a sampled launch: the events mark the kernel's own start and end
         if (vlds)
-            hipExtLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, true>), dim3(g.W), dim3(T), (uint32_t)lds, s,
-                                  e0, e1, 0, a);
+            hipExtLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, true, Q24>), dim3(g.W), dim3(T),
+                                  (uint32_t)lds, s, e0, e1, 0, a);
         else
-            hipExtLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, false>), dim3(g.W), dim3(T), 0, s, e0, e1, 0,
-                                  a);
+            hipExtLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, false, Q24>), dim3(g.W), dim3(T), 0, s, e0,
+                                  e1, 0, a);
         return;
     }
-    if (vlds) hipLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, true>), dim3(g.W), dim3(T), lds, s, a);
-    else hipLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, false>), dim3(g.W), dim3(T), 0, s, a);
+    if (vlds) hipLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, true, Q24>), dim3(g.W), dim3(T), lds, s, a);
+    else hipLaunchKernelGGL((sk_row_kernel<T, C, FIRST, PRECISE, false, Q24>), dim3(g.W), dim3(T), 0, s, a);
+}
+
+template <int T, int C, bool FIRST, bool PRECISE>
+void launch_row_TCP(const Geometry& g, const SkArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (a.G24) launch_row_TCPQ<T, C, FIRST, PRECISE, true>(g, a, s, e0, e1);
+    else launch_row_TCPQ<T, C, FIRST, PRECISE, false>(g, a, s, e0, e1);
 }
 
 template <int T, bool FIRST>
@@ -595,7 +628,11 @@ template <int T>
 int launch_fin_T(const Geometry& g, const FinArgs& fa, hipStream_t s) {
     dim3 grid(g.W), block(T);
     switch (g.C) {
-#define GOAT_SK_C(CC) case CC: hipLaunchKernelGGL((sk_finalize_kernel<T, CC>), grid, block, 0, s, fa); break;
+#define GOAT_SK_C(CC)                                                                              \
+    case CC:                                                                                       \
+        if (fa.a.G24) hipLaunchKernelGGL((sk_finalize_kernel<T, CC, true>), grid, block, 0, s, fa);   \
+        else hipLaunchKernelGGL((sk_finalize_kernel<T, CC, false>), grid, block, 0, s, fa);           \
+        break;
         GOAT_SK_C(1) GOAT_SK_C(2) GOAT_SK_C(3) GOAT_SK_C(4) GOAT_SK_C(5) GOAT_SK_C(6)
         GOAT_SK_C(8) GOAT_SK_C(10) GOAT_SK_C(12) GOAT_SK_C(16)
 #undef GOAT_SK_C
@@ -619,7 +656,33 @@ SkArgs make_args(int n, int np, const float* G, int ldg, const SkState& st, cons
     a.colpart = st.colpart;
     a.errpart = st.errpart;
     a.ctrl = st.ctrl;
+    a.G24 = st.g24;
+    a.ld24 = st.ld24;
     return a;
+}
+
+// 24-bit copy of G: one thread per four columns of a row (zero past n)
+__global__ __launch_bounds__(256) void pack_g24_kernel(int n, int np, const float* __restrict__ G, int ldg,
+                                                       const float* absmax, SkCtrl* ctrl, uint32_t* out, int ld24) {
+    const float gmax = *absmax;
+    const float qmax = 8388607.0f;                      // 2^23 - 1
+    const float s = gmax > 0.0f ? qmax / gmax : 0.0f;
+    const int i = blockIdx.y;
+    const int j4 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && j4 == 0) ctrl->g24 = gmax > 0.0f ? ctrl->kappa * (gmax / qmax) : 0.0f;
+    if (4 * j4 >= np) return;
+    const float* row = G + (size_t)i * ldg;
+    int q[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int j = 4 * j4 + e;
+        const float x = j < n ? row[j] : 0.0f;
+        q[e] = static_cast<int>(fminf(fmaxf(rintf(x * s), -qmax), qmax));
+    }
+    uint32_t* w = out + (size_t)i * ld24 + 3 * j4;
+    w[0] = (static_cast<uint32_t>(q[0]) & 0xFFFFFFu) | (static_cast<uint32_t>(q[1]) << 24);
+    w[1] = ((static_cast<uint32_t>(q[1]) >> 8) & 0xFFFFu) | (static_cast<uint32_t>(q[2]) << 16);
+    w[2] = ((static_cast<uint32_t>(q[2]) >> 16) & 0xFFu) | (static_cast<uint32_t>(q[3]) << 8);
 }
 
 }  // namespace
@@ -638,6 +701,18 @@ int sk_prepare(int n, const float* G, int ldg, const float* eps_dev, float eps_r
     const SkArgs a = make_args(n, pad_n(n), G, ldg, st, g);
     hipLaunchKernelGGL(sk_init_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, eps_dev, eps_rel, absmax,
                        g_init, tol, a);
+    GOAT_HIP(hipGetLastError());
+    return GOAT_OK;
+}
+
+int sk_pack_g24(int n, int np, const float* G, int ldg, const float* absmax_dev, SkState st, hipStream_t s) {
+    if (!st.g24 || st.ld24 < 3 * (np / 4)) {
+        set_error("sinkhorn: no 24-bit buffer");
+        return GOAT_EINVAL;
+    }
+    dim3 grid((np / 4 + 255) / 256, n);
+    hipLaunchKernelGGL(pack_g24_kernel, grid, dim3(256), 0, s, n, np, G, ldg, absmax_dev, st.ctrl,
+                       const_cast<uint32_t*>(st.g24), st.ld24);
     GOAT_HIP(hipGetLastError());
     return GOAT_OK;
 }

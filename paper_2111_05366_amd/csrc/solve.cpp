@@ -92,6 +92,7 @@ static int run_sinkhorn(Run& r) {
     // eps from the max|G_P| that the previous update (or the start) left in fscal[0]
     int rc = sk_prepare(n, p.GP, np, nullptr, r.opt.eps_rel, p.fscal, prev ? p.g_prev : nullptr, r.opt.sk_tol,
                         p.sk, p.fscal, p.red, r.s);
+    if (!rc && p.sk.g24) rc = sk_pack_g24(n, np, p.GP, np, p.fscal, p.sk, r.s);
     if (rc) return rc;
     if (net) {
         rc = mlp_features(n, np, p.GP, np, &p.sk.ctrl->eps, p.sk.colpart, p.feat, r.s);
@@ -188,6 +189,8 @@ static int run_begin_impl(int n, const float* A, const float* B, int ld, const f
     GOAT_CHECK_ARG(opt.warm >= 0 && opt.warm <= 3, "unknown warm-start mode");
     GOAT_CHECK_ARG(opt.lap == 0 || opt.lap == 1, "unknown assignment mode");
     GOAT_CHECK_ARG(opt.warm < 2 || opt.mlp_params, "warm-start network requested without parameters");
+    GOAT_CHECK_ARG(opt.sk_g24 == 0 || (opt.sk_g24 == 1 && opt.prec != GOAT_PREC_FP32),
+                   "sk_g24 must be 0, or 1 with a mixed precision (its workspace holds the 24-bit copy)");
     const Layout L = make_layout(n, opt.prec, opt.symmetric);
     if (ws_bytes < L.total) { set_error("goat_run_begin: workspace too small"); return GOAT_ENOMEM; }
 
@@ -197,6 +200,10 @@ static int run_begin_impl(int n, const float* A, const float* B, int ld, const f
     r.wall0 = std::chrono::steady_clock::now();
     r.L = L;
     r.p = make_ptrs(L, ws);
+    if (opt.sk_g24) {
+        r.p.sk.g24 = reinterpret_cast<const uint32_t*>(static_cast<char*>(ws) + L.g24);
+        r.p.sk.ld24 = 3 * (L.np / 4);
+    }
     r.opt = opt;
     r.s = static_cast<hipStream_t>(stream);
     r.A = A;
@@ -356,6 +363,30 @@ int goat_run_gradient(goat_run* h, float* G_out, int ldg) {
     GOAT_HIP(hipMemcpy2DAsync(G_out, (size_t)ldg * 4, r.p.GP, (size_t)np * 4, (size_t)n * 4, n,
                               hipMemcpyDeviceToDevice, r.s));
     GOAT_HIP(hipStreamSynchronize(r.s));
+    return GOAT_OK;
+}
+
+int goat_run_direction(goat_run* h, float* Q_out, int ldq) {
+    clear_error();
+    GOAT_CHECK_ARG(h && Q_out, "null pointer");
+    Run& r = h->r;
+    const int n = r.L.n, np = r.L.np;
+    GOAT_CHECK_ARG(ldq >= n, "leading dimension < n");
+    GOAT_CHECK_ARG(r.fw > 0, "no iteration has run yet");
+    GOAT_CHECK_ARG(!r.operands_spent, "the device assignment has reused the run's buffers");
+    GOAT_HIP(hipMemcpy2DAsync(Q_out, (size_t)ldq * 4, r.p.Q, (size_t)np * 4, (size_t)n * 4, n,
+                              hipMemcpyDeviceToDevice, r.s));
+    GOAT_HIP(hipStreamSynchronize(r.s));
+    return GOAT_OK;
+}
+
+int goat_run_set_sinkhorn(goat_run* h, int sk_max, float sk_tol) {
+    clear_error();
+    GOAT_CHECK_ARG(h, "null run");
+    GOAT_CHECK_ARG(sk_max >= 1, "sk_max must be >= 1");
+    GOAT_CHECK_ARG(std::isfinite(sk_tol) && sk_tol >= 0.0f, "bad sk_tol");
+    h->r.opt.sk_max = sk_max;
+    h->r.opt.sk_tol = sk_tol;
     return GOAT_OK;
 }
 

@@ -32,7 +32,8 @@ class Options(ctypes.Structure):
                 ("fw_max", ctypes.c_int), ("fw_tol", ctypes.c_float), ("prec", ctypes.c_int),
                 ("symmetric", ctypes.c_int), ("proj", ctypes.c_int), ("warm", ctypes.c_int),
                 ("stop_on_stall", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("lap", ctypes.c_int), ("reserved", ctypes.c_int * 4), ("mlp_params", ctypes.c_void_p)]
+                ("lap", ctypes.c_int), ("sk_g24", ctypes.c_int), ("reserved", ctypes.c_int * 3),
+                ("mlp_params", ctypes.c_void_p)]
 
 
 class IterRecord(ctypes.Structure):
@@ -116,6 +117,10 @@ def lib():
     L.goat_run_finish.argtypes = [_VP, _VP, ctypes.POINTER(Stats), _VP, _I]
     L.goat_run_gradient.restype = _I
     L.goat_run_gradient.argtypes = [_VP, _VP, _I]
+    L.goat_run_direction.restype = _I
+    L.goat_run_direction.argtypes = [_VP, _VP, _I]
+    L.goat_run_set_sinkhorn.restype = _I
+    L.goat_run_set_sinkhorn.argtypes = [_VP, _I, _F]
     L.goat_run_free.restype = None
     L.goat_run_free.argtypes = [_VP]
     L.goat_mlp_param_count.restype = _I
@@ -444,6 +449,17 @@ class Run:
         G = torch.empty((self.n, self.n), dtype=torch.float32, device=self.A.device)
         _check(lib().goat_run_gradient(self.h, _ptr(G), self.n))
         return G
+
+    def direction(self):
+        """The last iteration's Sinkhorn direction Q as an n x n device tensor."""
+        torch = _torch()
+        Q = torch.empty((self.n, self.n), dtype=torch.float32, device=self.A.device)
+        _check(lib().goat_run_direction(self.h, _ptr(Q), self.n))
+        return Q
+
+    def set_sinkhorn(self, sk_max: int, sk_tol: float):
+        """Sinkhorn cap and tolerance for the following steps."""
+        _check(lib().goat_run_set_sinkhorn(self.h, int(sk_max), float(sk_tol)))
 
     def finish(self, return_P: bool = False):
         torch = _torch()

@@ -175,6 +175,16 @@ def test_bad_arguments_rejected_before_device(G):
     s = L.goat_solve(4, ctypes.c_void_p(16), ctypes.c_void_p(16), 4, None, ctypes.byref(o),
                      ctypes.c_void_p(16), None, None, 0, None, ctypes.c_void_p(16), 1 << 30, None)
     assert s == G.GOAT_EINVAL
+    o = G.default_options(sk_g24=1)            # the 24-bit copy needs a mixed precision
+    s = L.goat_solve(4, ctypes.c_void_p(16), ctypes.c_void_p(16), 4, None, ctypes.byref(o),
+                     ctypes.c_void_p(16), None, None, 0, None, ctypes.c_void_p(16), 1 << 30, None)
+    assert s == G.GOAT_EINVAL and b"sk_g24" in L.goat_last_error()
+    o = G.default_options(sk_g24=2, prec="bf16x2")
+    s = L.goat_solve(4, ctypes.c_void_p(16), ctypes.c_void_p(16), 4, None, ctypes.byref(o),
+                     ctypes.c_void_p(16), None, None, 0, None, ctypes.c_void_p(16), 1 << 30, None)
+    assert s == G.GOAT_EINVAL
+    # the mixed forms' workspace holds the 24-bit copy (3 n_p^2 bytes more than fp32's operands need)
+    assert L.goat_workspace_size(1000, 1, 1) >= 3 * 1024 * 1024
     o = G.default_options(eps_rel=float("inf"))
     s = L.goat_solve(4, ctypes.c_void_p(16), ctypes.c_void_p(16), 4, None, ctypes.byref(o),
                      ctypes.c_void_p(16), None, None, 0, None, ctypes.c_void_p(16), 1 << 30, None)
@@ -200,7 +210,8 @@ def test_batch_arguments_rejected_before_device(G):
         assert L.goat_batch_workspace_size(one, 1, 1, ctypes.byref(o), ctypes.byref(need)) == G.GOAT_EINVAL
     for kw, status in ((dict(prec=G.PREC["bf16x3"]), G.GOAT_ENOTSUP), (dict(warm=2), G.GOAT_ENOTSUP),
                        (dict(sk_max=0), G.GOAT_EINVAL), (dict(fw_max=0), G.GOAT_EINVAL),
-                       (dict(eps_rel=float("nan")), G.GOAT_EINVAL), (dict(proj=2), G.GOAT_EINVAL)):
+                       (dict(eps_rel=float("nan")), G.GOAT_EINVAL), (dict(proj=2), G.GOAT_EINVAL),
+                       (dict(sk_g24=1), G.GOAT_ENOTSUP)):
         ob = G.default_options(**kw)
         assert L.goat_batch_workspace_size(pairs, 2, 8, ctypes.byref(ob), ctypes.byref(need)) == status, kw
     assert L.goat_random_init(0, ctypes.c_void_p(16), 4, ctypes.c_void_p(16), 4, ctypes.c_float(1e-6), 10,
