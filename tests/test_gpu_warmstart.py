@@ -61,8 +61,11 @@ def test_iterations_saved_on_held_out(G, params):
             # baseline start: the first column update alone (the LSE feature)
             lse = G.sinkhorn(Gm, max_iter=3000, tol=1e-6, g0=(-F[:, 3] * cold.eps).contiguous(),
                              want_Q=False)
+            # converged: the sweep's stop measure was within 1e-6; the error of
+            # the returned plan is that measure recomputed from Q (FP32 sums in
+            # another order), hence the 5 % margin
             for o in (cold, warm, lse):
-                assert float(o.err.item()) <= 1e-6
+                assert int(o.iters.item()) < 3000 and float(o.err.item()) <= 1.05e-6
             # same fixed point: Q agrees entrywise
             assert float((cold.Q - warm.Q).abs().max().item()) <= 1e-4 * float(cold.Q.abs().max().item())
             ic, iw, il = int(cold.iters.item()), int(warm.iters.item()), int(lse.iters.item())

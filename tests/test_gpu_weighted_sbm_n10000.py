@@ -1,0 +1,142 @@
+"""End-to-end parity on the benchmark's workload, the weighted 4-block SBM
+pair at n = 10,000, against the FP64 oracle's first three Frank-Wolfe
+iterations (tests/golden/weighted_sbm_n10000_<form>.npz, written by
+tests/golden/make_weighted_sbm_n10000.py, which calls only oracle/ and the
+seeded input module). The two forms the benchmark times:
+
+  plain : fp32 gradient, cold Sinkhorn start, float G in the sweeps;
+  mixed : bf16 hi/lo gradient (three products), the warm-start network on
+          the first iteration and the previous potentials afterwards (the
+          oracle evaluates the same stored network in float64).
+
+Replay: each device iteration runs the oracle's number of Sinkhorn sweeps
+(goat_run_set_sinkhorn with tolerance 0), so both sides execute the same
+steps and differ only by arithmetic. The tolerance-driven stop is compared
+too, on the device's own sweep counts.
+
+Bounds. Iterations 1 and 2 evaluate eps, fP and c at states both sides
+share closely (the barycenter, then the first plan, whose solve takes 7
+sweeps): the objective tolerance, 1e-5 relative (eps carries the gradient's
+error at its largest entry, updated by linearity in FP32). fQ, and every
+scalar from iteration 3 on, depend on a plan of a slow solve (972 sweeps at
+iteration 2), which magnifies FP32 rounding of G along its slow modes: the
+Q tolerance of 1e-4 relative then bounds eps and c (linear in the plan) by
+1e-4 and f (quadratic) by 2e-4. Measured: 2e-8 to 5e-8 at the shared states
+against 1.8e-5 to 2.4e-5 for the plan-level ones. The first plan's eight
+stored rows: 1e-4 per entry. t: 1e-4 absolute.
+Mixed form: its gradient differs from the FP64 one by the bf16 hi/lo split
+(measured 6e-6 relative, bounded by 2e-5), which enters eps, fP and c at
+first order (bounds 3e-5) and every plan entry through exp(G / eps) with
+G / eps up to 1 / 0.03 = 33, so by up to 33 * 2e-5 = 7e-4 (bound 1e-3 per
+entry; plan-level scalars 1e-3 for eps and c, 2e-3 for f)."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2111_05366_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+N = 10000
+
+BOUNDS = {
+    "plain": dict(eps=1e-5, state=1e-5, plan_c=1e-4, plan_f=2e-4, t=1e-4, q=1e-4),
+    "mixed": dict(eps=3e-5, state=3e-5, plan_c=1e-3, plan_f=2e-3, t=1e-4, q=1e-3),
+}
+
+
+def _golden(form):
+    path = os.path.join(HERE, "golden", f"weighted_sbm_n10000_{form}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} has not been generated")
+    return np.load(path, allow_pickle=False)
+
+
+@pytest.fixture(scope="module")
+def G():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_05366_amd import goat
+    goat.lib()
+    yield goat
+    goat.release_workspace()
+
+
+@pytest.fixture(scope="module")
+def pair(G):
+    g = I.workload_weighted_sbm(N)
+    return torch.as_tensor(g.A, device="cuda"), torch.as_tensor(g.B, device="cuda")
+
+
+def _run(G, pair, form, **kw):
+    from paper_2111_05366_amd import warmstart
+    A, B = pair
+    if form == "plain":
+        return G.Run(A, B, prec="fp32", warm=0, stop_on_stall=0, sk_max=1000, sk_tol=1e-6, **kw)
+    return G.Run(A, B, prec="bf16x3", warm=3, mlp_params=warmstart.load(), stop_on_stall=0,
+                 sk_max=1000, sk_tol=1e-6, **kw)
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+@pytest.mark.parametrize("form", ["plain", "mixed"])
+def test_replay_matches_oracle(G, pair, form):
+    ref = _golden(form)
+    bd = BOUNDS[form]
+    run = _run(G, pair, form)
+    rows = ref["rows"]
+    for k in range(3):
+        run.set_sinkhorn(int(ref["sk_iters"][k]), 0.0)
+        assert run.steps(1) == 1
+        h = run.history[-1]
+        errs = {key: _rel(h[key], float(ref[key][k])) for key in ("eps", "fP", "fQ", "c")}
+        print(f"{form} it {k + 1}: sweeps {h['sk_iters']} (oracle {int(ref['sk_iters'][k])}), "
+              + ", ".join(f"{key} {v:.2e}" for key, v in errs.items())
+              + f", t {h['t']:.6f} vs {float(ref['t'][k]):.6f}, sk_err {h['sk_err']:.2e} vs {float(ref['sk_err'][k]):.2e}",
+              flush=True)
+        assert h["sk_iters"] == int(ref["sk_iters"][k])
+        assert errs["fQ"] <= bd["plan_f"]
+        if k < 2:
+            assert errs["eps"] <= bd["eps"]
+            assert errs["fP"] <= bd["state"] and errs["c"] <= bd["state"]
+        else:
+            assert errs["eps"] <= bd["plan_c"]
+            assert errs["fP"] <= bd["plan_f"] and errs["c"] <= bd["plan_c"]
+        assert abs(h["t"] - float(ref["t"][k])) <= bd["t"]
+        if k == 0:
+            Q = run.direction()[torch.as_tensor(rows, device="cuda")].double().cpu().numpy()
+            Qr = ref["Q_rows_it1"]
+            m = Qr >= 1e-30
+            qerr = float(np.max(np.abs(Q[m] - Qr[m]) / Qr[m]))
+            fro = float(np.linalg.norm(Q - Qr) / np.linalg.norm(Qr))
+            print(f"{form} it 1: Q rows element-wise {qerr:.2e}, Frobenius {fro:.2e}", flush=True)
+            assert qerr <= bd["q"]
+    run.close()
+
+
+@pytest.mark.parametrize("form", ["plain", "mixed"])
+def test_tolerance_stop_against_oracle(G, pair, form):
+    # the device's own stop rule on the same pair: the sweep counts may
+    # differ where a solve crosses the tolerance slowly (the FP32 marginal
+    # error differs from the FP64 one by up to its compensated floor), and
+    # both then stop within the tolerance band; the steps agree as in replay
+    ref = _golden(form)
+    run = _run(G, pair, form)
+    run.steps(3)
+    for k, h in enumerate(run.history):
+        print(f"{form} free it {k + 1}: sweeps {h['sk_iters']} vs {int(ref['sk_iters'][k])}, "
+              f"fP {_rel(h['fP'], float(ref['fP'][k])):.2e}, c {_rel(h['c'], float(ref['c'][k])):.2e}, "
+              f"fQ {_rel(h['fQ'], float(ref['fQ'][k])):.2e}, t {h['t']:.6f} vs {float(ref['t'][k]):.6f}, "
+              f"sk_err {h['sk_err']:.2e} vs {float(ref['sk_err'][k]):.2e}", flush=True)
+        if int(ref["sk_iters"][k]) < 1000:
+            assert h["sk_iters"] < 1000 and h["sk_err"] <= 1e-6
+            assert abs(h["sk_iters"] - int(ref["sk_iters"][k])) <= 0.01 * int(ref["sk_iters"][k]) + 1
+        else:
+            assert h["sk_iters"] == 1000
+        assert abs(h["t"] - float(ref["t"][k])) <= 1e-4
+    run.close()
