@@ -44,7 +44,8 @@ MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "fp32": 157.3}
 # only for the kernel source it was measured on (sha256 of the row-sweep
 # kernel's text in sinkhorn.hip, from its template line to the column-update
 # comment); reported as null otherwise.
-TRAFFIC = {"src_sha256": None, "bytes_per_launch": {"f32": None, "g24": None}}
+TRAFFIC = {"src_sha256": "5d4f53b9a3ea9707915e452f142e8a47fad82ac82ac098de097bdae38d0e3202",
+           "bytes_per_launch": {"f32": 411315730, "g24": None}}
 
 
 def row_kernel_digest():
