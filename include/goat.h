@@ -29,7 +29,8 @@
  *    the outputs.
  *
  * Entry points
- *  - one Frank-Wolfe iteration's pieces: goat_grad (Alg. 3 step 1),
+ *  - one Frank-Wolfe iteration's pieces: goat_grad (Alg. 3 step 1; or
+ *    goat_pack once and goat_grad_packed per gradient),
  *    goat_sinkhorn (LOT direction, Alg. 2), goat_linesearch (step 3);
  *  - whole solves: goat_solve, goat_run_begin/steps/finish/gradient/free,
  *    goat_solve_seeded (seeds, unequal sizes), goat_random_init and
@@ -106,6 +107,23 @@ int goat_grad(int n, const float* A, const float* B, int ld,
               const float* P, int ldp, float* G, int ldg,
               int prec, int symmetric,
               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * goat_pack / goat_grad_packed - goat_grad in two parts, for callers that
+ * take many gradients of one pair: goat_pack converts A and B once into the
+ * matrix-core operands of `prec` (fp32, bf16, bf16 hi + lo planes or FP8
+ * E4M3; [X; X^T] stacked when symmetric = 0), zero padded, into the
+ * workspace (goat_workspace_size(n, prec, symmetric) bytes); every
+ * goat_grad_packed call with the same workspace, n, prec and symmetric then
+ * computes G = grad f(P) (Alg. 3 step 1) from them. The packed operands stay
+ * valid until the workspace is used by another call; goat_grad packs into
+ * the same place, so goat_grad_packed after goat_grad reuses its operands.
+ * Results are those of goat_grad, bit for bit. Asynchronous on `stream`.
+ */
+int goat_pack(int n, const float* A, const float* B, int ld, int prec, int symmetric,
+              void* ws, size_t ws_bytes, void* stream);
+int goat_grad_packed(int n, const float* P, int ldp, float* G, int ldg, int prec, int symmetric,
+                     void* ws, size_t ws_bytes, void* stream);
 
 /*
  * goat_sinkhorn - LOT direction (Alg. 2 with the cost negated, as the

@@ -313,6 +313,41 @@ void goat_default_options(goat_options* opt) {
     opt->check_every = 16;
 }
 
+int goat_pack(int n, const float* A, const float* B, int ld, int prec, int symmetric, void* ws, size_t ws_bytes,
+              void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(A && B && ws, "null pointer");
+    GOAT_CHECK_ARG(ld >= n, "leading dimension < n");
+    GOAT_CHECK_ARG(prec >= GOAT_PREC_FP32 && prec <= GOAT_PREC_FP8, "unknown precision");
+    const Layout L = make_layout(n, prec, symmetric);
+    if (ws_bytes < L.total) { set_error("goat_pack: workspace too small"); return GOAT_ENOMEM; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ptrs p = make_ptrs(L, ws);
+    int rc = pack_graph(L, A, ld, p.A_hi, p.A_lo, s);
+    if (!rc) rc = pack_graph(L, B, ld, p.B_hi, p.B_lo, s);
+    return rc;
+}
+
+int goat_grad_packed(int n, const float* P, int ldp, float* G, int ldg, int prec, int symmetric, void* ws,
+                     size_t ws_bytes, void* stream) {
+    clear_error();
+    GOAT_CHECK_ARG(n >= 1, "n < 1");
+    GOAT_CHECK_ARG(P && G && ws, "null pointer");
+    GOAT_CHECK_ARG(ldp >= n && ldg >= n, "leading dimension < n");
+    GOAT_CHECK_ARG(prec >= GOAT_PREC_FP32 && prec <= GOAT_PREC_FP8, "unknown precision");
+    const Layout L = make_layout(n, prec, symmetric);
+    if (ws_bytes < L.total) { set_error("goat_grad_packed: workspace too small"); return GOAT_ENOMEM; }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ptrs p = make_ptrs(L, ws);
+    int rc;
+    if (prec == GOAT_PREC_FP8) rc = prep_fp8_operand(L, grad_ops(p), P, ldp, s);
+    else if (prec == GOAT_PREC_FP32) rc = launch_copy_pad(n, P, ldp, static_cast<float*>(p.P_hi), L.np, L.np, s);
+    else rc = launch_split_bf16(n, L.np, P, ldp, static_cast<uint16_t*>(p.P_hi), static_cast<uint16_t*>(p.P_lo), s);
+    if (rc) return rc;
+    return grad_packed(L, grad_ops(p), G, ldg, n, s);
+}
+
 int goat_grad(int n, const float* A, const float* B, int ld, const float* P, int ldp, float* G, int ldg,
               int prec, int symmetric, void* ws, size_t ws_bytes, void* stream) {
     clear_error();

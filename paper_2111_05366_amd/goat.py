@@ -88,6 +88,10 @@ def lib():
     L.goat_default_options.argtypes = [ctypes.POINTER(Options)]
     L.goat_grad.restype = _I
     L.goat_grad.argtypes = [_I, _VP, _VP, _I, _VP, _I, _VP, _I, _I, _I, _VP, _SZ, _VP]
+    L.goat_pack.restype = _I
+    L.goat_pack.argtypes = [_I, _VP, _VP, _I, _I, _I, _VP, _SZ, _VP]
+    L.goat_grad_packed.restype = _I
+    L.goat_grad_packed.argtypes = [_I, _VP, _I, _VP, _I, _I, _I, _VP, _SZ, _VP]
     L.goat_sinkhorn.restype = _I
     L.goat_sinkhorn.argtypes = [_I, _VP, _I, _VP, _F, _VP, _VP, _I, _VP, _I, _F, _VP, _I, _VP, _VP, _VP,
                                 _VP, _SZ, _VP]
@@ -259,6 +263,31 @@ def grad(A, B, P, prec: str = "fp32", symmetric: bool = True, out=None):
     _check(lib().goat_grad(n, _ptr(A), _ptr(B), A.stride(0), _ptr(P), P.stride(0), _ptr(G), G.stride(0),
                            PREC[prec], int(symmetric), _ptr(ws), ws.numel(), _stream()))
     return G
+
+
+class Packed:
+    """A pair packed once into matrix-core operands (goat_pack), for many
+    gradients by goat_grad_packed. Holds its own workspace; A and B may be
+    released after construction."""
+
+    def __init__(self, A, B, prec: str = "fp32", symmetric: bool = True):
+        torch = _torch()
+        _mat(A, "A"); _mat(B, "B")
+        if A.stride(0) != B.stride(0):
+            raise ValueError("A and B must share a leading dimension")
+        self.n, self.prec, self.symmetric = A.shape[0], prec, bool(symmetric)
+        need = workspace_size(self.n, prec, self.symmetric)
+        self.ws = torch.empty(need, dtype=torch.uint8, device=A.device)
+        _check(lib().goat_pack(self.n, _ptr(A), _ptr(B), A.stride(0), PREC[prec], int(self.symmetric),
+                               _ptr(self.ws), need, _stream()))
+
+    def grad(self, P, out=None):
+        torch = _torch()
+        _mat(P, "P")
+        G = out if out is not None else torch.empty((self.n, self.n), dtype=torch.float32, device=P.device)
+        _check(lib().goat_grad_packed(self.n, _ptr(P), P.stride(0), _ptr(G), G.stride(0), PREC[self.prec],
+                                      int(self.symmetric), _ptr(self.ws), self.ws.numel(), _stream()))
+        return G
 
 
 @dataclass

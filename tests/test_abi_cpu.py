@@ -169,6 +169,13 @@ def test_bad_arguments_rejected_before_device(G):
     s = L.goat_sinkhorn(4, ctypes.c_void_p(16), 4, None, ctypes.c_float(0.03), None, None, 0, None, 10,
                         ctypes.c_float(float("nan")), None, 4, None, None, None, ctypes.c_void_p(16), 1 << 30, None)
     assert s == G.GOAT_EINVAL          # non-finite tol
+    dummy = ctypes.c_void_p(16)
+    assert L.goat_pack(0, dummy, dummy, 4, 0, 1, dummy, 1 << 30, None) == G.GOAT_EINVAL
+    assert L.goat_pack(4, dummy, None, 4, 0, 1, dummy, 1 << 30, None) == G.GOAT_EINVAL
+    assert L.goat_pack(4, dummy, dummy, 4, 7, 1, dummy, 1 << 30, None) == G.GOAT_EINVAL
+    assert L.goat_pack(4, dummy, dummy, 4, 0, 1, dummy, 16, None) == G.GOAT_ENOMEM
+    assert L.goat_grad_packed(4, dummy, 3, dummy, 4, 0, 1, dummy, 1 << 30, None) == G.GOAT_EINVAL
+    assert L.goat_grad_packed(4, dummy, 4, dummy, 4, 1, 1, dummy, 16, None) == G.GOAT_ENOMEM
     s = L.goat_linesearch(4, None, None, None, None, 4, None, None, 0, None)
     assert s == G.GOAT_EINVAL
     o = G.default_options(sk_max=0)

@@ -297,3 +297,18 @@ def test_nonfinite_graph_rejected(G, which, value):
     # the library keeps working after the refusal
     r = G.solve(dev(g.A), dev(g.B), sk_max=50, fw_max=2)
     assert r.stats.fw_iters >= 1
+
+
+@pytest.mark.parametrize("prec,sym,kind", [("fp32", True, "wsbm"), ("bf16x3", True, "wsbm"), ("bf16x2", False, "dir01"),
+                                           ("fp8", True, "er")])
+def test_pack_once_then_gradients(G, prec, sym, kind):
+    # goat_pack + goat_grad_packed give goat_grad's result bit for bit, for
+    # several P with one packing
+    n = 300
+    A, B = _pair(kind, n, 70)
+    pk = G.Packed(dev(A), dev(B), prec=prec, symmetric=sym)
+    for seed in (71, 72):
+        P = dev(I.uniform_matrix(n, seed) / n)
+        got = host(pk.grad(P))
+        ref = host(G.grad(dev(A), dev(B), P, prec=prec, symmetric=sym))
+        assert np.array_equal(got, ref)
