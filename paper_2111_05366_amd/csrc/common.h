@@ -190,6 +190,10 @@ struct SkState {
     // read it instead of the float G when set
     const uint32_t* g24 = nullptr;
     int ld24 = 0;                  // row stride in 32-bit words (3 np / 4)
+    // optional host-visible stop flag (pinned host memory): the kernels that
+    // set ctrl->done also store it here, so a host loop can poll it after an
+    // event without a device-to-host copy
+    int* hdone = nullptr;
 };
 // Writes the 24-bit copy of G into st.g24 (n rows of ld24 words, zero past
 // column n): q_ij = rint(G_ij (2^23 - 1) / max|G|), packed four to three

@@ -134,6 +134,7 @@ struct SkArgs {
     SkCtrl* ctrl;
     const uint32_t* G24;       // 24-bit copy of G (or null), ld24 words per row
     int ld24;
+    int* hdone;                // host-visible copy of ctrl->done (or null)
 };
 
 // Four consecutive 24-bit two's-complement values packed little-endian in
@@ -163,7 +164,6 @@ template <int T, int C, bool FIRST, bool PRECISE, bool VLDS, bool Q24>
 __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(T >= 512 ? 4 : 2)))
 void sk_row_kernel(SkArgs a) {
     static_assert(!(FIRST && PRECISE), "the first sweep uses the plain form");
-    if (a.ctrl->done) return;
     extern __shared__ float4 sv4[];          // [T*C] v (grid parts), then [T*C] remainders if PRECISE
     __shared__ float red[2][T / 64];
     const int tid = threadIdx.x;
@@ -173,33 +173,9 @@ void sk_row_kernel(SkArgs a) {
     const float kappa = Q24 ? a.ctrl->g24 : a.ctrl->kappa;
     const float h = a.ctrl->h, inv_h = 1.0f / h;
 
-    float4 vgr[VLDS ? 1 : C], vsr[VLDS ? 1 : C];
-    float acc[C][4];
-    bool live[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        const int j4 = tid + T * c;
-        live[c] = 4 * j4 < a.n;
-        float g[4], r[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int j = 4 * j4 + e;
-            g[e] = (j < a.n) ? a.vg[j] : -INFINITY;
-            r[e] = (j < a.n) ? a.vs[j] : 0.0f;
-            if (!PRECISE) { g[e] += r[e]; r[e] = 0.0f; }
-            acc[c][e] = 0.0f;
-        }
-        const float4 g4 = make_float4(g[0], g[1], g[2], g[3]);
-        const float4 r4 = make_float4(r[0], r[1], r[2], r[3]);
-        if (VLDS) {
-            sv4[j4] = g4;
-            if (PRECISE) sv4[T * C + j4] = r4;
-        } else {
-            vgr[VLDS ? 0 : c] = g4;
-            vsr[VLDS ? 0 : c] = r4;
-        }
-    }
-    if (VLDS) __syncthreads();
+    // Prologue: the strip's first row, its potential and the column
+    // potentials are all requested before the stop flag is read, so the
+    // launch waits for one memory round trip instead of three.
     float errmax = 0.0f;
     const int nrows = r1 - r0;
     // column groups past the row end re-read the last group (in bounds since
@@ -218,6 +194,56 @@ void sk_row_kernel(SkArgs a) {
     do {                                                                                           \
         if (!FIRST) U = make_float2(a.ug[I], a.us[I]);                                             \
     } while (0)
+    float2 ua = make_float2(0.0f, 0.0f), ub = ua;
+    if (nrows > 0) {
+        GOAT_LOAD_ROW(xa, GOAT_ROW_OF(0));
+        GOAT_LOAD_U(ua, GOAT_ROW_OF(0));
+    }
+    // np-sized arrays: one vector load per group inside np, entries past n
+    // replaced below
+    float4 gld[C], rld[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j4 = tid + T * c;
+        gld[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+        rld[c] = gld[c];
+        if (4 * j4 < a.np) {
+            gld[c] = reinterpret_cast<const float4*>(a.vg)[j4];
+            rld[c] = reinterpret_cast<const float4*>(a.vs)[j4];
+        }
+    }
+    // the stop flag is read with the loads above in flight (a launch after
+    // convergence discards them)
+    if (a.ctrl->done) return;
+    float4 vgr[VLDS ? 1 : C], vsr[VLDS ? 1 : C];
+    float acc[C][4];
+    bool live[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int j4 = tid + T * c;
+        live[c] = 4 * j4 < a.n;
+        float g[4], r[4];
+        const float4 gl = gld[c], rl = rld[c];
+        const float glv[4] = {gl.x, gl.y, gl.z, gl.w}, rlv[4] = {rl.x, rl.y, rl.z, rl.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * j4 + e;
+            g[e] = (j < a.n) ? glv[e] : -INFINITY;
+            r[e] = (j < a.n) ? rlv[e] : 0.0f;
+            if (!PRECISE) { g[e] += r[e]; r[e] = 0.0f; }
+            acc[c][e] = 0.0f;
+        }
+        const float4 g4 = make_float4(g[0], g[1], g[2], g[3]);
+        const float4 r4 = make_float4(r[0], r[1], r[2], r[3]);
+        if (VLDS) {
+            sv4[j4] = g4;
+            if (PRECISE) sv4[T * C + j4] = r4;
+        } else {
+            vgr[VLDS ? 0 : c] = g4;
+            vsr[VLDS ? 0 : c] = r4;
+        }
+    }
+    if (VLDS) __syncthreads();
     // One row k held in XC with its potential (u_grid, u_rem) in UC; the next
     // row and its potential are loaded into XN, UN before row k is used, so
     // no row starts with a dependent memory round trip. The row remainder
@@ -289,11 +315,6 @@ void sk_row_kernel(SkArgs a) {
             a.uns[i] = r_;                                                                         \
         }                                                                                          \
     } while (0)
-    float2 ua = make_float2(0.0f, 0.0f), ub = ua;
-    if (nrows > 0) {
-        GOAT_LOAD_ROW(xa, GOAT_ROW_OF(0));
-        GOAT_LOAD_U(ua, GOAT_ROW_OF(0));
-    }
     int par = 0;
     for (int k = 0; k < nrows; k += 2) {
         GOAT_ROW_STEP(xa, xb, ua, ub, k);
@@ -321,8 +342,9 @@ void sk_row_kernel(SkArgs a) {
 // a fixed order (strip lane l adds strips l, l + 32, ...; lanes combined in
 // order), then v_j <- v_j - log2 c_j and u <- u_new. 256 threads = 8 float4
 // column groups (one 128-byte line of a partial row) x 32 strip lanes per
-// block, n/32 blocks. With check, the largest row-marginal error of the
-// sweep decides convergence first (no update then).
+// block, n/32 blocks; L strips per lane (W <= 32 L). With check, the largest
+// row-marginal error of the sweep decides convergence first (no update then).
+template <int L>
 __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int check) {
     __shared__ float4 part[32][8];
     __shared__ float red[4];
@@ -330,26 +352,32 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
     // Every load of the kernel is issued before the first one is used: the
     // stop flag, the control scalars, the column partials, the strips'
     // error partials and (threads that write columns) the potentials, so
-    // the kernel waits for one memory round trip instead of four. Loads made
-    // after convergence are read and discarded.
+    // the kernel waits for one memory round trip instead of four. The strip
+    // loop has a fixed trip count (loads past W are predicated off), so no
+    // lane waits on its loads one at a time. Loads made after convergence
+    // are read and discarded.
     const int done = a.ctrl->done;
     const float tol = a.ctrl->tol, h = a.ctrl->h;
     const int cq = tid & 7, sl = tid >> 3;
     const int j4 = blockIdx.x * 8 + cq;
     const bool ok = 4 * j4 < a.n;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (ok) {
+    float4 t[L];
+    {
         const float4* cp = reinterpret_cast<const float4*>(a.colpart);
         const size_t stride = (size_t)a.np / 4;
-#pragma unroll 8
-        for (int w = sl; w < W; w += 32) {
-            const float4 t = cp[(size_t)w * stride + j4];
-            acc.x += t.x; acc.y += t.y; acc.z += t.z; acc.w += t.w;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            const int w = sl + 32 * l;
+            t[l] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (ok && w < W) t[l] = cp[(size_t)w * stride + j4];
         }
     }
-    float m = 0.0f;
-    if (check)
-        for (int w = tid; w < W; w += 256) m = fmaxf(m, a.errpart[w]);
+    // error partials: the array holds kSkWG >= 32 L entries, so every lane
+    // loads (a predicated load would make the compiler wait for it in its
+    // branch); entries past W are masked when the maximum is taken
+    float e[L / 8];
+#pragma unroll
+    for (int l = 0; l < L / 8; ++l) e[l] = a.errpart[tid + 256 * l];
     // potentials of this thread's four columns (np-sized arrays, so the
     // vector loads stay in bounds past n)
     float4 vg4 = make_float4(0.f, 0.f, 0.f, 0.f), vs4 = vg4, ung4 = vg4, uns4 = vg4;
@@ -359,6 +387,16 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
         ung4 = reinterpret_cast<const float4*>(a.ung)[j4];
         uns4 = reinterpret_cast<const float4*>(a.uns)[j4];
     }
+    // strips added in increasing order (zeros past W leave the sum unchanged)
+    float4 acc = t[0];
+#pragma unroll
+    for (int l = 1; l < L; ++l) {
+        acc.x += t[l].x; acc.y += t[l].y; acc.z += t[l].z; acc.w += t[l].w;
+    }
+    float m = 0.0f;
+#pragma unroll
+    for (int l = 0; l < L / 8; ++l)
+        if (check && tid + 256 * l < W) m = fmaxf(m, e[l]);
     if (done) return;
     if (check) {
         m = wave_max(m);
@@ -369,6 +407,10 @@ __global__ __launch_bounds__(256) void sk_merge_kernel(SkArgs a, int W, int chec
             if (blockIdx.x == 0 && tid == 0) {
                 a.ctrl->err = err;
                 a.ctrl->done = 1;
+                if (a.hdone) {
+                    *a.hdone = 1;
+                    __threadfence_system();
+                }
             }
             return;
         }
@@ -435,6 +477,10 @@ __global__ __launch_bounds__(256) void sk_init_kernel(int n, const float* eps_de
         a.ctrl->eps = eps;
         a.ctrl->h = h;
         a.ctrl->done = ok ? 0 : 2;
+        if (a.hdone) {
+            *a.hdone = ok ? 0 : 2;
+            __threadfence_system();
+        }
         a.ctrl->iters = 0;
         a.ctrl->err = 0.0f;
         a.ctrl->tol = tol;
@@ -658,6 +704,7 @@ SkArgs make_args(int n, int np, const float* G, int ldg, const SkState& st, cons
     a.ctrl = st.ctrl;
     a.G24 = st.g24;
     a.ld24 = st.ld24;
+    a.hdone = st.hdone;
     return a;
 }
 
@@ -724,7 +771,8 @@ int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, in
     a.rev = iter & 1;
     int rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool sampled = sample && prof_sample(0, &e0, &e1);
+    // only the steady-state (compensated) sweep is sampled
+    const bool sampled = sample && !first && prof_sample(0, &e0, &e1);
     if (g.T == 256)
         rc = first ? launch_row_T<256, true>(g, a, s, e0, e1) : launch_row_T<256, false>(g, a, s, e0, e1);
     else if (g.T == 512)
@@ -733,7 +781,10 @@ int sk_iterate(int n, int np, const float* G, int ldg, SkState st, int first, in
         rc = first ? launch_row_T<1024, true>(g, a, s, e0, e1) : launch_row_T<1024, false>(g, a, s, e0, e1);
     if (sampled && rc == GOAT_OK) prof_commit(0);
     if (rc) return rc;
-    hipLaunchKernelGGL(sk_merge_kernel, dim3((n + 31) / 32), dim3(256), 0, s, a, g.W, check);
+    const dim3 mgrid((n + 31) / 32), mblock(256);
+    if (g.W <= 256) hipLaunchKernelGGL(sk_merge_kernel<8>, mgrid, mblock, 0, s, a, g.W, check);
+    else if (g.W <= 512) hipLaunchKernelGGL(sk_merge_kernel<16>, mgrid, mblock, 0, s, a, g.W, check);
+    else hipLaunchKernelGGL(sk_merge_kernel<32>, mgrid, mblock, 0, s, a, g.W, check);
     GOAT_HIP(hipGetLastError());
     return GOAT_OK;
 }

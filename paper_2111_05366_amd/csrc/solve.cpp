@@ -59,7 +59,13 @@ static int run_sinkhorn_polled(Run& r) {
     rc = sk_iterate(n, np, p.GP, np, p.sk, 1, 0, 0, r.s);
     if (rc) return rc;
     const int check_every = r.opt.check_every > 0 ? r.opt.check_every : 16;
-    int* hflag = reinterpret_cast<int*>(static_cast<char*>(r.hbuf) + 128);
+    // The kernels that set the stop flag also store it in pinned host memory
+    // (p.sk.hdone; sk_prepare's init kernel resets it in stream order). After
+    // each chunk of sweeps an event is recorded, and the host waits for the
+    // previous chunk's event and reads the flag, so one chunk is always
+    // queued ahead and no copy enters the stream. A flag read late only
+    // costs launches that exit at once.
+    const volatile int* hflag = p.sk.hdone;
     int k = 1, chunk = 0;
     bool stop = false;
     while (k < r.opt.sk_max && !stop) {
@@ -70,11 +76,10 @@ static int run_sinkhorn_polled(Run& r) {
         }
         k += m;
         const int slot = chunk & 1;
-        GOAT_HIP(hipMemcpyAsync(&hflag[slot], &p.sk.ctrl->done, sizeof(int), hipMemcpyDeviceToHost, r.s));
         GOAT_HIP(hipEventRecord(r.ev_poll[slot], r.s));
         if (chunk >= 1) {
             GOAT_HIP(hipEventSynchronize(r.ev_poll[slot ^ 1]));
-            if (hflag[slot ^ 1]) stop = true;
+            if (hflag && *hflag) stop = true;
         }
         ++chunk;
     }
@@ -220,6 +225,8 @@ static int run_begin_impl(int n, const float* A, const float* B, int ld, const f
         }                                                                                \
     } while (0)
     RUN_HIP(hipHostMalloc(&r.hbuf, 256, hipHostMallocDefault));
+    // the Sinkhorn stop flag, stored by the device (see run_sinkhorn_polled)
+    r.p.sk.hdone = reinterpret_cast<int*>(static_cast<char*>(r.hbuf) + 128);
     for (hipEvent_t* e : {&r.ev_poll[0], &r.ev_poll[1], &r.ev0, &r.ev1}) RUN_HIP(hipEventCreate(e));
     Ptrs& p = r.p;
     const int np = L.np;
