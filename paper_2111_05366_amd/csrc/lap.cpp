@@ -25,7 +25,6 @@ int lap_max(int n, const double* M, int ld, int32_t* perm) {
         return GOAT_EINVAL;
     }
     const double INF = std::numeric_limits<double>::infinity();
-    auto cost = [&](int i, int j) { return -M[(size_t)i * ld + j]; };
     for (size_t k = 0; k < (size_t)n * ld; ++k) {
         if ((k % ld) < (size_t)n && !std::isfinite(M[k])) {
             set_error("goat_lap_max: non-finite entry");

@@ -116,7 +116,6 @@ static int run_sinkhorn(Run& r) {
 
 static int run_step(Run& r, goat_iter_record* rec) {
     const int n = r.L.n, np = r.L.np;
-    const bool bf = r.opt.prec == GOAT_PREC_BF16X2 || r.opt.prec == GOAT_PREC_BF16X3;
     Ptrs& p = r.p;
     int rc = run_sinkhorn(r);
     if (rc) return rc;
