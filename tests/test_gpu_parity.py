@@ -147,6 +147,27 @@ def test_sinkhorn_parity_fixed_iterations(G, n, iters):
     assert abs(float(out.err.item()) - ref.err) <= 1e-4 + 1e-3 * ref.err
 
 
+def test_sinkhorn_one_row_strips_parity(G, monkeypatch):
+    # GOAT_SK_GEOM="256,1000" at n = 1000: 1000 one-row strips, so the
+    # column update merges 32 strips per lane (its W <= 1024 form); the
+    # default geometries use W <= 256 (8 per lane) and W <= 512 (16)
+    n, iters = 1000, 60
+    Gm = _sk_problem(n, 40 + n)
+    monkeypatch.setenv("GOAT_SK_GEOM", "256,1000")
+    out = G.sinkhorn(dev(Gm), eps_rel=0.03, max_iter=iters, tol=0.0)
+    monkeypatch.delenv("GOAT_SK_GEOM")
+    eps = oracle_eps(Gm, 0.03, out.eps)
+    ref = O.log_sinkhorn_max(Gm.astype(np.float64), eps, tol=0.0, max_iter=iters)
+    assert int(out.iters.item()) == iters == ref.iters
+    Qd = host(out.Q)
+    df = np.max(np.abs(host(out.f) - ref.f)) / eps
+    dg = np.max(np.abs(host(out.g) - ref.g)) / eps
+    print(f"one-row strips: Q rel_fro={rel_fro(Qd, ref.Q):.3e} elem={q_elem_rel(Qd, ref.Q):.3e} "
+          f"|df|/eps={df:.2e} |dg|/eps={dg:.2e}")
+    assert rel_fro(Qd, ref.Q) <= 1e-4 and q_elem_rel(Qd, ref.Q) <= 1e-4
+    assert df <= 1e-4 and dg <= 1e-4
+
+
 def test_sinkhorn_stops_like_oracle(G):
     n = 300
     Gm = _sk_problem(n, 77)
