@@ -506,58 +506,94 @@ __global__ __launch_bounds__(T) void sk_finalize_kernel(FinArgs fa) {
     const float kappa = Q24 ? a.ctrl->g24 : a.ctrl->kappa;
     const bool flat = a.ctrl->done == 2;
     const float jval = 1.0f / (float)a.n;
+    using XT = typename std::conditional<Q24, W3, float4>::type;
+    // column potentials of this thread's groups, read once for all rows
+    float vgl[C][4], vsl[C][4];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int j = 4 * (tid + T * c) + e;
+            vgl[c][e] = j < a.n ? a.vg[j] : 0.0f;
+            vsl[c][e] = j < a.n ? a.vs[j] : 0.0f;
+        }
+    // one row of G in flight ahead of the row being written (rows past the
+    // strip are not loaded; groups past n read zeros)
+    XT xa[C], xb[C];
+    float2 ua = make_float2(0.0f, 0.0f), ub = ua;
+#define GOAT_FIN_LOAD(X, U, I)                                                                     \
+    do {                                                                                           \
+        _Pragma("unroll") for (int c = 0; c < C; ++c) {                                            \
+            const int j0_ = 4 * (tid + T * c);                                                     \
+            if (j0_ < a.n) {                                                                       \
+                if constexpr (Q24) X[c] = reinterpret_cast<const W3*>(a.G24 + (size_t)(I) * a.ld24)[j0_ >> 2]; \
+                else X[c] = *reinterpret_cast<const float4*>(a.G + (size_t)(I) * a.ldg + j0_);     \
+            }                                                                                      \
+        }                                                                                          \
+        U = make_float2(a.ug[I], a.us[I]);                                                         \
+    } while (0)
     float errmax = 0.0f;
     int par = 0;
-    for (int i = r0; i < r1; ++i) {
-        const float ug = a.ug[i], us = a.us[i];
-        const float* grow = a.G + (size_t)i * a.ldg;
-        float s = 0.0f;
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int j0 = 4 * (tid + T * c);
-            if (j0 >= a.np && j0 >= a.n) continue;
-            float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (j0 < a.n)
-                g4 = Q24 ? dec24(reinterpret_cast<const W3*>(a.G24 + (size_t)i * a.ld24)[j0 >> 2])
-                         : *reinterpret_cast<const float4*>(grow + j0);
-            const float gv[4] = {g4.x, g4.y, g4.z, g4.w};
-            float q[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int j = j0 + e;
-                q[e] = 0.0f;
-                if (j < a.n)
-                    q[e] = flat ? jval : exp2f(fmaf(gv[e], kappa, a.vg[j] + ug) + (a.vs[j] + us));
-                s += q[e];
-            }
-            if (fa.Q) {
-                float* qrow = fa.Q + (size_t)i * fa.ldq;
-                if (j0 + 3 < a.n && (fa.ldq & 3) == 0) {
-                    *reinterpret_cast<float4*>(qrow + j0) = make_float4(q[0], q[1], q[2], q[3]);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        if (j0 + e < a.n) qrow[j0 + e] = q[e];
-                }
-            }
-            if (fa.Qhi && j0 < a.np) {
-                ushort4 hi, lo;
-                uint16_t hv[4], lv[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    hv[e] = f32_to_bf16_rne(q[e]);
-                    lv[e] = f32_to_bf16_rne(q[e] - bf16_to_f32(hv[e]));
-                }
-                hi.x = hv[0]; hi.y = hv[1]; hi.z = hv[2]; hi.w = hv[3];
-                lo.x = lv[0]; lo.y = lv[1]; lo.z = lv[2]; lo.w = lv[3];
-                *reinterpret_cast<ushort4*>(fa.Qhi + (size_t)i * a.np + j0) = hi;
-                *reinterpret_cast<ushort4*>(fa.Qlo + (size_t)i * a.np + j0) = lo;
-            }
-        }
-        const float S = block_sum<T>(s, red[par]);
-        par ^= 1;
-        errmax = fmaxf(errmax, fabsf(S - 1.0f));
+    if (r0 < r1) GOAT_FIN_LOAD(xa, ua, r0);
+#define GOAT_FIN_ROW(XC, XN, UC, UN, I)                                                            \
+    do {                                                                                           \
+        const float ug = UC.x, us = UC.y;                                                          \
+        float q[C][4];                                                                             \
+        _Pragma("unroll") for (int c = 0; c < C; ++c) {                                            \
+            const int j0 = 4 * (tid + T * c);                                                      \
+            float4 g4 = make_float4(0.f, 0.f, 0.f, 0.f);                                           \
+            if (j0 < a.n) g4 = as_f4(XC[c]);                                                       \
+            const float gv[4] = {g4.x, g4.y, g4.z, g4.w};                                          \
+            _Pragma("unroll") for (int e = 0; e < 4; ++e) {                                        \
+                const int j = j0 + e;                                                              \
+                q[c][e] = 0.0f;                                                                    \
+                if (j < a.n)                                                                       \
+                    q[c][e] = flat ? jval : exp2f(fmaf(gv[e], kappa, vgl[c][e] + ug) + (vsl[c][e] + us)); \
+            }                                                                                      \
+        }                                                                                          \
+        /* the row is consumed before the next row's loads are issued (the  */                     \
+        /* wait counter is in order)                                        */                     \
+        _Pragma("unroll") for (int c = 0; c < C; ++c)                                              \
+            _Pragma("unroll") for (int e = 0; e < 4; ++e) asm volatile("" ::"v"(q[c][e]));         \
+        if ((I) + 1 < r1) GOAT_FIN_LOAD(XN, UN, (I) + 1);                                          \
+        float s = 0.0f;                                                                            \
+        _Pragma("unroll") for (int c = 0; c < C; ++c) {                                            \
+            const int j0 = 4 * (tid + T * c);                                                      \
+            if (j0 >= a.np && j0 >= a.n) continue;                                                 \
+            _Pragma("unroll") for (int e = 0; e < 4; ++e) s += q[c][e];                            \
+            if (fa.Q) {                                                                            \
+                float* qrow = fa.Q + (size_t)(I) * fa.ldq;                                         \
+                if (j0 + 3 < a.n && (fa.ldq & 3) == 0) {                                           \
+                    *reinterpret_cast<float4*>(qrow + j0) = make_float4(q[c][0], q[c][1], q[c][2], q[c][3]); \
+                } else {                                                                           \
+                    _Pragma("unroll") for (int e = 0; e < 4; ++e)                                  \
+                        if (j0 + e < a.n) qrow[j0 + e] = q[c][e];                                  \
+                }                                                                                  \
+            }                                                                                      \
+            if (fa.Qhi && j0 < a.np) {                                                             \
+                ushort4 hi, lo;                                                                    \
+                uint16_t hv[4], lv[4];                                                             \
+                _Pragma("unroll") for (int e = 0; e < 4; ++e) {                                    \
+                    hv[e] = f32_to_bf16_rne(q[c][e]);                                              \
+                    lv[e] = f32_to_bf16_rne(q[c][e] - bf16_to_f32(hv[e]));                         \
+                }                                                                                  \
+                hi.x = hv[0]; hi.y = hv[1]; hi.z = hv[2]; hi.w = hv[3];                            \
+                lo.x = lv[0]; lo.y = lv[1]; lo.z = lv[2]; lo.w = lv[3];                            \
+                *reinterpret_cast<ushort4*>(fa.Qhi + (size_t)(I) * a.np + j0) = hi;                \
+                *reinterpret_cast<ushort4*>(fa.Qlo + (size_t)(I) * a.np + j0) = lo;                \
+            }                                                                                      \
+        }                                                                                          \
+        const float S = block_sum<T>(s, red[par]);                                                 \
+        par ^= 1;                                                                                  \
+        errmax = fmaxf(errmax, fabsf(S - 1.0f));                                                   \
+    } while (0)
+    for (int i = r0; i < r1; i += 2) {
+        GOAT_FIN_ROW(xa, xb, ua, ub, i);
+        if (i + 1 >= r1) break;
+        GOAT_FIN_ROW(xb, xa, ub, ua, i + 1);
     }
+#undef GOAT_FIN_ROW
+#undef GOAT_FIN_LOAD
     const float m = block_max<T>(errmax, red[par]);
     if (tid == 0) a.errpart[blockIdx.x] = m;
 }
