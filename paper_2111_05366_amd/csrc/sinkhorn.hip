@@ -626,9 +626,9 @@ struct Geometry {
 // Strips: below n = 4096, 256 threads and up to 512 strips; from n = 4096,
 // 1024 threads (16 waves) and one strip per compute unit, so every strip
 // streams many rows and the per-strip prologue (potentials into LDS) and
-// epilogue (column partials) are amortised (n = 10,000: 68.6 us per sweep
-// against 81.1 us with 512 x 512 threads). GOAT_SK_GEOM="T,W" overrides
-// both (a measurement knob).
+// epilogue (column partials) are amortised (n = 10,000, when this geometry
+// was chosen: 68.6 us per sweep against 81.1 us with 512 x 512 threads).
+// GOAT_SK_GEOM="T,W" overrides both (a measurement knob).
 constexpr int kSkSmallWG = 512;
 
 
