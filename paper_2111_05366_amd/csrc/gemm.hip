@@ -517,6 +517,129 @@ void gemm_nt_bf16_w8_kernel(GemmParams p) {
     store_tile_w8<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
+// Three-segment bf16 products X0 Z0 + X0 Z1 + X2 Z0 (the hi/lo split of
+// both operands with the lo x lo term dropped) on the 256 x 256 eight-wave
+// tile: the four operand tiles X0, X2, Z0, Z1 of a 32-wide k slice are
+// staged once and feed all three segments, so per 16-wide k-step a wave
+// reads 12 fragments for 24 MFMAs (18 when the segments run one after the
+// other) and a barrier covers 48 MFMAs per wave. Tiles are stored without
+// padding, their 16-byte chunks XOR-swizzled with bits 2..3 of the row so
+// that the eight rows a group of lanes reads at one chunk column fall on
+// disjoint banks. Two stages of 64 KB.
+constexpr int BK4 = 32;
+constexpr size_t kTileF3 = (size_t)BM3 * BK4;                        // bf16 per operand tile
+constexpr size_t kLdsF3 = (size_t)2 * 4 * kTileF3 * sizeof(uint16_t);
+
+__device__ inline int f3_off(int r, int c) { return r * BK4 + ((c ^ ((r >> 2) & 3)) << 3); }
+
+template <int OUT>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void gemm_nt_bf16_w8f3_kernel(GemmParams p) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t smemf3[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;
+    int tm, tn;
+    tile_of(p, tm, tn);
+    const int m0 = p.m_off + tm * BM3, n0 = tn * BN3;
+    const int ktiles = p.K / BK4;
+    const uint16_t* X0 = static_cast<const uint16_t*>(p.X[0]);
+    const uint16_t* X2 = static_cast<const uint16_t*>(p.X[2]);
+    const uint16_t* Z0 = static_cast<const uint16_t*>(p.Z[0]);
+    const uint16_t* Z1 = static_cast<const uint16_t*>(p.Z[1]);
+
+    f32x16 acc[4][2];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
+
+    // staging: chunks tid and tid + 512 of each tile, i.e. rows tid / 4 and
+    // tid / 4 + 128, chunk tid % 4 (eight bf16)
+    const int lrow = tid >> 2, lc = tid & 3;
+    const size_t xr0 = (size_t)(m0 + lrow) * p.ldx, xr1 = xr0 + (size_t)128 * p.ldx;
+    const size_t zr0 = (size_t)(n0 + lrow) * p.ldz, zr1 = zr0 + (size_t)128 * p.ldz;
+    uint4 s0, s1, s2, s3, s4, s5, s6, s7;
+#define GOAT_GLOADF3(T)                                                                           \
+    do {                                                                                          \
+        const size_t k_ = (size_t)(T) * BK4 + lc * 8;                                             \
+        s0 = *reinterpret_cast<const uint4*>(X0 + xr0 + k_);                                      \
+        s1 = *reinterpret_cast<const uint4*>(X0 + xr1 + k_);                                      \
+        s2 = *reinterpret_cast<const uint4*>(X2 + xr0 + k_);                                      \
+        s3 = *reinterpret_cast<const uint4*>(X2 + xr1 + k_);                                      \
+        s4 = *reinterpret_cast<const uint4*>(Z0 + zr0 + k_);                                      \
+        s5 = *reinterpret_cast<const uint4*>(Z0 + zr1 + k_);                                      \
+        s6 = *reinterpret_cast<const uint4*>(Z1 + zr0 + k_);                                      \
+        s7 = *reinterpret_cast<const uint4*>(Z1 + zr1 + k_);                                      \
+    } while (0)
+    const int so0 = f3_off(lrow, lc), so1 = f3_off(lrow + 128, lc);
+#define GOAT_SSTOREF3(BUF)                                                                        \
+    do {                                                                                          \
+        uint16_t* b_ = smemf3 + (size_t)(BUF) * 4 * kTileF3;                                      \
+        *reinterpret_cast<uint4*>(b_ + so0) = s0;                                                 \
+        *reinterpret_cast<uint4*>(b_ + so1) = s1;                                                 \
+        *reinterpret_cast<uint4*>(b_ + kTileF3 + so0) = s2;                                       \
+        *reinterpret_cast<uint4*>(b_ + kTileF3 + so1) = s3;                                       \
+        *reinterpret_cast<uint4*>(b_ + 2 * kTileF3 + so0) = s4;                                   \
+        *reinterpret_cast<uint4*>(b_ + 2 * kTileF3 + so1) = s5;                                   \
+        *reinterpret_cast<uint4*>(b_ + 3 * kTileF3 + so0) = s6;                                   \
+        *reinterpret_cast<uint4*>(b_ + 3 * kTileF3 + so1) = s7;                                   \
+    } while (0)
+
+    GOAT_GLOADF3(0);
+    GOAT_SSTOREF3(0);
+    __syncthreads();
+    // fragment rows of this lane: X rows wm*128 + 32 i + lane % 32, Z rows
+    // wn*64 + 32 i + lane % 32; k chunk 2 ks + lane / 32 of the slice
+    const int ar = wm * 128 + (lane & 31), br = wn * 64 + (lane & 31), kh = lane >> 5;
+    for (int t = 0; t < ktiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ktiles) GOAT_GLOADF3(t + 1);
+        const uint16_t* sx0 = smemf3 + (size_t)buf * 4 * kTileF3;
+        const uint16_t* sx2 = sx0 + kTileF3;
+        const uint16_t* sz0 = sx0 + 2 * kTileF3;
+        const uint16_t* sz1 = sx0 + 3 * kTileF3;
+#pragma unroll
+        for (int ks = 0; ks < BK4 / 16; ++ks) {
+            const int c = 2 * ks + kh;
+            bf16x8 ah[4], al[4], bh[2], bl[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                ah[i] = *reinterpret_cast<const bf16x8*>(sx0 + f3_off(ar + 32 * i, c));
+                al[i] = *reinterpret_cast<const bf16x8*>(sx2 + f3_off(ar + 32 * i, c));
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                bh[i] = *reinterpret_cast<const bf16x8*>(sz0 + f3_off(br + 32 * i, c));
+                bl[i] = *reinterpret_cast<const bf16x8*>(sz1 + f3_off(br + 32 * i, c));
+            }
+            // segment-major, so consecutive MFMAs on one accumulator are
+            // eight apart
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+        }
+        if (t + 1 < ktiles) GOAT_SSTOREF3(buf ^ 1);
+        __syncthreads();
+    }
+#undef GOAT_GLOADF3
+#undef GOAT_SSTOREF3
+    store_tile_w8<OUT>(p, acc, m0, n0, wm, wn, lane);
+}
+
 // ------------------------------------------------------------------ fp32
 
 constexpr int BK32 = 16;                 // k-tile (float elements)
@@ -643,6 +766,22 @@ int tile_choice(int M, int N, int K) {
     return lds_ok ? want : 0;
 }
 
+// The fused three-segment kernel takes bf16 products whose segments are
+// (X0, Z0), (X0, Z1), (X2, Z0) on the eight-wave tile. GOAT_GEMM_F3=0 keeps
+// the segment-by-segment kernel (a measurement knob).
+bool fused3_ok(const GemmSegs& segs, int K) {
+    static const bool on = [] {
+        const char* e = getenv("GOAT_GEMM_F3");
+        return !(e && std::strcmp(e, "0") == 0);
+    }();
+    static const bool lds_ok =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_w8f3_kernel<OUT_F32>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsF3) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_w8f3_kernel<OUT_BF16_SPLIT>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsF3) == hipSuccess;
+    return on && lds_ok && segs.nseg == 3 && segs.X[0] == segs.X[1] && segs.Z[0] == segs.Z[2] && K % BK4 == 0;
+}
+
 }  // namespace
 
 int launch_gemm_nt(int kind, int M, int N, int K, int ldx, int ldz, const GemmSegs& segs,
@@ -713,6 +852,9 @@ int launch_gemm_nt(int kind, int M, int N, int K, int ldx, int ldz, const GemmSe
     } else if (tile == 1) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_256_kernel<OUT_F32>, grid, block, kLds256, s, p);
         else hipLaunchKernelGGL(gemm_nt_bf16_256_kernel<OUT_BF16_SPLIT>, grid, block, kLds256, s, p);
+    } else if (tile == 2 && fused3_ok(segs, K)) {
+        if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_w8f3_kernel<OUT_F32>, grid, block, kLdsF3, s, p);
+        else hipLaunchKernelGGL(gemm_nt_bf16_w8f3_kernel<OUT_BF16_SPLIT>, grid, block, kLdsF3, s, p);
     } else if (tile == 2) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_w8_kernel<OUT_F32>, grid, block, kLdsW8, s, p);
         else hipLaunchKernelGGL(gemm_nt_bf16_w8_kernel<OUT_BF16_SPLIT>, grid, block, kLdsW8, s, p);
