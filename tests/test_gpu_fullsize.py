@@ -57,6 +57,30 @@ def test_gradient_sampled_entries_full_size(G, pair, prec):
     assert err <= 1e-4 and err_c <= 1e-4
 
 
+def test_gradient_general_pair_bf16x3_n4500(G):
+    """A general (non-symmetric) pair at n = 4500 in the bf16 hi/lo form: the
+    first product stacks [B; B^T] (rows 2 np) and runs on the fused
+    three-segment eight-wave kernel, the second has six segments and runs
+    segment by segment. Sampled rows and columns of G against FP64."""
+    n = 4500
+    A = I.random_matrix(n, n, 61, 0.0, 1.0)
+    B = I.random_matrix(n, n, 62, 0.0, 1.0)
+    P = I.uniform_matrix(n, 63) / np.float32(n)
+    Gd = G.grad(torch.as_tensor(A, device="cuda"), torch.as_tensor(B, device="cuda"),
+                torch.as_tensor(P, device="cuda"), prec="bf16x3", symmetric=False)
+    got = Gd.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(9)
+    rows = rng.choice(n, size=4, replace=False)
+    cols = rng.choice(n, size=6, replace=False)
+    Ad, Bd, Pd = A.astype(np.float64), B.astype(np.float64), P.astype(np.float64)
+    ref_rows = (Ad[rows] @ Pd) @ Bd.T + (Ad.T[rows] @ Pd) @ Bd
+    ref_cols = Ad @ (Pd @ Bd.T[:, cols]) + Ad.T @ (Pd @ Bd[:, cols])
+    err = np.max(np.abs(got[rows] - ref_rows)) / np.max(np.abs(ref_rows))
+    err_c = np.max(np.abs(got[:, cols] - ref_cols)) / np.max(np.abs(ref_cols))
+    print(f"grad n={n} bf16x3 general: sampled rows rel {err:.2e}, sampled cols rel {err_c:.2e}")
+    assert err <= 1e-4 and err_c <= 1e-4
+
+
 def test_gradient_fp8_sampled_entries_er5000(G):
     """FP8 form on the 0/1 correlated ER pair at n = 5000 (p = 0.02,
     rho = 0.7): sampled rows and columns of G against FP64."""
