@@ -271,6 +271,123 @@ __global__ __launch_bounds__(256) void gemm_nt_fp8_kernel(GemmParams p) {
     store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
+// FP8 products whose segments come in groups of kFp8Terms = 3 that share X
+// and take the three terms of a split Z (segment 3 g + t: X_g, Z term t):
+// per 64-wide k slice the tiles X_g, Z_t0, Z_t1, Z_t2 are staged once, so a
+// wave reads 8 fragments for 12 MFMAs instead of 12. Tiles are stored
+// without padding, the four 16-byte chunks of a row XOR-swizzled with bits
+// 2..3 of the row, so the sixteen rows a group of lanes reads at one chunk
+// column fall on disjoint banks (a lane's 32-byte fragment is read as two
+// chunks). Two stages of 32 KB: two blocks per compute unit.
+constexpr int BKF8 = 64;                                              // k slice (bytes)
+constexpr size_t kTileF8 = (size_t)BM * BKF8;                         // bytes per operand tile
+constexpr size_t kLdsF8 = (size_t)2 * 4 * kTileF8;
+
+__device__ inline int f8_chunk(int r, int c) { return r * BKF8 + ((c ^ ((r >> 2) & 3)) << 4); }
+
+// the 32-byte fragment of row r, k half h (chunks 2h and 2h + 1)
+__device__ inline i32x8 f8_frag(const uint8_t* tile, int r, int h) {
+    const uint4 lo = *reinterpret_cast<const uint4*>(tile + f8_chunk(r, 2 * h));
+    const uint4 hi = *reinterpret_cast<const uint4*>(tile + f8_chunk(r, 2 * h + 1));
+    i32x8 v;
+    v[0] = (int)lo.x; v[1] = (int)lo.y; v[2] = (int)lo.z; v[3] = (int)lo.w;
+    v[4] = (int)hi.x; v[5] = (int)hi.y; v[6] = (int)hi.z; v[7] = (int)hi.w;
+    return v;
+}
+
+template <int OUT>
+__global__ __launch_bounds__(256) void gemm_nt_fp8_f3_kernel(GemmParams p) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smemf8[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_of(p, tm, tn);
+    const int m0 = p.m_off + tm * BM, n0 = tn * BN;
+    const int ktiles = p.K / BKF8;
+    const int total = ktiles * (p.nseg / kFp8Terms);
+    const int zexp = fp8_split_exponent(*p.zmax);
+    int zscale[kFp8Terms];
+#pragma unroll
+    for (int t = 0; t < kFp8Terms; ++t) zscale[t] = 127 - zexp - kFp8TermShift * t;
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
+
+    // staging: 16-byte pieces tid and tid + 256 of each tile, i.e. rows
+    // tid / 4 and tid / 4 + 64, piece tid % 4 (bytes 16 (tid % 4) ..)
+    const int lrow = tid >> 2, lp = tid & 3;
+    const size_t xr0 = (size_t)(m0 + lrow) * p.ldx, xr1 = xr0 + (size_t)64 * p.ldx;
+    const size_t zr0 = (size_t)(n0 + lrow) * p.ldz, zr1 = zr0 + (size_t)64 * p.ldz;
+    uint4 s0, s1, s2, s3, s4, s5, s6, s7;
+#define GOAT_GLOADF8(T)                                                                           \
+    do {                                                                                          \
+        const int g_ = (T) / ktiles, kt_ = (T) - g_ * ktiles;                                     \
+        const size_t k_ = (size_t)kt_ * BKF8 + lp * 16;                                           \
+        const uint8_t* X_ = static_cast<const uint8_t*>(p.X[kFp8Terms * g_]);                     \
+        const uint8_t* Z0_ = static_cast<const uint8_t*>(p.Z[kFp8Terms * g_]);                    \
+        const uint8_t* Z1_ = static_cast<const uint8_t*>(p.Z[kFp8Terms * g_ + 1]);                \
+        const uint8_t* Z2_ = static_cast<const uint8_t*>(p.Z[kFp8Terms * g_ + 2]);                \
+        s0 = *reinterpret_cast<const uint4*>(X_ + xr0 + k_);                                      \
+        s1 = *reinterpret_cast<const uint4*>(X_ + xr1 + k_);                                      \
+        s2 = *reinterpret_cast<const uint4*>(Z0_ + zr0 + k_);                                     \
+        s3 = *reinterpret_cast<const uint4*>(Z0_ + zr1 + k_);                                     \
+        s4 = *reinterpret_cast<const uint4*>(Z1_ + zr0 + k_);                                     \
+        s5 = *reinterpret_cast<const uint4*>(Z1_ + zr1 + k_);                                     \
+        s6 = *reinterpret_cast<const uint4*>(Z2_ + zr0 + k_);                                     \
+        s7 = *reinterpret_cast<const uint4*>(Z2_ + zr1 + k_);                                     \
+    } while (0)
+    const int so0 = f8_chunk(lrow, lp), so1 = f8_chunk(lrow + 64, lp);
+#define GOAT_SSTOREF8(BUF)                                                                        \
+    do {                                                                                          \
+        uint8_t* b_ = smemf8 + (size_t)(BUF) * 4 * kTileF8;                                       \
+        *reinterpret_cast<uint4*>(b_ + so0) = s0;                                                 \
+        *reinterpret_cast<uint4*>(b_ + so1) = s1;                                                 \
+        *reinterpret_cast<uint4*>(b_ + kTileF8 + so0) = s2;                                       \
+        *reinterpret_cast<uint4*>(b_ + kTileF8 + so1) = s3;                                       \
+        *reinterpret_cast<uint4*>(b_ + 2 * kTileF8 + so0) = s4;                                   \
+        *reinterpret_cast<uint4*>(b_ + 2 * kTileF8 + so1) = s5;                                   \
+        *reinterpret_cast<uint4*>(b_ + 3 * kTileF8 + so0) = s6;                                   \
+        *reinterpret_cast<uint4*>(b_ + 3 * kTileF8 + so1) = s7;                                   \
+    } while (0)
+
+    GOAT_GLOADF8(0);
+    GOAT_SSTOREF8(0);
+    __syncthreads();
+    // fragments: rows wm*64 + 32 i + lane % 32 (X) and wn*64 + 32 i + lane % 32
+    // (Z), 32 bytes from half lane / 32 of the slice
+    const int ar = wm * 64 + (lane & 31), br = wn * 64 + (lane & 31), hf = lane >> 5;
+    for (int t = 0; t < total; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < total) GOAT_GLOADF8(t + 1);
+        const uint8_t* sx = smemf8 + (size_t)buf * 4 * kTileF8;
+        i32x8 a[2], b[kFp8Terms][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = f8_frag(sx, ar + 32 * i, hf);
+#pragma unroll
+        for (int z = 0; z < kFp8Terms; ++z)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) b[z][i] = f8_frag(sx + (z + 1) * kTileF8, br + 32 * i, hf);
+#pragma unroll
+        for (int z = 0; z < kFp8Terms; ++z)
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a[mi], b[z][ni], acc[mi][ni], 0, 0,
+                                                                                  0, 127, 0, zscale[z]);
+        if (t + 1 < total) GOAT_SSTOREF8(buf ^ 1);
+        __syncthreads();
+    }
+#undef GOAT_GLOADF8
+#undef GOAT_SSTOREF8
+    store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
+}
+
 // ------------------------------------------------------------------ bf16, 256 x 256
 
 // Block tile 256 x 256 with four waves, each owning a 128 x 128 sub-tile
@@ -769,6 +886,23 @@ int tile_choice(int M, int N, int K) {
 // The fused three-segment kernel takes bf16 products whose segments are
 // (X0, Z0), (X0, Z1), (X2, Z0) on the eight-wave tile. GOAT_GEMM_F3=0 keeps
 // the segment-by-segment kernel (a measurement knob).
+// The fused fp8 kernel takes products whose segments come in groups of
+// kFp8Terms sharing X, segment kFp8Terms g + t holding term t of Z
+// (GOAT_GEMM_F3=0 keeps the segment-by-segment kernel).
+bool fused_fp8_ok(const GemmSegs& segs, int K) {
+    static const bool on = [] {
+        const char* e = getenv("GOAT_GEMM_F3");
+        return !(e && std::strcmp(e, "0") == 0);
+    }();
+    static const bool lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_fp8_f3_kernel<OUT_F32>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   (int)kLdsF8) == hipSuccess;
+    if (!on || !lds_ok || K % BKF8 || segs.nseg % kFp8Terms) return false;
+    for (int sg = 0; sg < segs.nseg; ++sg)
+        if (segs.X[sg] != segs.X[sg - sg % kFp8Terms] || segs.zterm[sg] != sg % kFp8Terms) return false;
+    return true;
+}
+
 bool fused3_ok(const GemmSegs& segs, int K) {
     static const bool on = [] {
         const char* e = getenv("GOAT_GEMM_F3");
@@ -847,7 +981,9 @@ int launch_gemm_nt(int kind, int M, int N, int K, int ldx, int ldz, const GemmSe
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_F32>, g2, b2, 0, s, q);
         else hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_BF16_SPLIT>, g2, b2, 0, s, q);
     }
-    if (is_fp8) {
+    if (is_fp8 && fused_fp8_ok(segs, K)) {
+        hipLaunchKernelGGL(gemm_nt_fp8_f3_kernel<OUT_F32>, grid, block, kLdsF8, s, p);
+    } else if (is_fp8) {
         hipLaunchKernelGGL(gemm_nt_fp8_kernel<OUT_F32>, grid, block, 0, s, p);
     } else if (tile == 1) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_256_kernel<OUT_F32>, grid, block, kLds256, s, p);
