@@ -757,6 +757,112 @@ void gemm_nt_bf16_w8f3_kernel(GemmParams p) {
     store_tile_w8<OUT>(p, acc, m0, n0, wm, wn, lane);
 }
 
+// The same fusion on the 128 x 128 tile (four waves of 64 x 64): the last
+// tile-rows of a large product and every three-segment product below the
+// eight-wave shapes. Per 16-wide k-step a wave reads 8 fragments for 12
+// MFMAs instead of 12; two stages of 32 KB.
+constexpr size_t kTileF3s = (size_t)BM * BK4;                         // bf16 per operand tile
+constexpr size_t kLdsF3s = (size_t)2 * 4 * kTileF3s * sizeof(uint16_t);
+
+template <int OUT>
+__global__ __launch_bounds__(256) void gemm_nt_bf16_f3_kernel(GemmParams p) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t smemf3s[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_of(p, tm, tn);
+    const int m0 = p.m_off + tm * BM, n0 = tn * BN;
+    const int ktiles = p.K / BK4;
+    const uint16_t* X0 = static_cast<const uint16_t*>(p.X[0]);
+    const uint16_t* X2 = static_cast<const uint16_t*>(p.X[2]);
+    const uint16_t* Z0 = static_cast<const uint16_t*>(p.Z[0]);
+    const uint16_t* Z1 = static_cast<const uint16_t*>(p.Z[1]);
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mi][ni][r] = 0.0f;
+
+    // staging: rows tid / 4 and tid / 4 + 64 of each tile, chunk tid % 4
+    const int lrow = tid >> 2, lc = tid & 3;
+    const size_t xr0 = (size_t)(m0 + lrow) * p.ldx, xr1 = xr0 + (size_t)64 * p.ldx;
+    const size_t zr0 = (size_t)(n0 + lrow) * p.ldz, zr1 = zr0 + (size_t)64 * p.ldz;
+    uint4 s0, s1, s2, s3, s4, s5, s6, s7;
+#define GOAT_GLOADF3S(T)                                                                          \
+    do {                                                                                          \
+        const size_t k_ = (size_t)(T) * BK4 + lc * 8;                                             \
+        s0 = *reinterpret_cast<const uint4*>(X0 + xr0 + k_);                                      \
+        s1 = *reinterpret_cast<const uint4*>(X0 + xr1 + k_);                                      \
+        s2 = *reinterpret_cast<const uint4*>(X2 + xr0 + k_);                                      \
+        s3 = *reinterpret_cast<const uint4*>(X2 + xr1 + k_);                                      \
+        s4 = *reinterpret_cast<const uint4*>(Z0 + zr0 + k_);                                      \
+        s5 = *reinterpret_cast<const uint4*>(Z0 + zr1 + k_);                                      \
+        s6 = *reinterpret_cast<const uint4*>(Z1 + zr0 + k_);                                      \
+        s7 = *reinterpret_cast<const uint4*>(Z1 + zr1 + k_);                                      \
+    } while (0)
+    const int so0 = f3_off(lrow, lc), so1 = f3_off(lrow + 64, lc);
+#define GOAT_SSTOREF3S(BUF)                                                                       \
+    do {                                                                                          \
+        uint16_t* b_ = smemf3s + (size_t)(BUF) * 4 * kTileF3s;                                    \
+        *reinterpret_cast<uint4*>(b_ + so0) = s0;                                                 \
+        *reinterpret_cast<uint4*>(b_ + so1) = s1;                                                 \
+        *reinterpret_cast<uint4*>(b_ + kTileF3s + so0) = s2;                                      \
+        *reinterpret_cast<uint4*>(b_ + kTileF3s + so1) = s3;                                      \
+        *reinterpret_cast<uint4*>(b_ + 2 * kTileF3s + so0) = s4;                                  \
+        *reinterpret_cast<uint4*>(b_ + 2 * kTileF3s + so1) = s5;                                  \
+        *reinterpret_cast<uint4*>(b_ + 3 * kTileF3s + so0) = s6;                                  \
+        *reinterpret_cast<uint4*>(b_ + 3 * kTileF3s + so1) = s7;                                  \
+    } while (0)
+
+    GOAT_GLOADF3S(0);
+    GOAT_SSTOREF3S(0);
+    __syncthreads();
+    const int ar = wm * 64 + (lane & 31), br = wn * 64 + (lane & 31), kh = lane >> 5;
+    for (int t = 0; t < ktiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ktiles) GOAT_GLOADF3S(t + 1);
+        const uint16_t* sx0 = smemf3s + (size_t)buf * 4 * kTileF3s;
+        const uint16_t* sx2 = sx0 + kTileF3s;
+        const uint16_t* sz0 = sx0 + 2 * kTileF3s;
+        const uint16_t* sz1 = sx0 + 3 * kTileF3s;
+#pragma unroll
+        for (int ks = 0; ks < BK4 / 16; ++ks) {
+            const int c = 2 * ks + kh;
+            bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ah[i] = *reinterpret_cast<const bf16x8*>(sx0 + f3_off(ar + 32 * i, c));
+                al[i] = *reinterpret_cast<const bf16x8*>(sx2 + f3_off(ar + 32 * i, c));
+                bh[i] = *reinterpret_cast<const bf16x8*>(sz0 + f3_off(br + 32 * i, c));
+                bl[i] = *reinterpret_cast<const bf16x8*>(sz1 + f3_off(br + 32 * i, c));
+            }
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[mi], bl[ni], acc[mi][ni], 0, 0, 0);
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[mi], bh[ni], acc[mi][ni], 0, 0, 0);
+        }
+        if (t + 1 < ktiles) GOAT_SSTOREF3S(buf ^ 1);
+        __syncthreads();
+    }
+#undef GOAT_GLOADF3S
+#undef GOAT_SSTOREF3S
+    store_tile<OUT>(p, acc, m0, n0, wm, wn, lane);
+}
+
 // ------------------------------------------------------------------ fp32
 
 constexpr int BK32 = 16;                 // k-tile (float elements)
@@ -883,9 +989,6 @@ int tile_choice(int M, int N, int K) {
     return lds_ok ? want : 0;
 }
 
-// The fused three-segment kernel takes bf16 products whose segments are
-// (X0, Z0), (X0, Z1), (X2, Z0) on the eight-wave tile. GOAT_GEMM_F3=0 keeps
-// the segment-by-segment kernel (a measurement knob).
 // The fused fp8 kernel takes products whose segments come in groups of
 // kFp8Terms sharing X, segment kFp8Terms g + t holding term t of Z
 // (GOAT_GEMM_F3=0 keeps the segment-by-segment kernel).
@@ -903,17 +1006,24 @@ bool fused_fp8_ok(const GemmSegs& segs, int K) {
     return true;
 }
 
-bool fused3_ok(const GemmSegs& segs, int K) {
+// The fused three-segment kernels take bf16 products whose segments are
+// (X0, Z0), (X0, Z1), (X2, Z0), on either tile. GOAT_GEMM_F3=0 keeps the
+// segment-by-segment kernels (a measurement knob).
+bool fused3_pattern(const GemmSegs& segs, int K) {
     static const bool on = [] {
         const char* e = getenv("GOAT_GEMM_F3");
         return !(e && std::strcmp(e, "0") == 0);
     }();
+    return on && segs.nseg == 3 && segs.X[0] == segs.X[1] && segs.Z[0] == segs.Z[2] && K % BK4 == 0;
+}
+
+bool fused3_ok(const GemmSegs& segs, int K) {
     static const bool lds_ok =
         hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_w8f3_kernel<OUT_F32>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsF3) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(gemm_nt_bf16_w8f3_kernel<OUT_BF16_SPLIT>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsF3) == hipSuccess;
-    return on && lds_ok && segs.nseg == 3 && segs.X[0] == segs.X[1] && segs.Z[0] == segs.Z[2] && K % BK4 == 0;
+    return lds_ok && fused3_pattern(segs, K);
 }
 
 }  // namespace
@@ -978,8 +1088,14 @@ int launch_gemm_nt(int kind, int M, int N, int K, int ldx, int ldz, const GemmSe
         q.tiles_m = (M - rows_big) / BM;
         q.tiles_n = N / BN;
         const dim3 g2(q.tiles_m * q.tiles_n), b2(256);
-        if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_F32>, g2, b2, 0, s, q);
-        else hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_BF16_SPLIT>, g2, b2, 0, s, q);
+        if (fused3_pattern(segs, K)) {
+            if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_f3_kernel<OUT_F32>, g2, b2, kLdsF3s, s, q);
+            else hipLaunchKernelGGL(gemm_nt_bf16_f3_kernel<OUT_BF16_SPLIT>, g2, b2, kLdsF3s, s, q);
+        } else if (out_mode == OUT_F32) {
+            hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_F32>, g2, b2, 0, s, q);
+        } else {
+            hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_BF16_SPLIT>, g2, b2, 0, s, q);
+        }
     }
     if (is_fp8 && fused_fp8_ok(segs, K)) {
         hipLaunchKernelGGL(gemm_nt_fp8_f3_kernel<OUT_F32>, grid, block, kLdsF8, s, p);
@@ -994,6 +1110,9 @@ int launch_gemm_nt(int kind, int M, int N, int K, int ldx, int ldz, const GemmSe
     } else if (tile == 2) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_w8_kernel<OUT_F32>, grid, block, kLdsW8, s, p);
         else hipLaunchKernelGGL(gemm_nt_bf16_w8_kernel<OUT_BF16_SPLIT>, grid, block, kLdsW8, s, p);
+    } else if (is_bf16 && tile == 0 && fused3_pattern(segs, K)) {
+        if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_f3_kernel<OUT_F32>, grid, block, kLdsF3s, s, p);
+        else hipLaunchKernelGGL(gemm_nt_bf16_f3_kernel<OUT_BF16_SPLIT>, grid, block, kLdsF3s, s, p);
     } else if (is_bf16) {
         if (out_mode == OUT_F32) hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_F32>, grid, block, 0, s, p);
         else hipLaunchKernelGGL(gemm_nt_bf16_kernel<OUT_BF16_SPLIT>, grid, block, 0, s, p);
