@@ -32,7 +32,19 @@ entry; plan-level scalars 1e-3 for eps and c, 2e-3 for f).
 
 The whole plain run to its stall is compared with the oracle's stored run
 (weighted_sbm_n10000_plain_run.json, same script) iteration by iteration,
-and the final match ratios against the benchmark's gate."""
+and the final match ratios against the benchmark's gate (0.005). From the
+third iteration on, P is a capped 1000-sweep plan at eps near 0.03 max|G|
+whose optimal assignment is decided below float resolution: the planted
+permutation's objective <P, X> lies within 1.3e-7 relative of the optimum,
+and a 1e-7 relative perturbation of P changes about half of the assigned
+rows (measured after 3, 5 and 7 iterations: 49 %, 76 %, 76 %; at 1e-6,
+79 % to 89 %). An fp32 gradient carries about 1e-6 relative rounding, so
+its run cannot reproduce the FP64 run's assignment, only its scalars.
+Where the match ratios differ by more than the gate, the test asserts that
+reading instead: the device assignment is optimal for its own P within the
+assignment's stated bound, the planted permutation is within 1e-6 relative
+of that optimum, and a 1e-7 perturbation moves more than 10 % of the rows."""
+import math
 import os
 
 import numpy as np
@@ -153,7 +165,8 @@ def test_plain_run_tracks_oracle(G, pair):
     # evaluates plan-level quantities of capped 1000-sweep solves, so the
     # replay test's plan-level bounds apply (1e-4 for eps and c, 2e-4 for
     # fP and fQ), and each step t within 1e-4. The final assignments'
-    # match ratios agree within 0.005, the gate of the benchmark's metric.
+    # match ratios agree within 0.005, or the assignment is shown to be
+    # undetermined at float resolution (module docstring).
     import json
     path = os.path.join(HERE, "golden", "weighted_sbm_n10000_plain_run.json")
     ref = json.load(open(path))
@@ -164,7 +177,7 @@ def test_plain_run_tracks_oracle(G, pair):
     run = G.Run(A, B, prec="fp32", warm=0, stop_on_stall=1, sk_max=1000, sk_tol=1e-6, fw_max=30, lap=1)
     while run.steps(1) == 1:
         pass
-    res = run.finish()
+    res = run.finish(return_P=True)
     run.close()
     its = ref["iterations"]
     print(f"plain run: {len(res.history)} FW iterations (oracle {len(its)})", flush=True)
@@ -184,4 +197,30 @@ def test_plain_run_tracks_oracle(G, pair):
     assert len(res.history) == len(its)
     mr = float(np.mean(res.perm == g.truth))
     print(f"match ratio {mr:.4f} (oracle {ref['match_ratio']:.4f})", flush=True)
-    assert abs(mr - ref["match_ratio"]) <= 0.005
+    assert sorted(res.perm.tolist()) == list(range(N))
+    if abs(mr - ref["match_ratio"]) <= 0.005:
+        return
+    P = res.P
+    rows = torch.arange(N, device=P.device)
+    perm = torch.as_tensor(res.perm, device=P.device)
+    P64 = P.double()
+
+    def objective(p):
+        return float(P64[rows, p.long()].sum())
+
+    # the device assignment's bound on P itself: n 2^-s, s = R - 1 - e with
+    # 2^(e-1) <= max P < 2^e and R = min(40, 55 - ceil(log2(n + 1)))
+    e = math.frexp(float(P.max()))[1]
+    s = min(40, 55 - math.ceil(math.log2(N + 1))) - 1 - e
+    opt = objective(perm)
+    planted = objective(torch.as_tensor(g.truth, device=P.device))
+    gen = torch.Generator(device=P.device)
+    gen.manual_seed(7)
+    Pp = (P * (1 + 1e-7 * (2 * torch.rand((N, N), device=P.device, generator=gen) - 1))).contiguous()
+    perm2, _ = G.lap_device(Pp)
+    moved = float((perm2.long() != perm.long()).float().mean())
+    print(f"assignment objective {opt:.9e}, planted {planted:.9e} ({planted / opt - 1:+.2e}); "
+          f"rows moved by a 1e-7 perturbation: {moved:.3f}", flush=True)
+    assert opt >= planted - N * 2.0 ** -s
+    assert planted >= opt * (1 - 1e-6)
+    assert moved > 0.10
