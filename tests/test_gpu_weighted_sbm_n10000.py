@@ -164,9 +164,17 @@ def test_plain_run_tracks_oracle(G, pair):
     # (weighted_sbm_n10000_plain_run.json); every iteration from the third on
     # evaluates plan-level quantities of capped 1000-sweep solves, so the
     # replay test's plan-level bounds apply (1e-4 for eps and c, 2e-4 for
-    # fP and fQ), and each step t within 1e-4. The final assignments'
-    # match ratios agree within 0.005, or the assignment is shown to be
-    # undetermined at float resolution (module docstring).
+    # fP and fQ), and each step t within 1e-4 where the step is resolved.
+    # Near the stall the line search's linear coefficient b (the gain of
+    # the full step) falls to 1e-7 |f|, below what the fp32 plans resolve
+    # (device against oracle b: 34.335 / 34.302 at iteration 7, 0.0129 /
+    # 0.0090 at iteration 8), so whether such a step is taken or is the
+    # stall is decided by rounding: a step is resolved when the oracle's
+    # |b| exceeds 1e-6 |fP|, and past the end of the shorter run every
+    # step of the longer one, and the stall that ended the shorter run,
+    # must be unresolved. The final assignments' match ratios agree within
+    # 0.005, or the assignment is shown to be undetermined at float
+    # resolution (module docstring).
     import json
     path = os.path.join(HERE, "golden", "weighted_sbm_n10000_plain_run.json")
     ref = json.load(open(path))
@@ -193,8 +201,13 @@ def test_plain_run_tracks_oracle(G, pair):
         bd = 1e-5 if k < 2 else 1e-4
         assert errs["eps"] <= bd and errs["c"] <= bd
         assert errs["fP"] <= 2 * bd and errs["fQ"] <= 2 * bd
-        assert abs(h["t"] - o["t"]) <= 1e-4
-    assert len(res.history) == len(its)
+        if abs(o["b"]) > 1e-6 * abs(o["fP"]):
+            assert abs(h["t"] - o["t"]) <= 1e-4
+    kd, ko = len(res.history), len(its)
+    if kd != ko:
+        longer = res.history if kd > ko else its
+        for h in longer[min(kd, ko) - 1:]:
+            assert abs(h["b"]) <= 1e-6 * abs(h["fP"])
     mr = float(np.mean(res.perm == g.truth))
     print(f"match ratio {mr:.4f} (oracle {ref['match_ratio']:.4f})", flush=True)
     assert sorted(res.perm.tolist()) == list(range(N))
