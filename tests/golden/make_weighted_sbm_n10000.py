@@ -20,8 +20,8 @@ or 1000 sweeps, and the exact step. Written:
 
 The mixed form never takes a zero step on this pair, so its run is cut at 3
 iterations (30 would take about a day of CPU). Calls only oracle/ and the
-seeded input module; the parameter file is data. About 45 minutes of CPU per
-FW iteration:
+seeded input module; the parameter file is data. About 87 minutes of one
+core per FW iteration once the solves reach the 1000-sweep cap:
 
     python tests/golden/make_weighted_sbm_n10000.py plain   # or mixed
 """
