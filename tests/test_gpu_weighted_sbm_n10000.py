@@ -177,7 +177,11 @@ def test_plain_run_tracks_oracle(G, pair):
     # resolution (module docstring).
     import json
     path = os.path.join(HERE, "golden", "weighted_sbm_n10000_plain_run.json")
-    ref = json.load(open(path))
+    try:
+        with open(path, encoding="utf-8") as fh:
+            ref = json.load(fh)
+    except (OSError, ValueError):
+        pytest.skip("no readable stored oracle run")
     if not ref.get("complete"):
         pytest.skip("the stored oracle run is incomplete")
     g = I.workload_weighted_sbm(N)
