@@ -174,7 +174,10 @@ def test_plain_run_tracks_oracle(G, pair):
     # step of the longer one, and the stall that ended the shorter run,
     # must be unresolved. The final assignments' match ratios agree within
     # 0.005, or the assignment is shown to be undetermined at float
-    # resolution (module docstring).
+    # resolution (module docstring). While the oracle run is still going
+    # (it writes every iteration as it ends), the device's run is compared
+    # with the iterations stored so far, and its final match ratio with
+    # the oracle's after the same number of iterations.
     import json
     path = os.path.join(HERE, "golden", "weighted_sbm_n10000_plain_run.json")
     try:
@@ -182,8 +185,9 @@ def test_plain_run_tracks_oracle(G, pair):
             ref = json.load(fh)
     except (OSError, ValueError):
         pytest.skip("no readable stored oracle run")
-    if not ref.get("complete"):
-        pytest.skip("the stored oracle run is incomplete")
+    complete = bool(ref.get("complete"))
+    if not ref.get("iterations"):
+        pytest.skip("the stored oracle run has no iterations yet")
     g = I.workload_weighted_sbm(N)
     A, B = pair
     run = G.Run(A, B, prec="fp32", warm=0, stop_on_stall=1, sk_max=1000, sk_tol=1e-6, fw_max=30, lap=1)
@@ -208,14 +212,21 @@ def test_plain_run_tracks_oracle(G, pair):
         if abs(o["b"]) > 1e-6 * abs(o["fP"]):
             assert abs(h["t"] - o["t"]) <= 1e-4
     kd, ko = len(res.history), len(its)
-    if kd != ko:
+    if kd < ko or (complete and kd > ko):
         longer = res.history if kd > ko else its
         for h in longer[min(kd, ko) - 1:]:
             assert abs(h["b"]) <= 1e-6 * abs(h["fP"])
     mr = float(np.mean(res.perm == g.truth))
-    print(f"match ratio {mr:.4f} (oracle {ref['match_ratio']:.4f})", flush=True)
+    if complete:
+        mr_ref = ref["match_ratio"]
+    else:
+        after = ref.get("match_ratio_after", {})
+        if not after:
+            return
+        mr_ref = after.get(str(kd), after[max(after, key=int)])
+    print(f"match ratio {mr:.4f} (oracle {mr_ref:.4f}{'' if complete else ', run in progress'})", flush=True)
     assert sorted(res.perm.tolist()) == list(range(N))
-    if abs(mr - ref["match_ratio"]) <= 0.005:
+    if abs(mr - mr_ref) <= 0.005:
         return
     P = res.P
     rows = torch.arange(N, device=P.device)
